@@ -1,0 +1,268 @@
+"""Seeded synthetic inputs shared by the FP64 CPU oracle and the GPU path.
+
+The paper's own samples (an Eagle Ford pore-size distribution and images of
+reconstructed shale, Sec. 3.2-3.3) are not available, so every workload is a
+synthetic stand-in: a three-phase map (pore / inorganic matter / organic
+matter) grown by seeded QSGS, a per-node radius class drawn from a lognormal
+pore-size distribution per matter phase, and the gas / adsorption parameters
+of each instance.
+
+This module holds no lattice Boltzmann or permeability arithmetic: it only
+produces maps, radius bins and parameter sets.  Radii are tabulated per class
+(127 equal-probability lognormal bins per matter phase) so both sides consume
+identical classes.
+
+Class codes of the uint8 map (x fastest, then y, then z):
+    0            open pore (porosity 1, no drag)
+    1 .. 127     inorganic-matter radius bins
+    128 .. 254   organic-matter radius bins
+    255          solid wall node (no fluid; halfway bounce-back)
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import math
+import os
+import subprocess
+from typing import Optional, Sequence, Tuple
+
+import numpy as np
+
+PORE, IOM, OM = 0, 1, 2
+N_BINS = 127
+CLS_PORE = 0
+CLS_IOM0 = 1
+CLS_OM0 = 128
+CLS_WALL = 255
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIBDIR = os.path.join(_HERE, "lib")
+_LIB = os.path.join(_LIBDIR, "libqsgs.so")
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile the QSGS helper with gcc (plain C, no GPU)."""
+    os.makedirs(_LIBDIR, exist_ok=True)
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-std=c99", "-fPIC", "-shared",
+                               os.path.join(_HERE, "qsgs.c"), "-o", tmp, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build(force=False)
+        lib = ctypes.CDLL(_LIB)
+        lib.qsgs_grow.restype = ctypes.c_int64
+        lib.qsgs_grow.argtypes = [ctypes.c_int32] * 4 + [
+            ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double, ctypes.c_uint64,
+            ctypes.c_uint64, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p]
+        _lib = lib
+    return _lib
+
+
+def _neighbourhood(ndim: int, p_axial: float, p_diag: float, p_corner: float):
+    offs, probs = [], []
+    rng = (-1, 0, 1)
+    if ndim == 2:
+        for dy in rng:
+            for dx in rng:
+                k = abs(dx) + abs(dy)
+                if k == 0:
+                    continue
+                offs.append((dx, dy, 0))
+                probs.append(p_axial if k == 1 else p_diag)
+    else:
+        for dz in rng:
+            for dy in rng:
+                for dx in rng:
+                    k = abs(dx) + abs(dy) + abs(dz)
+                    if k == 0:
+                        continue
+                    offs.append((dx, dy, dz))
+                    probs.append({1: p_axial, 2: p_diag, 3: p_corner}[k])
+    return (np.ascontiguousarray(np.array(offs, dtype=np.int32).reshape(-1)),
+            np.ascontiguousarray(np.array(probs, dtype=np.float64)))
+
+
+def qsgs_grow(shape: Tuple[int, ...], allowed: np.ndarray, target: int, seed: int, stream: int,
+              p_seed: float = 0.01, p_axial: float = 0.001, p_diag: float = 0.00025,
+              p_corner: float = 0.0000625) -> np.ndarray:
+    """Grow exactly `target` nodes inside `allowed` (uint8 mask of `shape`, z,y,x order)."""
+    lib = _load()
+    nz, ny, nx = (1,) + tuple(shape) if len(shape) == 2 else tuple(shape)
+    off, prob = _neighbourhood(len(shape), p_axial, p_diag, p_corner)
+    allowed = np.ascontiguousarray(allowed.astype(np.uint8).reshape(-1))
+    out = np.zeros(allowed.size, dtype=np.uint8)
+    got = lib.qsgs_grow(nx, ny, nz, len(prob), off.ctypes.data, prob.ctypes.data, p_seed,
+                        ctypes.c_uint64(seed & (2**64 - 1)), ctypes.c_uint64(stream),
+                        allowed.ctypes.data, int(target), out.ctypes.data)
+    if got < 0:
+        raise MemoryError("qsgs_grow: allocation failed")
+    return out.reshape(shape)
+
+
+def phase_map(shape: Tuple[int, ...], solid_frac: float, toc: float, seed: int) -> np.ndarray:
+    """Three-phase map: 0 pore, 1 IOM, 2 OM.
+
+    Solid grows by QSGS to round(solid_frac * N) nodes; organic matter grows
+    by the same process restricted to the solid, to round(toc * N_solid).
+    """
+    n = int(np.prod(shape))
+    solid = qsgs_grow(shape, np.ones(shape, np.uint8), int(round(solid_frac * n)), seed, 1)
+    n_solid = int(solid.sum())
+    om = qsgs_grow(shape, solid, int(round(toc * n_solid)), seed, 2)
+    ph = solid.astype(np.uint8)
+    ph[om.astype(bool)] = OM
+    return ph
+
+
+def class_map(phase: np.ndarray, seed: int) -> np.ndarray:
+    """Per-node radius class: each matter node draws one of 127 bins uniformly."""
+    rng = np.random.Generator(np.random.PCG64(seed * 1000003 + 7))
+    k = rng.integers(0, N_BINS, size=phase.shape, dtype=np.int64)
+    cls = np.zeros(phase.shape, dtype=np.uint8)
+    cls[phase == IOM] = (CLS_IOM0 + k[phase == IOM]).astype(np.uint8)
+    cls[phase == OM] = (CLS_OM0 + k[phase == OM]).astype(np.uint8)
+    return cls
+
+
+def radius_bins(median: float, sigma: float, nbins: int = N_BINS) -> np.ndarray:
+    """Radii of `nbins` equal-probability bins of a lognormal distribution.
+
+    Bin k holds the quantile at probability (k + 1/2) / nbins:
+    r_k = median * exp(sigma * Phi^-1((k + 1/2) / nbins)).
+    """
+    from scipy.special import ndtri
+    p = (np.arange(nbins, dtype=np.float64) + 0.5) / nbins
+    return median * np.exp(sigma * ndtri(p))
+
+
+@dataclasses.dataclass
+class Instance:
+    """One GLBM problem: geometry recipe plus the physical inputs of its classes."""
+    shape: Tuple[int, ...]            # (ny, nx) or (nz, ny, nx)
+    seed: int
+    solid_frac: float = 0.60
+    toc: float = 0.15
+    pressure: float = 5.0e6           # Pa
+    temperature: float = 400.0        # K
+    eps_iom: float = 0.1
+    eps_om: float = 0.3
+    r_iom_median: float = 20e-9       # m
+    r_om_median: float = 5e-9         # m
+    sigma_ln_r: float = 0.5
+    langmuir_pl: float = 4.0e6        # Pa, b = 1 / P_L
+    q_sat: Optional[float] = 4000.0   # mol/m^3; None -> from langmuir_vl
+    langmuir_vl: Optional[float] = None  # m^3/kg
+    d_s: float = 1e-8                 # m^2/s
+    viscosity: float = 18.231e-6      # Pa s
+    tortuosity: float = 2.0
+    dx: float = 62.5e-9               # m per lattice spacing
+    tau: float = 1.0
+    g: float = 1e-6                   # body force, lattice units
+    drive_axis: int = 0               # 0 = x, 1 = y, 2 = z
+    wall_faces: int = 0               # bit per face: x-, x+, y-, y+, z-, z+
+
+    def classes(self) -> np.ndarray:
+        return class_map(phase_map(self.shape, self.solid_frac, self.toc, self.seed), self.seed)
+
+    def radii(self) -> Tuple[np.ndarray, np.ndarray]:
+        return (radius_bins(self.r_iom_median, self.sigma_ln_r),
+                radius_bins(self.r_om_median, self.sigma_ln_r))
+
+    def gvec(self) -> Tuple[float, float, float]:
+        g = [0.0, 0.0, 0.0]
+        g[self.drive_axis] = self.g
+        return tuple(g)
+
+
+def cfg0() -> Instance:
+    """128^2 D2Q9 case: 60% solid, TOC 0.15, methane at 400 K and 5 MPa."""
+    return Instance(shape=(128, 128), seed=0)
+
+
+def cfg1(side: int = 4096) -> Instance:
+    """4096^2 D2Q9 case: TOC 0.10 at 10 MPa, otherwise as the 128^2 case."""
+    return Instance(shape=(side, side), seed=1, toc=0.10, pressure=10.0e6)
+
+
+def cfg1_crops(inst: Instance, cls: np.ndarray, size: int = 512):
+    """Four periodic crops of the large map at (0,0), (0,W/2), (W/2,0), (W/2,W/2)."""
+    h = cls.shape[0] // 2
+    out = []
+    for (y0, x0) in ((0, 0), (0, h), (h, 0), (h, h)):
+        out.append(np.ascontiguousarray(cls[y0:y0 + size, x0:x0 + size]))
+    return out
+
+
+BATCH_SIDES = (256, 384, 512, 768, 1024)
+
+
+def cfg2_instance(k: int, side: Optional[int] = None) -> Instance:
+    """Instance k of the uneven batch: seed 2000+k, parameters drawn per instance."""
+    seed = 2000 + k
+    rng = np.random.Generator(np.random.PCG64(seed))
+    s = int(rng.choice(BATCH_SIDES))
+    toc = float(rng.uniform(0.05, 0.30))
+    p = float(math.exp(rng.uniform(math.log(1.0e6), math.log(30.0e6))))
+    pl = float(rng.uniform(2.0e6, 8.0e6))
+    vl = float(rng.uniform(0.002, 0.008))
+    if side is not None:
+        s = side
+    return Instance(shape=(s, s), seed=seed, toc=toc, pressure=p, langmuir_pl=pl,
+                    q_sat=None, langmuir_vl=vl)
+
+
+def cfg3(side: int = 256) -> Instance:
+    """256^3 D3Q19 case: 55% solid, TOC 0.20, 20 MPa, drive along z, walls on x/y faces."""
+    return Instance(shape=(side, side, side), seed=3, solid_frac=0.55, toc=0.20,
+                    pressure=20.0e6, drive_axis=2, wall_faces=0b001111)
+
+
+def cfg4_instance(seed: int, side: int = 512) -> Instance:
+    """A warm-start problem: cfg2's parameter distributions at a fixed side."""
+    inst = cfg2_instance(0)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    rng.choice(BATCH_SIDES)
+    inst.seed = seed
+    inst.shape = (side, side)
+    inst.toc = float(rng.uniform(0.05, 0.30))
+    inst.pressure = float(math.exp(rng.uniform(math.log(1.0e6), math.log(30.0e6))))
+    inst.langmuir_pl = float(rng.uniform(2.0e6, 8.0e6))
+    inst.langmuir_vl = float(rng.uniform(0.002, 0.008))
+    return inst
+
+
+def uniform_classes(shape: Sequence[int], cls: int = 1) -> np.ndarray:
+    return np.full(tuple(shape), cls, dtype=np.uint8)
+
+
+def random_classes(shape: Sequence[int], seed: int, n_classes: int = 8,
+                   wall_frac: float = 0.0) -> np.ndarray:
+    """Unstructured random class map for small parity cases (classes 0..n_classes-1, walls 255)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    cls = rng.integers(0, n_classes, size=tuple(shape), dtype=np.int64).astype(np.uint8)
+    if wall_frac > 0:
+        cls[rng.random(tuple(shape)) < wall_frac] = CLS_WALL
+    return cls
+
+
+def random_table(n_classes: int, seed: int, k_range=(1e-3, 1e-1), eps_range=(0.1, 1.0),
+                 open_pore: bool = True, f_eps: float = 0.0):
+    """Random per-class (eps, K_lattice, F_eps) for parity cases; class 0 is open pore."""
+    rng = np.random.Generator(np.random.PCG64(seed + 99991))
+    eps = rng.uniform(*eps_range, size=n_classes)
+    k = np.exp(rng.uniform(math.log(k_range[0]), math.log(k_range[1]), size=n_classes))
+    fe = np.full(n_classes, f_eps)
+    if open_pore:
+        eps[0] = 1.0
+        k[0] = math.inf
+        fe[0] = 0.0
+    return eps, k, fe
