@@ -1,0 +1,165 @@
+"""Throughput of the GLBM hot path on one MI355X.
+
+One bench "step" is one check interval of the hot path on the whole lattice:
+n_c = 100 stream-and-collide sweeps (Eq. 29-37 with per-node eps and K_app)
+followed by the FP64 residual and Darcy-flux reductions of that state, all in
+the HIP library.  The workload is a 4096 x 4096 D2Q9 shale map (seeded QSGS,
+60% solid, TOC 0.10, methane at 400 K and 10 MPa) with FP32 populations.
+
+Reported (one JSON line):
+  value        lattice updates per second over the timed steps (MLUPS)
+  roofline     the sweep kernel's algorithmic HBM bytes per launch
+               (2 x 9 x 4 B populations + 1 B class per node) over its mean
+               launch time, measured with HIP events on the library's stream
+               around every sweep launch of the timed region
+  cpu_baseline the CPU oracle (FP64 C, OpenMP) on a 512 x 512 crop of the
+               same map, rank 0 only
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "GLBM MLUPS + % HBM peak; time-to-converged k_app, plain vs warm-start"
+PEAK_HBM_GBS = 8000.0
+N_C = 100
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("glbm_kernels.hip", "glbm_internal.h"):
+        with open(os.path.join(ROOT, "paper_1601_00704_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profile(store: str, side: int):
+    """HBM bytes per sweep launch from a committed rocprofv3 counter summary, if it
+    was taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", "sweep_d2q9_%s_%d_traffic.json" % (store, side))
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    if rec.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(cls_crop, table, steps):
+    import oracle
+    eps, k, fe = table
+    prob = oracle.Problem(q=9, cls=cls_crop, eps=eps, k=k, f_eps=fe, tau=1.0, G=(1e-6, 0, 0))
+    f = prob.rest()
+    prob.run(f, 2)
+    t0 = time.perf_counter()
+    prob.run(f, steps)
+    dt = time.perf_counter() - t0
+    return cls_crop.size * steps / dt / 1e6, dt, oracle.num_threads()
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--side", type=int, default=4096)
+    ap.add_argument("--store", default="f32", choices=("f32", "f16dev", "f64"))
+    ap.add_argument("--cpu-steps", type=int, default=1000)
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: the GLBM hot path here is built and timed on a single "
+              "MI355X (multi-GPU sharding is a design note, not part of this build).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import shale_inputs as si
+    import paper_1601_00704_amd.glbm as g
+
+    torch.cuda.set_device(0)
+    inst = si.cfg1(args.side)
+    t0 = time.perf_counter()
+    cls = inst.classes()
+    t_geom = time.perf_counter() - t0
+    r_iom, r_om = inst.radii()
+    eps, kl = g.glbm_class_table(g.gas_params(inst), r_iom, r_om)
+    store = g.STORE_NAMES[args.store]
+    d = g.make_desc(cls.shape, store=store, tau=inst.tau, g=inst.gvec(), check_every=N_C)
+    s = g.Solver([d], [cls])
+    s.set_local_perm(eps[:255], kl[:255])
+    s.set_option(g.GLBM_OPT_GRAPH, 0)
+    s.set_option(g.GLBM_OPT_TIMING, 1)
+    N = cls.size
+    print("setup: %dx%d map in %.1fs, store %s" % (args.side, args.side, t_geom, args.store),
+          file=sys.stderr, flush=True)
+
+    for w in range(args.warmup):
+        s.step(N_C)
+    torch.cuda.synchronize()
+    s.set_option(g.GLBM_OPT_TIMING, 1)  # reset the sweep timer
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        s.step(N_C)
+        print("step %d/%d done" % (k + 1, args.steps), file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    sweep_ms, launches = g.glbm_sweep_time(s.ctx)
+    r, st = s.residual()
+    kk = s.permeability()[0]
+    s.close()
+
+    lups = N * N_C * args.steps
+    mlups = lups / wall / 1e6
+    bytes_per_lu = 2 * 9 * g.STORE_BYTES[store] + 1
+    per_launch = sweep_ms / max(launches, 1)
+    achieved = bytes_per_lu * N / (per_launch * 1e-3) / 1e9
+    traffic = traffic_from_profile(args.store, args.side)
+    out = {
+        "metric": METRIC,
+        "value": round(mlups, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(wall / args.steps * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"f32": "f32", "f16dev": "f32 math / f16 storage", "f64": "f64"}[args.store],
+        "data": "synthetic (seeded QSGS shale map, generated in-process)",
+        "config": {"workload": "D2Q9 GLBM %dx%d, QSGS 60%% solid, TOC 0.10, CH4 400 K 10 MPa, %s "
+                               "populations, n_c=%d sweeps + FP64 residual/flux per step"
+                               % (args.side, args.side, args.store.upper(), N_C),
+                   "nodes": N, "sweeps_per_step": N_C, "steps_total": int(st[0]),
+                   "residual": float(r[0]), "k_lattice": float(kk[0])},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": round(achieved / PEAK_HBM_GBS, 4),
+                     "traffic": traffic,
+                     "kernel": "k_sweep<9,%s>" % args.store, "bytes_per_lu": bytes_per_lu,
+                     "mean_launch_ms": round(per_launch, 5), "launches": launches},
+    }
+    if not args.no_cpu:
+        y0, x0 = 0, 0
+        crop = np.ascontiguousarray(cls[y0:y0 + 512, x0:x0 + 512])
+        import oracle
+        from oracle import kapp
+        e_o, k_o, f_o = kapp.class_table(inst)
+        v, dt, cores = cpu_baseline(crop, (e_o, k_o, f_o), args.cpu_steps)
+        out["cpu_baseline"] = {"value": round(v, 2), "unit": "MLUPS", "cores": cores, "kind": "oracle",
+                               "sample": "%d steps of a 512x512 crop of the same map (FP64 oracle, %.1f s)"
+                                         % (args.cpu_steps, dt)}
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,249 @@
+/*
+ * glbm.h — C ABI of the MI355X generalized lattice Boltzmann (GLBM) library.
+ *
+ * The library solves the generalized lattice Boltzmann equation of
+ * Wang, Chen, Kang & Rahman, "Permeability prediction of organic shale with
+ * generalized lattice Boltzmann model considering surface diffusion effect"
+ * (arXiv:1601.00704), Sec. 2.3, Eq. (27)-(37): a Brinkman-type stream-and-
+ * collide sweep over a voxelised shale map in which every node carries its own
+ * porosity eps and apparent permeability K_app (Sec. 2.1, Eq. 18-19).  The
+ * sweep is iterated to steady state and the sample's apparent permeability is
+ * read off Darcy's law from the volume-averaged velocity (Eq. 26, Sec. 3.2).
+ *
+ * Conventions for every entry point
+ *   - Return value: GLBM_OK (0) or a negative GLBM_E* code; glbm_last_error()
+ *     then returns a thread-local message describing the failure.
+ *   - Units: everything crossing this ABI is in lattice units (dx = dt = 1,
+ *     c_s^2 = 1/3) except glbm_class_table, which converts SI inputs.
+ *   - Layout: node index n = (z * ny + y) * nx + x (x fastest).  Velocity
+ *     fields are three planes ux[N], uy[N], uz[N].
+ *   - Ownership: host arrays passed in are copied before the call returns;
+ *     host arrays passed out are written by the call and owned by the caller.
+ *     A device population buffer passed to glbm_init_geometry stays owned by
+ *     the caller and must outlive the context; all other device memory is
+ *     allocated and freed by the library.
+ *   - Streams: all device work of a context is issued on the HIP stream given
+ *     to glbm_init_geometry (NULL = the null stream).  Calls that return
+ *     values to the host synchronise that stream.
+ *   - A context is not thread-safe; distinct contexts are independent.
+ */
+#ifndef GLBM_H
+#define GLBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Velocity sets (Eq. 29-31 leave the stencil open; the standard ones are used). */
+enum { GLBM_D2Q9 = 9, GLBM_D3Q19 = 19 };
+
+/* Population storage.  Arithmetic is FP64 for F64 and FP32 otherwise; the
+ * residual and flux reductions are always accumulated in FP64.
+ *   F64     f_i - w_i stored as double
+ *   F32     f_i - w_i stored as float
+ *   F16DEV  (f_i - w_i) * 2^s stored as IEEE half, rounded to nearest even */
+enum { GLBM_STORE_F64 = 0, GLBM_STORE_F32 = 1, GLBM_STORE_F16DEV = 2 };
+
+enum {
+    GLBM_OK = 0,
+    GLBM_EINVAL = -1,        /* invalid argument (shape, tau <= 1/2, eps outside (0,1], K <= 0, ...) */
+    GLBM_ENOMEM = -2,        /* device or host allocation failed, or caller buffer too small */
+    GLBM_EDEVICE = -3,       /* a HIP runtime call failed */
+    GLBM_ESTATE = -4,        /* call out of order (e.g. stepping before glbm_set_local_perm) */
+    GLBM_ENONFINITE = -5,    /* a NaN or Inf population was seen by a check */
+    GLBM_ENOTCONVERGED = -6  /* glbm_step_n reached its step budget with tol > 0 unmet */
+};
+
+#define GLBM_WALL_CLASS 255           /* class code of a solid wall node (no fluid) */
+#define GLBM_SCALE_AUTO (-2147483647 - 1) /* let the library pick the FP16 scale */
+
+typedef struct glbm_ctx_s* glbm_ctx;
+
+/* One problem instance.  lattice, store and check_every must be equal for
+ * every instance of a context. */
+typedef struct {
+    int32_t lattice;         /* GLBM_D2Q9 or GLBM_D3Q19 */
+    int32_t store;           /* GLBM_STORE_* */
+    int32_t nx, ny, nz;      /* grid; nz = 1 for GLBM_D2Q9 */
+    uint32_t wall_faces;     /* bit 0 x-, 1 x+, 2 y-, 3 y+, 4 z-, 5 z+: halfway bounce-back
+                                at that domain face; faces without a bit are periodic.
+                                Both faces of an axis must be set or clear together. */
+    double tau;              /* BGK relaxation time of Eq. (29), > 1/2; nu = (tau - 1/2)/3 */
+    double g[3];             /* external body force G of Eq. (27), lattice units */
+    int32_t dev_scale_log2;  /* s of the F16DEV scale 2^s in [0, 30], or GLBM_SCALE_AUTO */
+    int32_t check_every;     /* n_c > 0, even: residual and flux are evaluated every n_c steps */
+} glbm_instance_desc;
+
+/*
+ * Bytes of device memory that the populations of these instances need (both
+ * ping-pong buffers, with the library's plane padding).  Returns 0 if the
+ * descriptors are invalid.
+ */
+size_t glbm_required_bytes(int32_t n_inst, const glbm_instance_desc* desc);
+
+/*
+ * Create a context for n_inst instances and upload their class maps.
+ *   out         receives the context
+ *   desc        n_inst descriptors
+ *   cls_host    n_inst host pointers to uint8 class maps of nx*ny*nz nodes
+ *               (x fastest); class 255 is a wall node, every other class
+ *               must be given a table entry by glbm_set_local_perm
+ *   pop_dev     device buffer of at least glbm_required_bytes() bytes owned
+ *               by the caller, or NULL to let the library allocate it
+ *   pop_bytes   size of pop_dev (ignored when pop_dev is NULL)
+ *   hip_stream  hipStream_t for all work of the context (NULL: null stream)
+ * The populations start at rest, f_i = w_i (rho = 1, u = 0) — the paper
+ * leaves the initial state open.
+ * Errors: GLBM_EINVAL (n_inst < 1, empty grid, tau <= 1/2, mixed lattice /
+ * store / check_every, nz != 1 for D2Q9, odd check_every, scale outside
+ * [0, 30], a wall face without its opposite face); GLBM_ENOMEM; GLBM_EDEVICE.
+ */
+int glbm_init_geometry(glbm_ctx* out, int32_t n_inst, const glbm_instance_desc* desc,
+                       const uint8_t* const* cls_host, void* pop_dev, size_t pop_bytes,
+                       void* hip_stream);
+
+/*
+ * Set the per-class porosity eps, local permeability K (Eq. 27-28, K -> K_app)
+ * and Forchheimer coefficient F_eps (Eq. 27) of instance inst (-1: every
+ * instance).  Arrays hold n_classes entries for classes 0 .. n_classes-1
+ * (n_classes <= 255).  k_lattice is K_app / dx^2; +INF marks an open pore (no
+ * drag).  f_eps may be NULL (F_eps = 0: the paper drops the Forchheimer
+ * term, Sec. 2.3).  The per-node constants of Eq. (36)-(37) are derived here.
+ * Every class present in the map must be covered.
+ * Errors: GLBM_EINVAL (eps outside (0, 1], K <= 0 or NaN, F_eps < 0, a class
+ * of the map without an entry).
+ */
+int glbm_set_local_perm(glbm_ctx ctx, int32_t inst, int32_t n_classes, const double* eps,
+                        const double* k_lattice, const double* f_eps);
+
+/*
+ * Advance every active instance by up to n time steps of Eq. (29).  At every
+ * step count that is a multiple of check_every the library evaluates, per
+ * instance, the residual r = ||u(t) - u(t - n_c)||_2 / (n_c ||u(t)||_2) over
+ * fluid nodes (FP64 sums) and the Darcy flux.  tol <= 0: exactly n steps.
+ * tol > 0: an instance stops at the first check with r <= tol; the call
+ * returns when all instances have stopped (GLBM_OK) or after n steps
+ * (GLBM_ENOTCONVERGED).  GLBM_ENONFINITE if a check saw NaN/Inf.
+ * GLBM_ESTATE before glbm_set_local_perm.
+ */
+int glbm_step_n(glbm_ctx ctx, int64_t n, double tol);
+
+/*
+ * Per instance: r at the most recent check (+INF before the first) and the
+ * number of steps taken.  Either pointer may be NULL.  Synchronises.
+ */
+int glbm_residual(glbm_ctx ctx, double* r, int64_t* steps);
+
+/*
+ * Apparent permeability of each instance by Darcy's law on the current state:
+ * k[3*i + d] = nu <u_d> / G_d, <.> the mean over fluid nodes of the
+ * volume-averaged velocity of Eq. (34); NaN where G_d = 0.  Lattice units
+ * (multiply by dx^2 for m^2).  Synchronises.
+ */
+int glbm_permeability(glbm_ctx ctx, double* k_lattice);
+
+/*
+ * Replace the state of instance inst by the equilibrium of Eq. (30) at the
+ * given density (N doubles) and velocity (3N doubles): a warm start.  The
+ * residual snapshot is reset; step counts are kept.
+ */
+int glbm_set_fields(glbm_ctx ctx, int32_t inst, const double* rho, const double* u);
+
+/* Same as glbm_set_fields from device arrays of floats (rho[N], u[3N]). */
+int glbm_set_fields_device(glbm_ctx ctx, int32_t inst, const float* rho_dev, const float* u_dev);
+
+/*
+ * Density (N doubles) and velocity (3N doubles, Eq. 34) of the current state
+ * of instance inst; wall nodes get zeros.  Either pointer may be NULL.
+ */
+int glbm_get_fields(glbm_ctx ctx, int32_t inst, double* rho, double* u);
+
+/*
+ * Post-streaming populations f_i(x, t) of instance inst as q planes of N
+ * doubles (f_i, not deviations); wall-node slots are zero.  For tests and
+ * inspection.
+ */
+int glbm_get_populations(glbm_ctx ctx, int32_t inst, double* f_host);
+
+/*
+ * Bitwise checkpoint of a whole context: glbm_state_bytes() bytes of host
+ * memory hold the populations, residual snapshots and step counters.
+ * glbm_load_state restores a checkpoint taken from a context created with
+ * identical descriptors and tables.
+ */
+size_t glbm_state_bytes(glbm_ctx ctx);
+int glbm_save_state(glbm_ctx ctx, void* host, size_t bytes);
+int glbm_load_state(glbm_ctx ctx, const void* host, size_t bytes);
+
+/*
+ * Options.  GLBM_OPT_GRAPH (default 1): replay full n_c-step chunks from a
+ * captured HIP graph.  GLBM_OPT_TIMING (default 0): bracket every sweep launch
+ * with HIP events on the context stream; glbm_sweep_time reports the summed
+ * time and launch count since the option was last set.  GLBM_OPT_TILE_ROWS:
+ * rows of nodes each workgroup walks (1, 2, 4, 8, 16; default picked by size).
+ */
+enum { GLBM_OPT_GRAPH = 1, GLBM_OPT_TIMING = 2, GLBM_OPT_TILE_ROWS = 3 };
+int glbm_set_option(glbm_ctx ctx, int32_t option, int64_t value);
+int glbm_sweep_time(glbm_ctx ctx, double* ms_total, int64_t* launches);
+
+/*
+ * Pick GLBM_OPT_TILE_ROWS for this context by timing each candidate for
+ * `steps` sweeps (the state advances by those steps, an even total).  The
+ * chosen value is returned in *chosen (may be NULL).
+ */
+int glbm_autotune(glbm_ctx ctx, int32_t steps, int32_t* chosen);
+
+/*
+ * Velocity set of a lattice in the library's direction order: e receives q*3
+ * ints (e_x, e_y, e_z per direction), w the q weights; either may be NULL.
+ * This is the plane order of glbm_get_populations.
+ * D2Q9:  rest, +x, +y, -x, -y, (+x,+y), (-x,+y), (-x,-y), (+x,-y).
+ * D3Q19: rest, +x, -x, +y, -y, +z, -z, then the 12 edges as opposite pairs.
+ */
+int glbm_velocity_set(int32_t lattice, int32_t* e, double* w);
+
+/* Release every resource of the context (the caller's population buffer is not freed). */
+int glbm_destroy(glbm_ctx ctx);
+
+/* Message of the last failure on this thread ("" if none). */
+const char* glbm_last_error(void);
+
+/*
+ * Physical inputs of the class table (SI units).
+ */
+typedef struct {
+    double pressure;       /* P, Pa */
+    double temperature;    /* T, K */
+    double viscosity;      /* eta, Pa s */
+    double molar_mass;     /* M, kg/mol */
+    double tortuosity;     /* tau_t of Eq. (4) */
+    double dx;             /* lattice spacing, m */
+    double eps_iom;        /* porosity of inorganic matter */
+    double eps_om;         /* porosity of organic matter */
+    double langmuir_b;     /* b of Eq. (13), 1/Pa */
+    double q_sat;          /* mol/m^3; <= 0: from langmuir_vl and toc by Eq. (38) */
+    double langmuir_vl;    /* Langmuir volume, m^3 of methane at 273.15 K, 101.325 kPa per kg of rock */
+    double toc;            /* organic volume fraction used by Eq. (38) */
+    double d_s;            /* Maxwell-Stefan surface diffusivity, m^2/s */
+} glbm_gas_params;
+
+/*
+ * Class table of a three-phase shale map: class 0 open pore (eps 1, K +INF);
+ * classes 1 .. n_iom inorganic matter of radii r_iom (Eq. 18); classes
+ * 128 .. 127 + n_om organic matter of radii r_om (Eq. 19).  Radii in m; the
+ * pore diameter of Eq. (3)-(4) is twice the radius.  The gas density is the
+ * ideal-gas P M / (R T).  eps_out and k_lattice_out receive 256 entries each
+ * (unused classes: eps 1, K +INF); K is returned as K_app / dx^2.
+ * Errors: GLBM_EINVAL (n_iom or n_om outside [0, 127], non-positive inputs).
+ */
+int glbm_class_table(const glbm_gas_params* p, int32_t n_iom, const double* r_iom, int32_t n_om,
+                     const double* r_om, double* eps_out, double* k_lattice_out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GLBM_H */

@@ -1,0 +1,1010 @@
+// Host side of libglbm: contexts, the C ABI of include/glbm.h, chunked stepping
+// with HIP graph replay, checks and timing.
+#include "glbm.h"
+#include "glbm_internal.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <limits>
+#include <string>
+#include <vector>
+
+using namespace glbm;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define HIPCHK(expr)                                                                              \
+    do {                                                                                          \
+        hipError_t e_ = (expr);                                                                   \
+        if (e_ != hipSuccess)                                                                     \
+            return fail(GLBM_EDEVICE, "%s failed: %s (%s:%d)", #expr, hipGetErrorString(e_), __FILE__, \
+                        __LINE__);                                                                \
+    } while (0)
+
+size_t store_bytes(int store) { return store == GLBM_STORE_F64 ? 8 : (store == GLBM_STORE_F32 ? 4 : 2); }
+size_t compute_bytes(int store) { return store == GLBM_STORE_F64 ? 8 : 4; }
+int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
+
+// Plane stride: a multiple of 128 elements plus 128, so that the q planes of a
+// power-of-two grid do not all start at the same offset modulo large powers
+// of two (HBM channel interleave).
+int64_t plane_stride(int64_t n) { return round_up(n, 128) + 128; }
+
+int validate(int32_t n_inst, const glbm_instance_desc* d)
+{
+    if (n_inst < 1 || !d) return fail(GLBM_EINVAL, "n_inst must be >= 1");
+    for (int i = 0; i < n_inst; ++i) {
+        const glbm_instance_desc& x = d[i];
+        if (x.lattice != GLBM_D2Q9 && x.lattice != GLBM_D3Q19)
+            return fail(GLBM_EINVAL, "instance %d: lattice must be 9 or 19", i);
+        if (x.store < 0 || x.store > 2) return fail(GLBM_EINVAL, "instance %d: bad store %d", i, x.store);
+        if (x.nx < 1 || x.ny < 1 || x.nz < 1) return fail(GLBM_EINVAL, "instance %d: empty grid", i);
+        if (x.lattice == GLBM_D2Q9 && x.nz != 1) return fail(GLBM_EINVAL, "instance %d: D2Q9 needs nz = 1", i);
+        if ((int64_t)x.nx * x.ny * x.nz * x.lattice >= (int64_t)1 << 30)
+            return fail(GLBM_EINVAL, "instance %d: grid too large for 32-bit plane indexing", i);
+        if (!(x.tau > 0.5) || !std::isfinite(x.tau)) return fail(GLBM_EINVAL, "instance %d: tau must be > 1/2", i);
+        for (int a = 0; a < 3; ++a)
+            if (!std::isfinite(x.g[a])) return fail(GLBM_EINVAL, "instance %d: non-finite body force", i);
+        if (x.check_every < 2 || (x.check_every & 1))
+            return fail(GLBM_EINVAL, "instance %d: check_every must be even and >= 2", i);
+        if (x.wall_faces & ~0x3Fu) return fail(GLBM_EINVAL, "instance %d: unknown wall face bits", i);
+        for (int a = 0; a < 3; ++a)
+            if (((x.wall_faces >> (2 * a)) & 1u) != ((x.wall_faces >> (2 * a + 1)) & 1u))
+                return fail(GLBM_EINVAL, "instance %d: wall faces must come in pairs per axis", i);
+        if (x.store == GLBM_STORE_F16DEV && x.dev_scale_log2 != GLBM_SCALE_AUTO &&
+            (x.dev_scale_log2 < 0 || x.dev_scale_log2 > 30))
+            return fail(GLBM_EINVAL, "instance %d: dev_scale_log2 must be in [0, 30]", i);
+        if (x.lattice != d[0].lattice || x.store != d[0].store || x.check_every != d[0].check_every)
+            return fail(GLBM_EINVAL, "instance %d: lattice, store and check_every must match instance 0", i);
+    }
+    return GLBM_OK;
+}
+
+// Element layout of one population buffer.
+struct Layout {
+    std::vector<int64_t> off, stride;
+    int64_t elems = 0;
+};
+
+Layout layout_of(int32_t n_inst, const glbm_instance_desc* d)
+{
+    Layout L;
+    for (int i = 0; i < n_inst; ++i) {
+        const int64_t n = (int64_t)d[i].nx * d[i].ny * d[i].nz;
+        const int64_t s = plane_stride(n);
+        L.off.push_back(L.elems);
+        L.stride.push_back(s);
+        L.elems += round_up(s * d[i].lattice, 256);
+    }
+    return L;
+}
+
+int auto_scale(const glbm_instance_desc& d)
+{
+    // Deviations |f_i - w_i| of a slow body-force-driven flow stay far below
+    // 2^-5; 2^20 keeps everything above 2^-34 in the normal FP16 range.
+    (void)d;
+    return 20;
+}
+
+}  // namespace
+
+struct glbm_ctx_s {
+    int n_inst = 0;
+    Config cfg{};
+    int n_c = 100;
+    size_t esz = 0, tsz = 0;
+    hipStream_t user = nullptr, work = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    std::vector<glbm_instance_desc> desc;
+    std::vector<InstDev> inst_h;
+    std::vector<Tile> tiles_h;
+    std::vector<int64_t> n_fluid, steps, snap_step;
+    std::vector<int32_t> active_h, dsteps_h, has_table;
+    std::vector<std::vector<uint8_t>> cls_h;
+    int64_t gstep = 0;
+    bool snap_valid = false;
+    // device memory
+    void* buf[2] = {nullptr, nullptr};
+    bool own_pop = false;
+    void* pop_base = nullptr;
+    size_t pop_bytes = 0;
+    uint8_t* cls_d = nullptr;
+    InstDev* inst_d = nullptr;
+    Tile* tiles_d = nullptr;
+    void* tab_d = nullptr;
+    void* snap_d = nullptr;
+    double* part_d = nullptr;
+    double* res_d = nullptr;
+    double* flux_d = nullptr;
+    int32_t* active_d = nullptr;
+    int32_t* dsteps_d = nullptr;
+    int64_t snap_elems = 0;
+    // pinned host mirrors
+    double* res_p = nullptr;
+    int32_t* active_p = nullptr;
+    // tiling and graph
+    int rows = 4;
+    int ntiles = 0;
+    bool use_graph = true;
+    hipGraphExec_t graph = nullptr;
+    double graph_tol = 0.0;
+    bool graph_valid = false;
+    // timing
+    bool timing = false;
+    std::vector<hipEvent_t> ev_pool;
+    size_t ev_used = 0;
+    double time_ms = 0.0;
+    int64_t launches = 0;
+
+    Args args(int parity) const
+    {
+        Args a{};
+        a.tiles = tiles_d;
+        a.inst = inst_d;
+        a.cls = cls_d;
+        a.buf[0] = buf[0];
+        a.buf[1] = buf[1];
+        a.tab = tab_d;
+        a.snap = snap_d;
+        a.part = part_d;
+        a.res = res_d;
+        a.active = active_d;
+        a.dsteps = dsteps_d;
+        a.ntiles = ntiles;
+        a.parity = parity & 1;
+        a.rows = rows;
+        return a;
+    }
+};
+
+namespace {
+
+void free_graph(glbm_ctx c)
+{
+    if (c->graph) (void)hipGraphExecDestroy(c->graph);
+    c->graph = nullptr;
+    c->graph_valid = false;
+}
+
+int build_tiles(glbm_ctx c)
+{
+    c->tiles_h.clear();
+    const int th = kBlockRows * c->rows;
+    for (int i = 0; i < c->n_inst; ++i) {
+        InstDev& I = c->inst_h[i];
+        I.tile0 = (int32_t)c->tiles_h.size();
+        for (int z = 0; z < I.nz; ++z)
+            for (int y = 0; y < I.ny; y += th)
+                for (int x = 0; x < I.nx; x += kTileX) c->tiles_h.push_back(Tile{i, x, y, z});
+        I.ntiles = (int32_t)c->tiles_h.size() - I.tile0;
+    }
+    c->ntiles = (int)c->tiles_h.size();
+    if (c->tiles_d) (void)hipFree(c->tiles_d);
+    if (c->part_d) (void)hipFree(c->part_d);
+    c->tiles_d = nullptr;
+    c->part_d = nullptr;
+    HIPCHK(hipMalloc(&c->tiles_d, c->tiles_h.size() * sizeof(Tile)));
+    HIPCHK(hipMalloc(&c->part_d, c->tiles_h.size() * kPartW * sizeof(double)));
+    HIPCHK(hipMemcpyAsync(c->tiles_d, c->tiles_h.data(), c->tiles_h.size() * sizeof(Tile), hipMemcpyHostToDevice,
+                          c->work));
+    HIPCHK(hipMemcpyAsync(c->inst_d, c->inst_h.data(), c->inst_h.size() * sizeof(InstDev), hipMemcpyHostToDevice,
+                          c->work));
+    HIPCHK(hipStreamSynchronize(c->work));
+    free_graph(c);
+    return GLBM_OK;
+}
+
+int default_rows(glbm_ctx c)
+{
+    int64_t total = 0;
+    int min_ny = 1 << 30;
+    for (auto& I : c->inst_h) {
+        total += (int64_t)I.nx * I.ny * I.nz;
+        min_ny = std::min(min_ny, I.ny);
+    }
+    int r = 4;
+    while (r > 1 && kBlockRows * r > min_ny) r >>= 1;
+    // small problems: keep enough workgroups to cover the 256 compute units
+    while (r > 1 && total / (kBlock * r) < 2048) r >>= 1;
+    return r;
+}
+
+// Fork the work stream from the caller's stream.
+int enter(glbm_ctx c)
+{
+    HIPCHK(hipEventRecord(c->ev_fork, c->user));
+    HIPCHK(hipStreamWaitEvent(c->work, c->ev_fork, 0));
+    return GLBM_OK;
+}
+
+// Join: make the caller's stream wait for the work queued so far.
+int leave(glbm_ctx c)
+{
+    HIPCHK(hipEventRecord(c->ev_join, c->work));
+    HIPCHK(hipStreamWaitEvent(c->user, c->ev_join, 0));
+    return GLBM_OK;
+}
+
+int resolve_timing(glbm_ctx c)
+{
+    if (!c->ev_used) return GLBM_OK;
+    HIPCHK(hipEventSynchronize(c->ev_pool[c->ev_used - 1]));
+    for (size_t k = 0; k + 1 < c->ev_used; k += 2) {
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, c->ev_pool[k], c->ev_pool[k + 1]));
+        c->time_ms += ms;
+        c->launches += 1;
+    }
+    c->ev_used = 0;
+    return GLBM_OK;
+}
+
+int sweep_once(glbm_ctx c, int parity)
+{
+    if (c->timing) {
+        if (c->ev_used + 2 > c->ev_pool.size()) {
+            int rc = resolve_timing(c);
+            if (rc) return rc;
+            while (c->ev_pool.size() < 512) {
+                hipEvent_t e;
+                HIPCHK(hipEventCreate(&e));
+                c->ev_pool.push_back(e);
+            }
+        }
+        HIPCHK(hipEventRecord(c->ev_pool[c->ev_used++], c->work));
+    }
+    HIPCHK(launch_sweep(c->cfg, c->args(parity), c->work));
+    if (c->timing) HIPCHK(hipEventRecord(c->ev_pool[c->ev_used++], c->work));
+    return GLBM_OK;
+}
+
+int upload_state(glbm_ctx c)
+{
+    HIPCHK(hipMemcpyAsync(c->inst_d, c->inst_h.data(), c->inst_h.size() * sizeof(InstDev), hipMemcpyHostToDevice,
+                          c->work));
+    HIPCHK(hipMemcpyAsync(c->active_d, c->active_h.data(), c->active_h.size() * sizeof(int32_t),
+                          hipMemcpyHostToDevice, c->work));
+    HIPCHK(hipMemcpyAsync(c->dsteps_d, c->dsteps_h.data(), c->dsteps_h.size() * sizeof(int32_t),
+                          hipMemcpyHostToDevice, c->work));
+    // the host vectors may change before the copies run
+    HIPCHK(hipStreamSynchronize(c->work));
+    return GLBM_OK;
+}
+
+// Observe the current state of every instance (snapshot u) without a residual.
+int take_snapshot(glbm_ctx c)
+{
+    HIPCHK(launch_observe(c->cfg, c->args(c->gstep), 1 | 4, c->work));
+    for (int i = 0; i < c->n_inst; ++i) c->snap_step[i] = c->steps[i];
+    c->snap_valid = true;
+    return GLBM_OK;
+}
+
+int capture_chunk(glbm_ctx c, double tol)
+{
+    free_graph(c);
+    hipGraph_t g = nullptr;
+    HIPCHK(hipStreamBeginCapture(c->work, hipStreamCaptureModeRelaxed));
+    hipError_t err = hipSuccess;
+    for (int k = 0; k < c->n_c && err == hipSuccess; ++k) err = launch_sweep(c->cfg, c->args(k), c->work);
+    if (err == hipSuccess) err = launch_observe(c->cfg, c->args(0), 3, c->work);
+    if (err == hipSuccess) err = launch_finalize(c->args(0), c->n_inst, tol, 1, 1, c->work);
+    hipError_t e2 = hipStreamEndCapture(c->work, &g);
+    if (err != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return fail(GLBM_EDEVICE, "graph capture: %s", hipGetErrorString(err));
+    }
+    HIPCHK(e2);
+    err = hipGraphInstantiate(&c->graph, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (err != hipSuccess) {
+        c->graph = nullptr;
+        return fail(GLBM_EDEVICE, "graph instantiate: %s", hipGetErrorString(err));
+    }
+    c->graph_tol = tol;
+    c->graph_valid = true;
+    return GLBM_OK;
+}
+
+int check_tables(glbm_ctx c)
+{
+    for (int i = 0; i < c->n_inst; ++i)
+        if (!c->has_table[i]) return fail(GLBM_ESTATE, "instance %d: glbm_set_local_perm not called", i);
+    return GLBM_OK;
+}
+
+void set_parities(glbm_ctx c)
+{
+    for (int i = 0; i < c->n_inst; ++i) c->inst_h[i].par = (int32_t)((c->steps[i] - c->gstep) & 1);
+}
+
+int read_results(glbm_ctx c)
+{
+    HIPCHK(hipMemcpyAsync(c->res_p, c->res_d, (size_t)c->n_inst * kPartW * sizeof(double), hipMemcpyDeviceToHost,
+                          c->work));
+    HIPCHK(hipMemcpyAsync(c->active_p, c->active_d, (size_t)c->n_inst * sizeof(int32_t), hipMemcpyDeviceToHost,
+                          c->work));
+    HIPCHK(hipStreamSynchronize(c->work));
+    return GLBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* glbm_last_error(void) { return g_err.c_str(); }
+
+size_t glbm_required_bytes(int32_t n_inst, const glbm_instance_desc* desc)
+{
+    if (validate(n_inst, desc) != GLBM_OK) return 0;
+    Layout L = layout_of(n_inst, desc);
+    const size_t one = (size_t)round_up(L.elems * (int64_t)store_bytes(desc[0].store), 256);
+    return 2 * one;
+}
+
+int glbm_init_geometry(glbm_ctx* out, int32_t n_inst, const glbm_instance_desc* desc, const uint8_t* const* cls_host,
+                       void* pop_dev, size_t pop_bytes, void* hip_stream)
+{
+    g_err.clear();
+    if (!out) return fail(GLBM_EINVAL, "out is NULL");
+    *out = nullptr;
+    int rc = validate(n_inst, desc);
+    if (rc) return rc;
+    if (!cls_host) return fail(GLBM_EINVAL, "cls_host is NULL");
+    for (int i = 0; i < n_inst; ++i)
+        if (!cls_host[i]) return fail(GLBM_EINVAL, "cls_host[%d] is NULL", i);
+    const size_t need = glbm_required_bytes(n_inst, desc);
+    if (pop_dev && pop_bytes < need)
+        return fail(GLBM_ENOMEM, "population buffer too small: %zu < %zu bytes", pop_bytes, need);
+
+    glbm_ctx c = new (std::nothrow) glbm_ctx_s();
+    if (!c) return fail(GLBM_ENOMEM, "host allocation failed");
+    c->n_inst = n_inst;
+    c->desc.assign(desc, desc + n_inst);
+    c->cfg.q = desc[0].lattice;
+    c->cfg.store = desc[0].store;
+    c->cfg.forch = false;
+    c->n_c = desc[0].check_every;
+    c->esz = store_bytes(desc[0].store);
+    c->tsz = compute_bytes(desc[0].store);
+    c->user = static_cast<hipStream_t>(hip_stream);
+
+    auto bail = [&](int code) {
+        glbm_destroy(c);
+        return code;
+    };
+#define TRY(expr)                        \
+    do {                                 \
+        int r_ = (expr);                 \
+        if (r_) return bail(r_);         \
+    } while (0)
+#define TRYHIP(expr)                                                                               \
+    do {                                                                                           \
+        hipError_t e_ = (expr);                                                                    \
+        if (e_ != hipSuccess) return bail(fail(e_ == hipErrorOutOfMemory ? GLBM_ENOMEM : GLBM_EDEVICE, \
+                                               "%s failed: %s", #expr, hipGetErrorString(e_)));    \
+    } while (0)
+
+    TRYHIP(hipStreamCreateWithFlags(&c->work, hipStreamDefault));
+    TRYHIP(hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
+    TRYHIP(hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming));
+
+    Layout L = layout_of(n_inst, desc);
+    int64_t cls_total = 0, snap_total = 0;
+    bool any_wall_node = false, any_wall_face = false;
+    c->cls_h.resize(n_inst);
+    for (int i = 0; i < n_inst; ++i) {
+        const glbm_instance_desc& d = desc[i];
+        const int64_t n = (int64_t)d.nx * d.ny * d.nz;
+        InstDev I{};
+        I.pop_off = L.off[i];
+        I.cls_off = cls_total;
+        I.snap_off = snap_total;
+        I.stride = (int32_t)L.stride[i];
+        I.nx = d.nx;
+        I.ny = d.ny;
+        I.nz = d.nz;
+        I.walls = d.wall_faces;
+        I.par = 0;
+        for (int a = 0; a < 3; ++a) I.g[a] = d.g[a];
+        I.omega = 1.0 / d.tau;
+        I.cforce = 1.0 - 0.5 / d.tau;
+        I.nu = (d.tau - 0.5) / 3.0;
+        const int s = d.store == GLBM_STORE_F16DEV ? (d.dev_scale_log2 == GLBM_SCALE_AUTO ? auto_scale(d)
+                                                                                         : d.dev_scale_log2)
+                                                   : 0;
+        I.scale = std::ldexp(1.0f, s);
+        I.inv_scale = std::ldexp(1.0f, -s);
+        c->inst_h.push_back(I);
+        c->cls_h[i].assign(cls_host[i], cls_host[i] + n);
+        int64_t nf = 0;
+        for (int64_t k = 0; k < n; ++k) {
+            if (cls_host[i][k] == kWallClass) any_wall_node = true;
+            else ++nf;
+        }
+        if (nf == 0) return bail(fail(GLBM_EINVAL, "instance %d has no fluid node", i));
+        c->n_fluid.push_back(nf);
+        if (d.wall_faces) any_wall_face = true;
+        cls_total += round_up(n, 256);
+        snap_total += round_up(3 * n, 64);
+    }
+    c->cfg.bc = any_wall_node ? 2 : (any_wall_face ? 1 : 0);
+    c->steps.assign(n_inst, 0);
+    c->snap_step.assign(n_inst, 0);
+    c->active_h.assign(n_inst, 1);
+    c->dsteps_h.assign(n_inst, c->n_c);
+    c->has_table.assign(n_inst, 0);
+    c->snap_elems = snap_total;
+
+    // population buffers
+    const size_t half = need / 2;
+    if (pop_dev) {
+        c->pop_base = pop_dev;
+        c->own_pop = false;
+    } else {
+        TRYHIP(hipMalloc(&c->pop_base, need));
+        c->own_pop = true;
+    }
+    c->pop_bytes = need;
+    c->buf[0] = c->pop_base;
+    c->buf[1] = static_cast<char*>(c->pop_base) + half;
+
+    TRYHIP(hipMalloc(&c->cls_d, (size_t)cls_total));
+    TRYHIP(hipMalloc(&c->inst_d, n_inst * sizeof(InstDev)));
+    TRYHIP(hipMalloc(&c->tab_d, (size_t)n_inst * kClasses * kTabW * c->tsz));
+    TRYHIP(hipMalloc(&c->snap_d, (size_t)snap_total * c->tsz));
+    TRYHIP(hipMalloc(&c->res_d, (size_t)n_inst * kPartW * sizeof(double)));
+    TRYHIP(hipMalloc(&c->flux_d, (size_t)n_inst * kPartW * sizeof(double)));
+    TRYHIP(hipMalloc(&c->active_d, n_inst * sizeof(int32_t)));
+    TRYHIP(hipMalloc(&c->dsteps_d, n_inst * sizeof(int32_t)));
+    TRYHIP(hipHostMalloc(reinterpret_cast<void**>(&c->res_p), (size_t)n_inst * kPartW * sizeof(double),
+                         hipHostMallocDefault));
+    TRYHIP(hipHostMalloc(reinterpret_cast<void**>(&c->active_p), n_inst * sizeof(int32_t), hipHostMallocDefault));
+
+    TRY(enter(c));
+    for (int i = 0; i < n_inst; ++i)
+        TRYHIP(hipMemcpyAsync(c->cls_d + c->inst_h[i].cls_off, c->cls_h[i].data(), c->cls_h[i].size(),
+                              hipMemcpyHostToDevice, c->work));
+    // rest state: all deviations zero (f_i = w_i, rho = 1, u = 0)
+    TRYHIP(launch_zero(c->pop_base, need, c->work));
+    TRYHIP(launch_zero(c->snap_d, (size_t)snap_total * c->tsz, c->work));
+    TRYHIP(launch_zero(c->res_d, (size_t)n_inst * kPartW * sizeof(double), c->work));
+    TRYHIP(launch_zero(c->tab_d, (size_t)n_inst * kClasses * kTabW * c->tsz, c->work));
+    for (int i = 0; i < n_inst; ++i) c->res_p[i * kPartW + P_R] = INFINITY;
+    c->rows = default_rows(c);
+    TRY(build_tiles(c));
+    TRY(upload_state(c));
+    TRY(leave(c));
+    *out = c;
+    return GLBM_OK;
+#undef TRY
+#undef TRYHIP
+}
+
+int glbm_set_local_perm(glbm_ctx c, int32_t inst, int32_t n_classes, const double* eps, const double* k_lattice,
+                        const double* f_eps)
+{
+    g_err.clear();
+    if (!c) return fail(GLBM_EINVAL, "null context");
+    if (inst < -1 || inst >= c->n_inst) return fail(GLBM_EINVAL, "instance %d out of range", inst);
+    if (n_classes < 1 || n_classes > 255) return fail(GLBM_EINVAL, "n_classes must be in [1, 255]");
+    if (!eps || !k_lattice) return fail(GLBM_EINVAL, "eps and k_lattice are required");
+    for (int k = 0; k < n_classes; ++k) {
+        if (!(eps[k] > 0.0 && eps[k] <= 1.0)) return fail(GLBM_EINVAL, "class %d: eps %g outside (0, 1]", k, eps[k]);
+        if (!(k_lattice[k] > 0.0)) return fail(GLBM_EINVAL, "class %d: K %g must be > 0", k, k_lattice[k]);
+        if (f_eps && !(f_eps[k] >= 0.0 && std::isfinite(f_eps[k])))
+            return fail(GLBM_EINVAL, "class %d: F_eps %g must be finite and >= 0", k, f_eps[k]);
+    }
+    const int i0 = inst < 0 ? 0 : inst, i1 = inst < 0 ? c->n_inst : inst + 1;
+    for (int i = i0; i < i1; ++i)
+        for (uint8_t v : c->cls_h[i])
+            if (v != kWallClass && v >= n_classes)
+                return fail(GLBM_EINVAL, "instance %d: class %d of the map has no table entry", i, (int)v);
+    bool forch = false;
+    for (int k = 0; k < n_classes && f_eps; ++k)
+        if (f_eps[k] > 0.0 && std::isfinite(k_lattice[k])) forch = true;
+
+    int rc = enter(c);
+    if (rc) return rc;
+    std::vector<double> row((size_t)kClasses * kTabW, 0.0);
+    for (int i = i0; i < i1; ++i) {
+        const double nu = c->inst_h[i].nu;
+        std::fill(row.begin(), row.end(), 0.0);
+        for (int k = 0; k < kClasses; ++k) {
+            const bool have = k < n_classes;
+            const double e = have ? eps[k] : 1.0;
+            const double kinv = (have && std::isfinite(k_lattice[k])) ? 1.0 / k_lattice[k] : 0.0;
+            const double fe = (have && f_eps) ? f_eps[k] : 0.0;
+            const double c0 = 0.5 * (1.0 + e * 0.5 * nu * kinv);   // Eq. (36)
+            const double c1 = e * 0.5 * fe * std::sqrt(kinv);      // Eq. (37)
+            double* r = &row[(size_t)k * kTabW];
+            r[TAB_EPS] = e;
+            r[TAB_INV_EPS] = 1.0 / e;
+            r[TAB_INV_2C0] = 1.0 / (2.0 * c0);
+            r[TAB_DRAG] = e * nu * kinv;
+            r[TAB_C0] = c0;
+            r[TAB_C1] = c1;
+            r[TAB_FORCH] = e * fe * std::sqrt(kinv);
+        }
+        char* dst = static_cast<char*>(c->tab_d) + (size_t)i * kClasses * kTabW * c->tsz;
+        if (c->tsz == 8) {
+            HIPCHK(hipMemcpyAsync(dst, row.data(), row.size() * 8, hipMemcpyHostToDevice, c->work));
+        } else {
+            std::vector<float> rf(row.begin(), row.end());
+            HIPCHK(hipMemcpyAsync(dst, rf.data(), rf.size() * 4, hipMemcpyHostToDevice, c->work));
+        }
+        HIPCHK(hipStreamSynchronize(c->work));
+        c->has_table[i] = 1;
+    }
+    if (forch && !c->cfg.forch) {
+        c->cfg.forch = true;
+        free_graph(c);
+    }
+    c->snap_valid = false;
+    free_graph(c);
+    return leave(c);
+}
+
+int glbm_step_n(glbm_ctx c, int64_t n, double tol)
+{
+    g_err.clear();
+    if (!c) return fail(GLBM_EINVAL, "null context");
+    if (n < 0) return fail(GLBM_EINVAL, "n must be >= 0");
+    int rc = check_tables(c);
+    if (rc) return rc;
+    rc = enter(c);
+    if (rc) return rc;
+
+    // (re)activate: everything when tol <= 0, else every instance not already below tol
+    for (int i = 0; i < c->n_inst; ++i) {
+        const double r = c->res_p[i * kPartW + P_R];
+        c->active_h[i] = (tol > 0.0 && c->snap_valid && r <= tol && c->snap_step[i] == c->steps[i]) ? 0 : 1;
+    }
+    set_parities(c);
+    rc = upload_state(c);
+    if (rc) return rc;
+    if (!c->snap_valid) {
+        rc = take_snapshot(c);
+        if (rc) return rc;
+    }
+    bool nonfinite = false;
+    int64_t left = n;
+    auto any_active = [&]() {
+        for (int i = 0; i < c->n_inst; ++i)
+            if (c->active_h[i]) return true;
+        return false;
+    };
+    while (left > 0 && any_active()) {
+        const int64_t phase = c->gstep % c->n_c;
+        const int64_t len = std::min<int64_t>(c->n_c - phase, left);
+        const bool check = phase + len == c->n_c;
+        if (check) {
+            // steps since each active instance's snapshot, after this chunk
+            bool changed = false;
+            for (int i = 0; i < c->n_inst; ++i) {
+                if (!c->active_h[i]) continue;
+                const int32_t ds = (int32_t)(c->steps[i] + len - c->snap_step[i]);
+                if (ds != c->dsteps_h[i]) changed = true;
+                c->dsteps_h[i] = ds;
+            }
+            if (changed) {
+                rc = upload_state(c);
+                if (rc) return rc;
+            }
+        }
+        if (check && len == c->n_c && c->use_graph && !c->timing && (c->gstep & 1) == 0) {
+            if (!c->graph_valid || c->graph_tol != tol) {
+                rc = capture_chunk(c, tol);
+                if (rc) return rc;
+            }
+            HIPCHK(hipGraphLaunch(c->graph, c->work));
+        } else {
+            for (int64_t k = 0; k < len; ++k) {
+                rc = sweep_once(c, (int)((c->gstep + k) & 1));
+                if (rc) return rc;
+            }
+            if (check) {
+                HIPCHK(launch_observe(c->cfg, c->args(c->gstep + len), 3, c->work));
+                HIPCHK(launch_finalize(c->args(c->gstep + len), c->n_inst, tol, 1, 1, c->work));
+            }
+        }
+        c->gstep += len;
+        left -= len;
+        for (int i = 0; i < c->n_inst; ++i)
+            if (c->active_h[i]) c->steps[i] += len;
+        if (check) {
+            rc = read_results(c);
+            if (rc) return rc;
+            for (int i = 0; i < c->n_inst; ++i) {
+                if (!c->active_h[i]) continue;
+                c->snap_step[i] = c->steps[i];
+                if (!std::isfinite(c->res_p[i * kPartW + P_R]) && c->res_p[i * kPartW + P_BAD] > 0) nonfinite = true;
+                c->active_h[i] = c->active_p[i];
+            }
+            if (nonfinite) break;
+        }
+    }
+    if (c->timing) {
+        rc = resolve_timing(c);
+        if (rc) return rc;
+    }
+    // host view of the active flags may differ from the device after the loop; keep them equal
+    set_parities(c);
+    rc = upload_state(c);
+    if (rc) return rc;
+    rc = leave(c);
+    if (rc) return rc;
+    if (nonfinite) return fail(GLBM_ENONFINITE, "non-finite populations detected");
+    if (tol > 0.0 && any_active()) return fail(GLBM_ENOTCONVERGED, "step budget reached before r <= %g", tol);
+    return GLBM_OK;
+}
+
+int glbm_residual(glbm_ctx c, double* r, int64_t* steps)
+{
+    g_err.clear();
+    if (!c) return fail(GLBM_EINVAL, "null context");
+    HIPCHK(hipStreamSynchronize(c->work));
+    for (int i = 0; i < c->n_inst; ++i) {
+        if (r) r[i] = c->res_p[i * kPartW + P_R];
+        if (steps) steps[i] = c->steps[i];
+    }
+    return GLBM_OK;
+}
+
+int glbm_permeability(glbm_ctx c, double* k)
+{
+    g_err.clear();
+    if (!c) return fail(GLBM_EINVAL, "null context");
+    if (!k) return fail(GLBM_EINVAL, "k is NULL");
+    int rc = check_tables(c);
+    if (rc) return rc;
+    rc = enter(c);
+    if (rc) return rc;
+    Args a = c->args(c->gstep);
+    a.res = c->flux_d;
+    HIPCHK(launch_observe(c->cfg, a, 4, c->work));
+    HIPCHK(launch_finalize(a, c->n_inst, 0.0, 0, 0, c->work));
+    std::vector<double> h((size_t)c->n_inst * kPartW);
+    HIPCHK(hipMemcpyAsync(h.data(), c->flux_d, h.size() * sizeof(double), hipMemcpyDeviceToHost, c->work));
+    HIPCHK(hipStreamSynchronize(c->work));
+    for (int i = 0; i < c->n_inst; ++i) {
+        const double nu = c->inst_h[i].nu;
+        for (int d = 0; d < 3; ++d) {
+            const double g = c->inst_h[i].g[d];
+            const double mean = h[i * kPartW + P_UX + d] / (double)c->n_fluid[i];
+            k[3 * i + d] = g != 0.0 ? nu * mean / g : NAN;
+        }
+    }
+    return leave(c);
+}
+
+static int set_fields_impl(glbm_ctx c, int32_t inst, const void* rho_d, const void* u_d, int is_double)
+{
+    HIPCHK(launch_set_fields(c->cfg, c->args(c->gstep), inst, c->inst_h[inst].ntiles, rho_d, u_d, is_double,
+                             c->work));
+    c->snap_valid = false;
+    for (int i = 0; i < c->n_inst; ++i) c->res_p[i * kPartW + P_R] = INFINITY;
+    HIPCHK(hipMemcpyAsync(c->res_d, c->res_p, (size_t)c->n_inst * kPartW * sizeof(double), hipMemcpyHostToDevice,
+                          c->work));
+    HIPCHK(hipStreamSynchronize(c->work));
+    return GLBM_OK;
+}
+
+int glbm_set_fields(glbm_ctx c, int32_t inst, const double* rho, const double* u)
+{
+    g_err.clear();
+    if (!c) return fail(GLBM_EINVAL, "null context");
+    if (inst < 0 || inst >= c->n_inst) return fail(GLBM_EINVAL, "instance %d out of range", inst);
+    if (!rho || !u) return fail(GLBM_EINVAL, "rho and u are required");
+    int rc = check_tables(c);
+    if (rc) return rc;
+    rc = enter(c);
+    if (rc) return rc;
+    const InstDev& I = c->inst_h[inst];
+    const size_t n = (size_t)I.nx * I.ny * I.nz;
+    double* d = nullptr;
+    HIPCHK(hipMalloc(&d, 4 * n * sizeof(double)));
+    hipError_t e = hipMemcpyAsync(d, rho, n * sizeof(double), hipMemcpyHostToDevice, c->work);
+    if (e == hipSuccess) e = hipMemcpyAsync(d + n, u, 3 * n * sizeof(double), hipMemcpyHostToDevice, c->work);
+    if (e != hipSuccess) {
+        (void)hipFree(d);
+        return fail(GLBM_EDEVICE, "upload: %s", hipGetErrorString(e));
+    }
+    rc = set_fields_impl(c, inst, d, d + n, 1);
+    hipError_t es = hipStreamSynchronize(c->work);
+    (void)hipFree(d);
+    if (rc) return rc;
+    HIPCHK(es);
+    return leave(c);
+}
+
+int glbm_set_fields_device(glbm_ctx c, int32_t inst, const float* rho_dev, const float* u_dev)
+{
+    g_err.clear();
+    if (!c) return fail(GLBM_EINVAL, "null context");
+    if (inst < 0 || inst >= c->n_inst) return fail(GLBM_EINVAL, "instance %d out of range", inst);
+    if (!rho_dev || !u_dev) return fail(GLBM_EINVAL, "rho and u are required");
+    int rc = check_tables(c);
+    if (rc) return rc;
+    rc = enter(c);
+    if (rc) return rc;
+    rc = set_fields_impl(c, inst, rho_dev, u_dev, 0);
+    if (rc) return rc;
+    return leave(c);
+}
+
+static int get_impl(glbm_ctx c, int32_t inst, double* rho, double* u, double* pops)
+{
+    if (!c) return fail(GLBM_EINVAL, "null context");
+    if (inst < 0 || inst >= c->n_inst) return fail(GLBM_EINVAL, "instance %d out of range", inst);
+    int rc = check_tables(c);
+    if (rc) return rc;
+    rc = enter(c);
+    if (rc) return rc;
+    const InstDev& I = c->inst_h[inst];
+    const size_t n = (size_t)I.nx * I.ny * I.nz;
+    const size_t q = (size_t)c->cfg.q;
+    double* d = nullptr;
+    HIPCHK(hipMalloc(&d, (4 + q) * n * sizeof(double)));
+    hipError_t e = launch_get_fields(c->cfg, c->args(c->gstep), inst, I.ntiles, d, d + n, pops ? d + 4 * n : nullptr,
+                                     c->work);
+    if (e == hipSuccess && rho) e = hipMemcpyAsync(rho, d, n * sizeof(double), hipMemcpyDeviceToHost, c->work);
+    if (e == hipSuccess && u) e = hipMemcpyAsync(u, d + n, 3 * n * sizeof(double), hipMemcpyDeviceToHost, c->work);
+    if (e == hipSuccess && pops)
+        e = hipMemcpyAsync(pops, d + 4 * n, q * n * sizeof(double), hipMemcpyDeviceToHost, c->work);
+    hipError_t es = hipStreamSynchronize(c->work);
+    (void)hipFree(d);
+    if (e != hipSuccess) return fail(GLBM_EDEVICE, "get fields: %s", hipGetErrorString(e));
+    HIPCHK(es);
+    return leave(c);
+}
+
+int glbm_get_fields(glbm_ctx c, int32_t inst, double* rho, double* u)
+{
+    g_err.clear();
+    return get_impl(c, inst, rho, u, nullptr);
+}
+
+int glbm_get_populations(glbm_ctx c, int32_t inst, double* f_host)
+{
+    g_err.clear();
+    if (!f_host) return fail(GLBM_EINVAL, "f_host is NULL");
+    return get_impl(c, inst, nullptr, nullptr, f_host);
+}
+
+// checkpoint layout: header | populations (both buffers) | snapshots | results | counters
+struct CkptHeader {
+    uint64_t magic, pop_bytes, snap_bytes, n_inst;
+    int64_t gstep;
+    int32_t snap_valid, pad;
+};
+static const uint64_t kMagic = 0x474c424d434b5031ULL;
+
+size_t glbm_state_bytes(glbm_ctx c)
+{
+    if (!c) return 0;
+    return sizeof(CkptHeader) + c->pop_bytes + (size_t)c->snap_elems * c->tsz +
+           (size_t)c->n_inst * (kPartW * sizeof(double) + 2 * sizeof(int64_t));
+}
+
+int glbm_save_state(glbm_ctx c, void* host, size_t bytes)
+{
+    g_err.clear();
+    if (!c || !host) return fail(GLBM_EINVAL, "null argument");
+    if (bytes < glbm_state_bytes(c)) return fail(GLBM_ENOMEM, "buffer too small");
+    int rc = enter(c);
+    if (rc) return rc;
+    char* p = static_cast<char*>(host);
+    CkptHeader h{kMagic, c->pop_bytes, (uint64_t)c->snap_elems * c->tsz, (uint64_t)c->n_inst, c->gstep,
+                 c->snap_valid ? 1 : 0, 0};
+    memcpy(p, &h, sizeof h);
+    p += sizeof h;
+    HIPCHK(hipMemcpyAsync(p, c->pop_base, c->pop_bytes, hipMemcpyDeviceToHost, c->work));
+    p += c->pop_bytes;
+    HIPCHK(hipMemcpyAsync(p, c->snap_d, h.snap_bytes, hipMemcpyDeviceToHost, c->work));
+    p += h.snap_bytes;
+    HIPCHK(hipStreamSynchronize(c->work));
+    memcpy(p, c->res_p, (size_t)c->n_inst * kPartW * sizeof(double));
+    p += (size_t)c->n_inst * kPartW * sizeof(double);
+    memcpy(p, c->steps.data(), c->n_inst * sizeof(int64_t));
+    p += c->n_inst * sizeof(int64_t);
+    memcpy(p, c->snap_step.data(), c->n_inst * sizeof(int64_t));
+    return leave(c);
+}
+
+int glbm_load_state(glbm_ctx c, const void* host, size_t bytes)
+{
+    g_err.clear();
+    if (!c || !host) return fail(GLBM_EINVAL, "null argument");
+    if (bytes < glbm_state_bytes(c)) return fail(GLBM_EINVAL, "checkpoint too small");
+    const char* p = static_cast<const char*>(host);
+    CkptHeader h;
+    memcpy(&h, p, sizeof h);
+    if (h.magic != kMagic || h.pop_bytes != c->pop_bytes || h.n_inst != (uint64_t)c->n_inst ||
+        h.snap_bytes != (uint64_t)c->snap_elems * c->tsz)
+        return fail(GLBM_EINVAL, "checkpoint does not match this context");
+    int rc = enter(c);
+    if (rc) return rc;
+    p += sizeof h;
+    HIPCHK(hipMemcpyAsync(c->pop_base, p, c->pop_bytes, hipMemcpyHostToDevice, c->work));
+    p += c->pop_bytes;
+    HIPCHK(hipMemcpyAsync(c->snap_d, p, h.snap_bytes, hipMemcpyHostToDevice, c->work));
+    p += h.snap_bytes;
+    HIPCHK(hipStreamSynchronize(c->work));
+    memcpy(c->res_p, p, (size_t)c->n_inst * kPartW * sizeof(double));
+    p += (size_t)c->n_inst * kPartW * sizeof(double);
+    memcpy(c->steps.data(), p, c->n_inst * sizeof(int64_t));
+    p += c->n_inst * sizeof(int64_t);
+    memcpy(c->snap_step.data(), p, c->n_inst * sizeof(int64_t));
+    c->gstep = h.gstep;
+    c->snap_valid = h.snap_valid != 0;
+    HIPCHK(hipMemcpyAsync(c->res_d, c->res_p, (size_t)c->n_inst * kPartW * sizeof(double), hipMemcpyHostToDevice,
+                          c->work));
+    set_parities(c);
+    rc = upload_state(c);
+    if (rc) return rc;
+    free_graph(c);
+    return leave(c);
+}
+
+int glbm_set_option(glbm_ctx c, int32_t option, int64_t value)
+{
+    g_err.clear();
+    if (!c) return fail(GLBM_EINVAL, "null context");
+    switch (option) {
+    case GLBM_OPT_GRAPH:
+        c->use_graph = value != 0;
+        return GLBM_OK;
+    case GLBM_OPT_TIMING: {
+        int rc = resolve_timing(c);
+        if (rc) return rc;
+        c->timing = value != 0;
+        c->time_ms = 0.0;
+        c->launches = 0;
+        return GLBM_OK;
+    }
+    case GLBM_OPT_TILE_ROWS: {
+        if (value != 1 && value != 2 && value != 4 && value != 8 && value != 16)
+            return fail(GLBM_EINVAL, "tile rows must be 1, 2, 4, 8 or 16");
+        if (c->rows == (int)value) return GLBM_OK;
+        HIPCHK(hipStreamSynchronize(c->work));
+        c->rows = (int)value;
+        return build_tiles(c);
+    }
+    default:
+        return fail(GLBM_EINVAL, "unknown option %d", option);
+    }
+}
+
+int glbm_sweep_time(glbm_ctx c, double* ms_total, int64_t* launches)
+{
+    g_err.clear();
+    if (!c) return fail(GLBM_EINVAL, "null context");
+    int rc = resolve_timing(c);
+    if (rc) return rc;
+    if (ms_total) *ms_total = c->time_ms;
+    if (launches) *launches = c->launches;
+    return GLBM_OK;
+}
+
+int glbm_autotune(glbm_ctx c, int32_t steps, int32_t* chosen)
+{
+    g_err.clear();
+    if (!c) return fail(GLBM_EINVAL, "null context");
+    if (steps < 2 || (steps & 1)) return fail(GLBM_EINVAL, "steps must be even and >= 2");
+    int rc = check_tables(c);
+    if (rc) return rc;
+    const bool old_timing = c->timing;
+    const int cand[] = {1, 2, 4, 8, 16};
+    double best = 1e300;
+    int best_r = c->rows;
+    for (int r : cand) {
+        int min_ny = 1 << 30;
+        for (auto& I : c->inst_h) min_ny = std::min(min_ny, I.ny);
+        if (r > 1 && kBlockRows * r > min_ny) continue;
+        rc = glbm_set_option(c, GLBM_OPT_TILE_ROWS, r);
+        if (rc) return rc;
+        rc = glbm_set_option(c, GLBM_OPT_TIMING, 1);
+        if (rc) return rc;
+        rc = enter(c);
+        if (rc) return rc;
+        for (int k = 0; k < steps && rc == GLBM_OK; ++k) rc = sweep_once(c, (int)((c->gstep + k) & 1));
+        if (rc) return rc;
+        double ms = 0.0;
+        int64_t nl = 0;
+        rc = glbm_sweep_time(c, &ms, &nl);
+        if (rc) return rc;
+        // the sweeps advanced every instance whose flag is set; keep the counters exact
+        for (int i = 0; i < c->n_inst; ++i)
+            if (c->active_h[i]) c->steps[i] += steps;
+        c->gstep += steps;
+        c->snap_valid = false;
+        rc = leave(c);
+        if (rc) return rc;
+        if (ms < best) {
+            best = ms;
+            best_r = r;
+        }
+    }
+    rc = glbm_set_option(c, GLBM_OPT_TIMING, old_timing ? 1 : 0);
+    if (rc) return rc;
+    rc = glbm_set_option(c, GLBM_OPT_TILE_ROWS, best_r);
+    if (rc) return rc;
+    if (chosen) *chosen = best_r;
+    return GLBM_OK;
+}
+
+int glbm_destroy(glbm_ctx c)
+{
+    if (!c) return GLBM_OK;
+    if (c->work) (void)hipStreamSynchronize(c->work);
+    free_graph(c);
+    for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
+    if (c->own_pop && c->pop_base) (void)hipFree(c->pop_base);
+    (void)hipFree(c->cls_d);
+    (void)hipFree(c->inst_d);
+    (void)hipFree(c->tiles_d);
+    (void)hipFree(c->tab_d);
+    (void)hipFree(c->snap_d);
+    (void)hipFree(c->part_d);
+    (void)hipFree(c->res_d);
+    (void)hipFree(c->flux_d);
+    (void)hipFree(c->active_d);
+    (void)hipFree(c->dsteps_d);
+    if (c->res_p) (void)hipHostFree(c->res_p);
+    if (c->active_p) (void)hipHostFree(c->active_p);
+    if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
+    if (c->ev_join) (void)hipEventDestroy(c->ev_join);
+    if (c->work) (void)hipStreamDestroy(c->work);
+    delete c;
+    return GLBM_OK;
+}
+
+int glbm_velocity_set(int32_t lattice, int32_t* e, double* w)
+{
+    g_err.clear();
+    if (lattice == GLBM_D2Q9) {
+        static const int v[9][2] = {{0, 0}, {1, 0}, {0, 1}, {-1, 0}, {0, -1}, {1, 1}, {-1, 1}, {-1, -1}, {1, -1}};
+        for (int i = 0; i < 9; ++i) {
+            if (e) {
+                e[3 * i] = v[i][0];
+                e[3 * i + 1] = v[i][1];
+                e[3 * i + 2] = 0;
+            }
+            if (w) w[i] = i == 0 ? 4.0 / 9.0 : (i < 5 ? 1.0 / 9.0 : 1.0 / 36.0);
+        }
+        return GLBM_OK;
+    }
+    if (lattice == GLBM_D3Q19) {
+        static const int v[19][3] = {{0, 0, 0},  {1, 0, 0},  {-1, 0, 0}, {0, 1, 0},  {0, -1, 0},
+                                     {0, 0, 1},  {0, 0, -1}, {1, 1, 0},  {-1, -1, 0}, {1, -1, 0},
+                                     {-1, 1, 0}, {1, 0, 1},  {-1, 0, -1}, {1, 0, -1}, {-1, 0, 1},
+                                     {0, 1, 1},  {0, -1, -1}, {0, 1, -1}, {0, -1, 1}};
+        for (int i = 0; i < 19; ++i) {
+            if (e)
+                for (int a = 0; a < 3; ++a) e[3 * i + a] = v[i][a];
+            if (w) w[i] = i == 0 ? 1.0 / 3.0 : (i < 7 ? 1.0 / 18.0 : 1.0 / 36.0);
+        }
+        return GLBM_OK;
+    }
+    return fail(GLBM_EINVAL, "lattice must be 9 or 19");
+}
+
+}  // extern "C"

@@ -1,0 +1,102 @@
+// Internal declarations shared by the HIP kernels and the host side of libglbm.
+// Not part of the public ABI (include/glbm.h is).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace glbm {
+
+constexpr int kTileX = 64;          // nodes along x per tile (one wavefront row)
+constexpr int kBlockRows = 4;       // rows of a 256-thread workgroup
+constexpr int kBlock = kTileX * kBlockRows;
+constexpr int kClasses = 256;
+constexpr int kWallClass = 255;
+constexpr int kTabW = 8;            // constants per class in the device table
+constexpr int kPartW = 8;           // doubles per tile partial / instance result
+
+// Per-class constants (index into a row of kTabW values).
+enum TabSlot {
+    TAB_EPS = 0,        // eps
+    TAB_INV_EPS = 1,    // 1 / eps
+    TAB_INV_2C0 = 2,    // 1 / (2 c0), Eq. (36)
+    TAB_DRAG = 3,       // eps nu / K
+    TAB_C0 = 4,         // c0, Eq. (36)
+    TAB_C1 = 5,         // c1, Eq. (37)
+    TAB_FORCH = 6,      // eps F_eps / sqrt(K)
+};
+
+// Per-tile / per-instance reduction record (doubles).
+enum PartSlot {
+    P_SD = 0,    // sum |u - u_snap|^2
+    P_SU = 1,    // sum |u|^2
+    P_UX = 2,    // sum u_x
+    P_UY = 3,
+    P_UZ = 4,
+    P_BAD = 5,   // count of non-finite nodes
+    P_R = 6,     // residual (instance record only)
+    P_NCHK = 7,  // checks done (instance record only)
+};
+
+// Device-side instance descriptor.
+struct InstDev {
+    int64_t pop_off;     // element offset of plane 0 of this instance in each buffer
+    int64_t cls_off;     // byte offset of the class map
+    int64_t snap_off;    // element offset of the u snapshot (3 planes of N)
+    int32_t stride;      // elements between planes
+    int32_t nx, ny, nz;
+    uint32_t walls;      // face bits
+    int32_t par;         // parity offset: state buffer = (g + par) & 1 at global step g
+    int32_t tile0, ntiles;  // range of this instance in the tile list
+    double g[3];
+    double omega;        // 1 / tau
+    double cforce;       // 1 - 1 / (2 tau)
+    double nu;
+    float scale, inv_scale;  // FP16 deviation scale 2^s and 2^-s
+};
+
+struct Tile {
+    int32_t inst, x0, y0, z0;
+};
+
+// Everything a kernel launch needs (passed by value).
+struct Args {
+    const Tile* tiles;
+    const InstDev* inst;
+    const uint8_t* cls;
+    void* buf[2];          // population buffers A, B
+    const void* tab;       // per instance kTabW * kClasses values of the compute type
+    void* snap;            // u snapshots (compute type)
+    double* part;          // per tile kPartW doubles
+    double* res;           // per instance kPartW doubles
+    int32_t* active;       // per instance flag
+    const int32_t* dsteps; // per instance steps since the snapshot
+    int32_t ntiles;
+    int32_t parity;        // g & 1
+    int32_t rows;          // rows per thread (tile height = 4 * rows)
+};
+
+// Kernel configuration of a context.
+struct Config {
+    int q;        // 9 or 19
+    int store;    // GLBM_STORE_*
+    int bc;       // 0 periodic only, 1 face walls, 2 face walls + wall nodes
+    bool forch;   // any F_eps > 0
+};
+
+// Host launchers (glbm_kernels.hip).
+hipError_t launch_sweep(const Config& c, const Args& a, hipStream_t s);
+// mode bit 0: update snapshot; bit 1: accumulate residual terms
+hipError_t launch_observe(const Config& c, const Args& a, int mode, hipStream_t s);
+// tol > 0: deactivate converged instances; with_r: compute r from S_d, S_u
+hipError_t launch_finalize(const Args& a, int n_inst, double tol, int with_r, int count_check,
+                           hipStream_t s);
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
+// Write the equilibrium of (rho, u) of instance `inst` (device arrays; T = double or float)
+hipError_t launch_set_fields(const Config& c, const Args& a, int inst, int ntiles, const void* rho,
+                             const void* u, int src_is_double, hipStream_t s);
+// Density, velocity (double, N and 3N) and optionally populations (double, q*N) of instance `inst`
+hipError_t launch_get_fields(const Config& c, const Args& a, int inst, int ntiles, double* rho, double* u,
+                             double* pops, hipStream_t s);
+
+}  // namespace glbm

@@ -1,0 +1,574 @@
+// HIP kernels of the GLBM sweep for gfx950 (MI355X).
+//
+// The state of an instance is q planes of population deviations d_i = f_i - w_i
+// (rho0 = 1) in one of three storage types, laid out as SoA planes
+// plane_i[node], node = (z * ny + y) * nx + x.  One time step of the
+// generalized lattice Boltzmann equation (Eq. 29 of arXiv:1601.00704) is one
+// launch of k_sweep: every thread pulls the q post-collision values that stream
+// into its node (periodic wrap, or halfway bounce-back at wall faces and wall
+// nodes), evaluates the moments (Eq. 32-35), the Brinkman-Forchheimer force
+// (Eq. 27-28), the porous equilibrium (Eq. 30) and the forcing term (Eq. 31,
+// with the 1/eps that keeps it mass-conserving), relaxes, and writes its own q
+// values to the other buffer.  The kernel is bound by HBM bandwidth: it reads
+// q values and one class byte and writes q values per node, with the per-class
+// constants (eps, 1/eps, c0, drag) in LDS, indexed by the class byte.
+//
+// k_observe evaluates the same moments on the current state and reduces, per
+// tile and in FP64, the residual terms |u - u_snap|^2 and |u|^2, the velocity
+// sum (Darcy flux) and a non-finite count; k_finalize sums the tiles of each
+// instance in a fixed order, so results are deterministic.
+#include "glbm_internal.h"
+#include "glbm.h"
+
+#include <hip/hip_fp16.h>
+
+namespace glbm {
+namespace {
+
+// ---------------------------------------------------------------- lattices --
+// D2Q9: rest, +x, +y, -x, -y, then the diagonals (+,+), (-,+), (-,-), (+,-).
+// D3Q19: rest, the 6 faces in +/- pairs (x, y, z), then the 12 edges in
+// opposite pairs.  Weights: D2Q9 4/9, 1/9, 1/36; D3Q19 1/3, 1/18, 1/36.
+template <int Q> struct Lat;
+template <> struct Lat<9> {
+    static constexpr int ex(int i) { constexpr int a[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1}; return a[i]; }
+    static constexpr int ey(int i) { constexpr int a[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1}; return a[i]; }
+    static constexpr int ez(int) { return 0; }
+    static constexpr int opp(int i) { constexpr int a[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6}; return a[i]; }
+    static constexpr double w(int i) { return i == 0 ? 4.0 / 9.0 : (i < 5 ? 1.0 / 9.0 : 1.0 / 36.0); }
+};
+template <> struct Lat<19> {
+    static constexpr int ex(int i) {
+        constexpr int a[19] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
+        return a[i];
+    }
+    static constexpr int ey(int i) {
+        constexpr int a[19] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
+        return a[i];
+    }
+    static constexpr int ez(int i) {
+        constexpr int a[19] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
+        return a[i];
+    }
+    static constexpr int opp(int i) { return i == 0 ? 0 : ((i & 1) ? i + 1 : i - 1); }
+    static constexpr double w(int i) { return i == 0 ? 1.0 / 3.0 : (i < 7 ? 1.0 / 18.0 : 1.0 / 36.0); }
+};
+
+// ----------------------------------------------------------------- storage --
+template <int STORE> struct St;
+template <> struct St<GLBM_STORE_F64> {
+    using S = double;
+    using T = double;
+    __device__ static T dec(S s, float) { return s; }
+    __device__ static S enc(T d, float) { return d; }
+};
+template <> struct St<GLBM_STORE_F32> {
+    using S = float;
+    using T = float;
+    __device__ static T dec(S s, float) { return s; }
+    __device__ static S enc(T d, float) { return d; }
+};
+template <> struct St<GLBM_STORE_F16DEV> {
+    using S = uint16_t;
+    using T = float;
+    __device__ static T dec(S s, float inv_scale) { return __half2float(__ushort_as_half(s)) * inv_scale; }
+    __device__ static S enc(T d, float scale) { return __half_as_ushort(__float2half_rn(d * scale)); }
+};
+
+// Workgroups are dispatched round-robin over the 8 XCDs.  Map them so that
+// each XCD walks a contiguous range of tiles: x-neighbouring tiles share the
+// cache lines their shifted reads straddle, and those then meet in one L2.
+__device__ __forceinline__ int xcd_tile(int bid, int G)
+{
+    const int q = G >> 3, r = G & 7, x = bid & 7, k = bid >> 3;
+    return x * q + min(x, r) + k;
+}
+
+template <typename T> __device__ __forceinline__ bool finite(T v) { return isfinite(v); }
+
+// Pull the q post-collision values that stream into node (x, y, z).
+template <int Q, int STORE, int BC>
+__device__ __forceinline__ void gather(typename St<STORE>::T (&d)[Q], const typename St<STORE>::S* __restrict__ src,
+                                       const uint8_t* __restrict__ cls, const InstDev& I, int x, int y, int z,
+                                       int n)
+{
+    using L = Lat<Q>;
+    using S = St<STORE>;
+    const int nx = I.nx, ny = I.ny, nz = I.nz, stride = I.stride;
+    const int xm = x == 0 ? nx - 1 : x - 1, xp = x == nx - 1 ? 0 : x + 1;
+    const int ym = y == 0 ? ny - 1 : y - 1, yp = y == ny - 1 ? 0 : y + 1;
+    const int zm = z == 0 ? nz - 1 : z - 1, zp = z == nz - 1 ? 0 : z + 1;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const int ex = L::ex(i), ey = L::ey(i), ez = L::ez(i);
+        const int sx = ex > 0 ? xm : (ex < 0 ? xp : x);
+        const int sy = ey > 0 ? ym : (ey < 0 ? yp : y);
+        const int sz = ez > 0 ? zm : (ez < 0 ? zp : z);
+        const int sn = (sz * ny + sy) * nx + sx;
+        int idx = i * stride + sn;
+        if (BC >= 1) {
+            const uint32_t w = I.walls;
+            bool blocked = false;
+            if (ex > 0) blocked |= (x == 0) && (w & 1u);
+            if (ex < 0) blocked |= (x == nx - 1) && (w & 2u);
+            if (ey > 0) blocked |= (y == 0) && (w & 4u);
+            if (ey < 0) blocked |= (y == ny - 1) && (w & 8u);
+            if (ez > 0) blocked |= (z == 0) && (w & 16u);
+            if (ez < 0) blocked |= (z == nz - 1) && (w & 32u);
+            if (BC >= 2 && i != 0) blocked |= cls[sn] == kWallClass;
+            if (blocked) idx = L::opp(i) * stride + n;
+        }
+        d[i] = S::dec(src[idx], I.inv_scale);
+    }
+}
+
+// Moments and force of one node: Eq. (32)-(35) and (27)-(28) on deviations.
+template <int Q, typename T, bool FORCH> struct Node {
+    T drho, rho, u[3], F[3];
+    __device__ __forceinline__ void moments(const T (&d)[Q], const T* tab, const T g[3])
+    {
+        using L = Lat<Q>;
+        T j[3] = {0, 0, 0};
+        drho = 0;
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            drho += d[i];
+            if (L::ex(i)) j[0] += L::ex(i) > 0 ? d[i] : -d[i];
+            if (L::ey(i)) j[1] += L::ey(i) > 0 ? d[i] : -d[i];
+            if (L::ez(i)) j[2] += L::ez(i) > 0 ? d[i] : -d[i];
+        }
+        rho = T(1) + drho;
+        const T irho = T(1) / rho;
+        const T eps = tab[TAB_EPS];
+        T v[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) v[a] = j[a] * irho + T(0.5) * eps * g[a];
+        if (FORCH) {
+            const T c0 = tab[TAB_C0], c1 = tab[TAB_C1];
+            const T vm = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+            const T den = T(1) / (c0 + sqrt(c0 * c0 + c1 * vm));
+#pragma unroll
+            for (int a = 0; a < 3; ++a) u[a] = v[a] * den;
+            const T um = sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+            const T drag = tab[TAB_DRAG] + tab[TAB_FORCH] * um;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) F[a] = eps * g[a] - drag * u[a];
+        } else {
+            const T h = tab[TAB_INV_2C0], drag = tab[TAB_DRAG];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                u[a] = v[a] * h;
+                F[a] = eps * g[a] - drag * u[a];
+            }
+        }
+    }
+};
+
+// Relax towards Eq. (30) and add Eq. (31); deviations in, deviations out.
+template <int Q, typename T, bool FORCH>
+__device__ __forceinline__ void collide(T (&d)[Q], const Node<Q, T, FORCH>& s, const T* tab, T omega, T cforce)
+{
+    using L = Lat<Q>;
+    const T ieps = tab[TAB_INV_EPS];
+    const T uu = s.u[0] * s.u[0] + s.u[1] * s.u[1] + s.u[2] * s.u[2];
+    const T uF = s.u[0] * s.F[0] + s.u[1] * s.F[1] + s.u[2] * s.F[2];
+    const T A = T(-1.5) * ieps * uu;
+    const T B = T(-3) * ieps * uF;
+    const T omw = T(1) - omega;
+    const T odr = omega * s.drho;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const T eu = T(L::ex(i)) * s.u[0] + T(L::ey(i)) * s.u[1] + T(L::ez(i)) * s.u[2];
+        const T eF = T(L::ex(i)) * s.F[0] + T(L::ey(i)) * s.F[1] + T(L::ez(i)) * s.F[2];
+        const T teq = T(3) * eu + T(4.5) * ieps * eu * eu + A;
+        const T tF = cforce * (T(3) * eF + T(9) * ieps * eu * eF + B);
+        d[i] = omw * d[i] + T(L::w(i)) * (odr + s.rho * (omega * teq + tF));
+    }
+}
+
+template <int Q, typename T, bool FORCH>
+__device__ __forceinline__ void load_table(T* lds, const Args& a, int inst)
+{
+    constexpr int NT = FORCH ? kTabW : 4;
+    const T* gt = static_cast<const T*>(a.tab) + (size_t)inst * kClasses * kTabW;
+    for (int k = threadIdx.x; k < kClasses * NT; k += kBlock) lds[k] = gt[(k / NT) * kTabW + (k % NT)];
+    __syncthreads();
+}
+
+// ---------------------------------------------------------------- the sweep --
+template <int Q, int STORE, int BC, bool FORCH>
+__global__ __launch_bounds__(kBlock) void k_sweep(Args a)
+{
+    using SS = St<STORE>;
+    using S = typename SS::S;
+    using T = typename SS::T;
+    constexpr int NT = FORCH ? kTabW : 4;
+    __shared__ T tab[kClasses * NT];
+
+    const int tid = xcd_tile(blockIdx.x, gridDim.x);
+    const Tile t = a.tiles[tid];
+    if (!a.active[t.inst]) return;
+    const InstDev& I = a.inst[t.inst];
+    load_table<Q, T, FORCH>(tab, a, t.inst);
+
+    const int sel = (a.parity + I.par) & 1;
+    const S* __restrict__ src = static_cast<const S*>(a.buf[sel]) + I.pop_off;
+    S* __restrict__ dst = static_cast<S*>(a.buf[sel ^ 1]) + I.pop_off;
+    const uint8_t* __restrict__ cls = a.cls + I.cls_off;
+    const T g[3] = {T(I.g[0]), T(I.g[1]), T(I.g[2])};
+    const T omega = T(I.omega), cforce = T(I.cforce);
+    const float scale = I.scale;
+    const int x = t.x0 + (threadIdx.x & (kTileX - 1));
+    const int z = t.z0;
+
+    for (int r = 0; r < a.rows; ++r) {
+        const int y = t.y0 + r * kBlockRows + (threadIdx.x / kTileX);
+        if (x >= I.nx || y >= I.ny) continue;
+        const int n = (z * I.ny + y) * I.nx + x;
+        const int c = cls[n];
+        if (BC >= 2 && c == kWallClass) continue;
+        T d[Q];
+        gather<Q, STORE, BC>(d, src, cls, I, x, y, z, n);
+        Node<Q, T, FORCH> s;
+        const T* ct = tab + c * NT;
+        s.moments(d, ct, g);
+        collide<Q, T, FORCH>(d, s, ct, omega, cforce);
+#pragma unroll
+        for (int i = 0; i < Q; ++i) dst[i * I.stride + n] = SS::enc(d[i], scale);
+    }
+}
+
+// ------------------------------------------------------------ observations --
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Sum kN doubles over the 256 threads of a block in a fixed order; result in thread 0.
+template <int kN> __device__ __forceinline__ void block_sum(double (&v)[kN], double* lds)
+{
+#pragma unroll
+    for (int k = 0; k < kN; ++k) v[k] = wave_sum(v[k]);
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (lane == 0)
+#pragma unroll
+        for (int k = 0; k < kN; ++k) lds[wave * kN + k] = v[k];
+    __syncthreads();
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int k = 0; k < kN; ++k) v[k] = lds[k] + lds[kN + k] + lds[2 * kN + k] + lds[3 * kN + k];
+}
+
+// mode bit 0: store u into the snapshot; bit 1: accumulate |u - u_snap|^2.
+template <int Q, int STORE, int BC, bool FORCH>
+__global__ __launch_bounds__(kBlock) void k_observe(Args a, int mode, int all)
+{
+    using SS = St<STORE>;
+    using S = typename SS::S;
+    using T = typename SS::T;
+    constexpr int NT = FORCH ? kTabW : 4;
+    __shared__ T tab[kClasses * NT];
+    __shared__ double red[4 * 6];
+
+    const int tid = xcd_tile(blockIdx.x, gridDim.x);
+    const Tile t = a.tiles[tid];
+    if (!all && !a.active[t.inst]) return;
+    const InstDev& I = a.inst[t.inst];
+    load_table<Q, T, FORCH>(tab, a, t.inst);
+
+    const int sel = (a.parity + I.par) & 1;
+    const S* __restrict__ src = static_cast<const S*>(a.buf[sel]) + I.pop_off;
+    const uint8_t* __restrict__ cls = a.cls + I.cls_off;
+    T* __restrict__ snap = static_cast<T*>(a.snap) + I.snap_off;
+    const int N = I.nx * I.ny * I.nz;
+    const T g[3] = {T(I.g[0]), T(I.g[1]), T(I.g[2])};
+    const int x = t.x0 + (threadIdx.x & (kTileX - 1));
+    const int z = t.z0;
+    double acc[6] = {0, 0, 0, 0, 0, 0};
+
+    for (int r = 0; r < a.rows; ++r) {
+        const int y = t.y0 + r * kBlockRows + (threadIdx.x / kTileX);
+        if (x >= I.nx || y >= I.ny) continue;
+        const int n = (z * I.ny + y) * I.nx + x;
+        const int c = cls[n];
+        if (BC >= 2 && c == kWallClass) continue;
+        T d[Q];
+        gather<Q, STORE, BC>(d, src, cls, I, x, y, z, n);
+        Node<Q, T, FORCH> s;
+        s.moments(d, tab + c * NT, g);
+        if (mode & 2) {
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                const double du = double(s.u[k]) - double(snap[k * N + n]);
+                acc[P_SD] += du * du;
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            acc[P_SU] += double(s.u[k]) * double(s.u[k]);
+            acc[P_UX + k] += double(s.u[k]);
+        }
+        if (!(finite(s.drho) && finite(s.u[0]) && finite(s.u[1]) && finite(s.u[2]))) acc[P_BAD] += 1.0;
+        if (mode & 1)
+#pragma unroll
+            for (int k = 0; k < 3; ++k) snap[k * N + n] = s.u[k];
+    }
+    block_sum<6>(acc, red);
+    if (threadIdx.x == 0) {
+        double* p = a.part + (size_t)tid * kPartW;
+#pragma unroll
+        for (int k = 0; k < 6; ++k) p[k] = acc[k];
+    }
+}
+
+// One workgroup per instance: sum its tile partials in a fixed order.
+__global__ __launch_bounds__(kBlock) void k_finalize(Args a, double tol, int with_r, int count_check, int all)
+{
+    __shared__ double red[kBlock];
+    const int inst = blockIdx.x;
+    if (!all && !a.active[inst]) return;
+    const InstDev& I = a.inst[inst];
+    double acc[6] = {0, 0, 0, 0, 0, 0};
+    for (int t = threadIdx.x; t < I.ntiles; t += kBlock) {
+        const double* p = a.part + (size_t)(I.tile0 + t) * kPartW;
+#pragma unroll
+        for (int k = 0; k < 6; ++k) acc[k] += p[k];
+    }
+    double out[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        red[threadIdx.x] = acc[k];
+        __syncthreads();
+        for (int s = kBlock / 2; s > 0; s >>= 1) {
+            if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+            __syncthreads();
+        }
+        out[k] = red[0];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        double* res = a.res + (size_t)inst * kPartW;
+#pragma unroll
+        for (int k = 0; k < 6; ++k) res[k] = out[k];
+        if (with_r) {
+            const double r = sqrt(out[P_SD]) / (double(a.dsteps[inst]) * sqrt(out[P_SU]));
+            res[P_R] = (out[P_SU] > 0.0) ? r : INFINITY;
+            if (out[P_BAD] > 0.0) res[P_R] = NAN;
+            if (tol > 0.0 && res[P_R] <= tol) a.active[inst] = 0;
+        }
+        if (count_check) res[P_NCHK] += 1.0;
+    }
+}
+
+__global__ void k_zero(uint32_t* p, size_t n)
+{
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        p[i] = 0u;
+}
+
+// Equilibrium of (rho, u) written so that the next pull reads it back as f(x).
+template <int Q, int STORE, int BC, typename R>
+__global__ __launch_bounds__(kBlock) void k_set_fields(Args a, int inst, const R* rho_in, const R* u_in)
+{
+    using SS = St<STORE>;
+    using S = typename SS::S;
+    using T = typename SS::T;
+    using L = Lat<Q>;
+    const InstDev& I = a.inst[inst];
+    const Tile t = a.tiles[I.tile0 + blockIdx.x];
+    const T* tabg = static_cast<const T*>(a.tab) + (size_t)inst * kClasses * kTabW;
+    const int sel = (a.parity + I.par) & 1;
+    S* __restrict__ dst = static_cast<S*>(a.buf[sel]) + I.pop_off;
+    const uint8_t* __restrict__ cls = a.cls + I.cls_off;
+    const int N = I.nx * I.ny * I.nz;
+    const int x = t.x0 + (threadIdx.x & (kTileX - 1));
+    const int z = t.z0;
+    for (int r = 0; r < a.rows; ++r) {
+        const int y = t.y0 + r * kBlockRows + (threadIdx.x / kTileX);
+        if (x >= I.nx || y >= I.ny) continue;
+        const int n = (z * I.ny + y) * I.nx + x;
+        const int c = cls[n];
+        if (c == kWallClass) continue;
+        const T rho = T(rho_in[n]);
+        const T u[3] = {T(u_in[n]), T(u_in[N + n]), T(u_in[2 * N + n])};
+        const T ieps = tabg[c * kTabW + TAB_INV_EPS];
+        const T uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            const T eu = T(L::ex(i)) * u[0] + T(L::ey(i)) * u[1] + T(L::ez(i)) * u[2];
+            const T dq = T(L::w(i)) * ((rho - T(1)) +
+                                        rho * (T(3) * eu + T(4.5) * ieps * eu * eu - T(1.5) * ieps * uu));
+            // destination slot: the pull of direction i at n reads plane i at n - e_i
+            // when that move is open, else plane opp(i) at n itself.
+            const int ex = L::ex(i), ey = L::ey(i), ez = L::ez(i);
+            int sx = x - ex, sy = y - ey, sz = z - ez;
+            bool blocked = false;
+            if (sx < 0) { blocked |= (I.walls & 1u) != 0; sx += I.nx; }
+            if (sx >= I.nx) { blocked |= (I.walls & 2u) != 0; sx -= I.nx; }
+            if (sy < 0) { blocked |= (I.walls & 4u) != 0; sy += I.ny; }
+            if (sy >= I.ny) { blocked |= (I.walls & 8u) != 0; sy -= I.ny; }
+            if (sz < 0) { blocked |= (I.walls & 16u) != 0; sz += I.nz; }
+            if (sz >= I.nz) { blocked |= (I.walls & 32u) != 0; sz -= I.nz; }
+            const int sn = (sz * I.ny + sy) * I.nx + sx;
+            if (BC >= 2 && !blocked && i != 0) blocked = cls[sn] == kWallClass;
+            const int idx = blocked ? L::opp(i) * I.stride + n : i * I.stride + sn;
+            dst[idx] = SS::enc(dq, I.scale);
+        }
+    }
+}
+
+template <int Q, int STORE, int BC, bool FORCH>
+__global__ __launch_bounds__(kBlock) void k_get_fields(Args a, int inst, double* rho_out, double* u_out,
+                                                        double* pops)
+{
+    using SS = St<STORE>;
+    using S = typename SS::S;
+    using T = typename SS::T;
+    using L = Lat<Q>;
+    const InstDev& I = a.inst[inst];
+    const Tile t = a.tiles[I.tile0 + blockIdx.x];
+    const T* tabg = static_cast<const T*>(a.tab) + (size_t)inst * kClasses * kTabW;
+    const int sel = (a.parity + I.par) & 1;
+    const S* __restrict__ src = static_cast<const S*>(a.buf[sel]) + I.pop_off;
+    const uint8_t* __restrict__ cls = a.cls + I.cls_off;
+    const int N = I.nx * I.ny * I.nz;
+    const T g[3] = {T(I.g[0]), T(I.g[1]), T(I.g[2])};
+    const int x = t.x0 + (threadIdx.x & (kTileX - 1));
+    const int z = t.z0;
+    for (int r = 0; r < a.rows; ++r) {
+        const int y = t.y0 + r * kBlockRows + (threadIdx.x / kTileX);
+        if (x >= I.nx || y >= I.ny) continue;
+        const int n = (z * I.ny + y) * I.nx + x;
+        const int c = cls[n];
+        if (c == kWallClass) {
+            if (rho_out) rho_out[n] = 0.0;
+            if (u_out) u_out[n] = u_out[N + n] = u_out[2 * N + n] = 0.0;
+            if (pops)
+                for (int i = 0; i < Q; ++i) pops[(size_t)i * N + n] = 0.0;
+            continue;
+        }
+        T d[Q];
+        gather<Q, STORE, BC>(d, src, cls, I, x, y, z, n);
+        T ct[kTabW];
+#pragma unroll
+        for (int k = 0; k < kTabW; ++k) ct[k] = tabg[c * kTabW + k];
+        Node<Q, T, FORCH> s;
+        s.moments(d, ct, g);
+        if (rho_out) rho_out[n] = 1.0 + double(s.drho);
+        if (u_out)
+            for (int k = 0; k < 3; ++k) u_out[k * N + n] = double(s.u[k]);
+        if (pops)
+#pragma unroll
+            for (int i = 0; i < Q; ++i) pops[(size_t)i * N + n] = L::w(i) + double(d[i]);
+    }
+}
+
+// -------------------------------------------------------------- dispatch --
+template <int Q, int STORE, int BC, bool FORCH> struct SweepK {
+    static hipError_t go(const Args& a, hipStream_t s)
+    {
+        hipLaunchKernelGGL((k_sweep<Q, STORE, BC, FORCH>), dim3(a.ntiles), dim3(kBlock), 0, s, a);
+        return hipGetLastError();
+    }
+};
+template <int Q, int STORE, int BC, bool FORCH> struct ObserveK {
+    static hipError_t go(const Args& a, hipStream_t s, int mode, int all)
+    {
+        hipLaunchKernelGGL((k_observe<Q, STORE, BC, FORCH>), dim3(a.ntiles), dim3(kBlock), 0, s, a, mode, all);
+        return hipGetLastError();
+    }
+};
+template <int Q, int STORE, int BC, bool FORCH> struct GetFieldsK {
+    static hipError_t go(const Args& a, hipStream_t s, int inst, int ntiles, double* rho, double* u, double* p)
+    {
+        hipLaunchKernelGGL((k_get_fields<Q, STORE, BC, FORCH>), dim3(ntiles), dim3(kBlock), 0, s, a, inst, rho, u,
+                           p);
+        return hipGetLastError();
+    }
+};
+
+template <template <int, int, int, bool> class K, typename... A>
+hipError_t dispatch(const Config& c, A... args)
+{
+#define GLBM_CASE(QQ, SS, BB, FF)                                                          \
+    if (c.q == QQ && c.store == SS && c.bc == BB && c.forch == FF) return K<QQ, SS, BB, FF>::go(args...);
+#define GLBM_F(QQ, SS, BB) GLBM_CASE(QQ, SS, BB, false) GLBM_CASE(QQ, SS, BB, true)
+#define GLBM_B(QQ, SS) GLBM_F(QQ, SS, 0) GLBM_F(QQ, SS, 1) GLBM_F(QQ, SS, 2)
+#define GLBM_S(QQ) GLBM_B(QQ, GLBM_STORE_F64) GLBM_B(QQ, GLBM_STORE_F32) GLBM_B(QQ, GLBM_STORE_F16DEV)
+    GLBM_S(9)
+    GLBM_S(19)
+#undef GLBM_S
+#undef GLBM_B
+#undef GLBM_F
+#undef GLBM_CASE
+    return hipErrorInvalidValue;
+}
+
+template <int Q, int STORE, int BC, typename R>
+hipError_t set_fields_go(const Args& a, hipStream_t s, int inst, int ntiles, const R* rho, const R* u)
+{
+    hipLaunchKernelGGL((k_set_fields<Q, STORE, BC, R>), dim3(ntiles), dim3(kBlock), 0, s, a, inst, rho, u);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_sweep(const Config& c, const Args& a, hipStream_t s)
+{
+    if (a.ntiles <= 0) return hipSuccess;
+    return dispatch<SweepK>(c, a, s);
+}
+
+hipError_t launch_observe(const Config& c, const Args& a, int mode, hipStream_t s)
+{
+    if (a.ntiles <= 0) return hipSuccess;
+    return dispatch<ObserveK>(c, a, s, mode & 3, (mode & 4) ? 1 : 0);
+}
+
+hipError_t launch_finalize(const Args& a, int n_inst, double tol, int with_r, int count_check, hipStream_t s)
+{
+    const int all = with_r ? 0 : 1;
+    hipLaunchKernelGGL(k_finalize, dim3(n_inst), dim3(kBlock), 0, s, a, tol, with_r, count_check, all);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t s)
+{
+    const size_t n = bytes / 4;
+    if (n == 0) return hipSuccess;
+    const size_t blocks = std::min<size_t>((n + 255) / 256, 65536);
+    hipLaunchKernelGGL(k_zero, dim3((unsigned)blocks), dim3(256), 0, s, static_cast<uint32_t*>(p), n);
+    return hipGetLastError();
+}
+
+hipError_t launch_set_fields(const Config& c, const Args& a, int inst, int ntiles, const void* rho,
+                             const void* u, int src_is_double, hipStream_t s)
+{
+    if (ntiles <= 0) return hipSuccess;
+#define GLBM_SF(QQ, SS, BB)                                                                              \
+    if (c.q == QQ && c.store == SS && c.bc == BB)                                                        \
+        return src_is_double                                                                             \
+                   ? set_fields_go<QQ, SS, BB, double>(a, s, inst, ntiles, static_cast<const double*>(rho), \
+                                                       static_cast<const double*>(u))                     \
+                   : set_fields_go<QQ, SS, BB, float>(a, s, inst, ntiles, static_cast<const float*>(rho),   \
+                                                      static_cast<const float*>(u));
+#define GLBM_SF_B(QQ, SS) GLBM_SF(QQ, SS, 0) GLBM_SF(QQ, SS, 1) GLBM_SF(QQ, SS, 2)
+#define GLBM_SF_S(QQ) GLBM_SF_B(QQ, GLBM_STORE_F64) GLBM_SF_B(QQ, GLBM_STORE_F32) GLBM_SF_B(QQ, GLBM_STORE_F16DEV)
+    GLBM_SF_S(9)
+    GLBM_SF_S(19)
+#undef GLBM_SF_S
+#undef GLBM_SF_B
+#undef GLBM_SF
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_get_fields(const Config& c, const Args& a, int inst, int ntiles, double* rho, double* u,
+                             double* pops, hipStream_t s)
+{
+    if (ntiles <= 0) return hipSuccess;
+    return dispatch<GetFieldsK>(c, a, s, inst, ntiles, rho, u, pops);
+}
+
+}  // namespace glbm
