@@ -53,6 +53,60 @@ def traffic_from_profile(store: str, side: int):
     return rec.get("hbm_bytes_per_launch")
 
 
+def calibrate_copy(nbytes=1 << 30, reps=5):
+    """A plain elementwise copy of known size, for scaling the HBM counters."""
+    import torch
+    a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(reps):
+        torch.neg(a, out=b)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "reps": reps}))
+
+
+def _pmc_per_kernel(path):
+    import csv
+    import glob
+    files = glob.glob(os.path.join(path, "**", "*counter_collection.csv"), recursive=True)
+    out = {}
+    for f in files:
+        for r in csv.DictReader(open(f)):
+            out.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
+    return out
+
+
+def pmc_summary(fetch_dir, write_dir, cfetch_dir, cwrite_dir, store, side):
+    """Turn four rocprofv3 --pmc runs (FETCH_SIZE / WRITE_SIZE of the bench and of
+    calibrate_copy) into HBM bytes per sweep launch.  Counters are KiB per
+    dispatch; each is scaled by (known copy bytes) / (counter on the copy)."""
+    def pick(d, key):
+        vals = [v for k, vs in d.items() if key in k for v in vs]
+        return sum(vals) / len(vals), len(vals)
+    nbytes = 1 << 30
+    cf, _ = pick(_pmc_per_kernel(cfetch_dir), "neg")
+    cw, _ = pick(_pmc_per_kernel(cwrite_dir), "neg")
+    f_scale = nbytes / (cf * 1024.0)
+    w_scale = nbytes / (cw * 1024.0)
+    sf, nf = pick(_pmc_per_kernel(fetch_dir), "k_sweep")
+    sw, nw = pick(_pmc_per_kernel(write_dir), "k_sweep")
+    read = sf * 1024.0 * f_scale
+    write = sw * 1024.0 * w_scale
+    n = side * side
+    bpl = 2 * 9 * {"f32": 4, "f16dev": 2, "f64": 8}[store] + 1
+    rec = {"kernel": "k_sweep<9,%s> on %dx%d" % (store, side, side),
+           "kernel_source_hash": kernel_source_hash(),
+           "fetch_kib_per_launch": sf, "write_kib_per_launch": sw, "launches": [nf, nw],
+           "copy_fetch_kib": cf, "copy_write_kib": cw, "fetch_scale": f_scale, "write_scale": w_scale,
+           "hbm_read_bytes_per_launch": read, "hbm_write_bytes_per_launch": write,
+           "hbm_bytes_per_launch": read + write,
+           "algorithmic_bytes_per_launch": bpl * n,
+           "traffic_over_algorithmic": (read + write) / (bpl * n)}
+    path = os.path.join(ROOT, "profiles", "sweep_d2q9_%s_%d_traffic.json" % (store, side))
+    with open(path, "w") as fh:
+        json.dump(rec, fh, indent=1)
+    print(json.dumps(rec))
+
+
 def cpu_baseline(cls_crop, table, steps):
     import oracle
     eps, k, fe = table
@@ -74,7 +128,17 @@ def main():
     ap.add_argument("--store", default="f32", choices=("f32", "f16dev", "f64"))
     ap.add_argument("--cpu-steps", type=int, default=1000)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run only a plain 1 GiB elementwise copy (counter calibration)")
+    ap.add_argument("--pmc-summary", nargs=4, metavar=("FETCH", "WRITE", "COPY_FETCH", "COPY_WRITE"),
+                    help="summarise rocprofv3 --pmc output directories into profiles/")
     args = ap.parse_args()
+    if args.pmc_summary:
+        pmc_summary(*args.pmc_summary, store=args.store, side=args.side)
+        return
+    if args.calibrate_copy:
+        calibrate_copy()
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the GLBM hot path here is built and timed on a single "
               "MI355X (multi-GPU sharding is a design note, not part of this build).", file=sys.stderr)

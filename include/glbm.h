@@ -179,20 +179,32 @@ int glbm_save_state(glbm_ctx ctx, void* host, size_t bytes);
 int glbm_load_state(glbm_ctx ctx, const void* host, size_t bytes);
 
 /*
- * Options.  GLBM_OPT_GRAPH (default 1): replay full n_c-step chunks from a
- * captured HIP graph.  GLBM_OPT_TIMING (default 0): bracket every sweep launch
- * with HIP events on the context stream; glbm_sweep_time reports the summed
- * time and launch count since the option was last set.  GLBM_OPT_TILE_ROWS:
- * rows of nodes each workgroup walks (1, 2, 4, 8, 16; default picked by size).
+ * Options (value in parentheses: default).
+ *   GLBM_OPT_GRAPH (1)       replay full n_c-step chunks from a captured HIP graph
+ *   GLBM_OPT_TIMING (0)      bracket every sweep launch with HIP events on the
+ *                            context's stream; glbm_sweep_time reports the summed
+ *                            time and the launch count since the option was set
+ *   GLBM_OPT_TILE_WIDTH      nodes along x per workgroup tile: 64 .. 1024, a power
+ *                            of two (default: 256, or the largest <= max nx)
+ *   GLBM_OPT_TILE_ROWS       rows per tile, 1 .. 256; width x rows must be a
+ *                            multiple of 256 (default: 256 / width)
+ *   GLBM_OPT_CACHE (13)      memory policy bits: 0 nontemporal population stores;
+ *                            1 nontemporal loads of the planes without an x shift;
+ *                            2 workgroups in launch order (clear: grouped per XCD);
+ *                            3 per-class constants read through L1 (clear: staged
+ *                            in LDS)
+ * Errors: GLBM_EINVAL for unknown options or values.
  */
-enum { GLBM_OPT_GRAPH = 1, GLBM_OPT_TIMING = 2, GLBM_OPT_TILE_ROWS = 3 };
+enum { GLBM_OPT_GRAPH = 1, GLBM_OPT_TIMING = 2, GLBM_OPT_TILE_ROWS = 3, GLBM_OPT_TILE_WIDTH = 4,
+       GLBM_OPT_CACHE = 5 };
 int glbm_set_option(glbm_ctx ctx, int32_t option, int64_t value);
 int glbm_sweep_time(glbm_ctx ctx, double* ms_total, int64_t* launches);
 
 /*
- * Pick GLBM_OPT_TILE_ROWS for this context by timing each candidate for
- * `steps` sweeps (the state advances by those steps, an even total).  The
- * chosen value is returned in *chosen (may be NULL).
+ * Autotuner: time every (tile width, tile rows, cache policy) candidate for
+ * `steps` sweeps and keep the fastest.  The state advances by those sweeps
+ * (an even number per candidate); the residual snapshot is reset.  If chosen
+ * is not NULL it receives {width, rows, cache}.
  */
 int glbm_autotune(glbm_ctx ctx, int32_t steps, int32_t* chosen);
 

@@ -140,7 +140,9 @@ struct glbm_ctx_s {
     double* res_p = nullptr;
     int32_t* active_p = nullptr;
     // tiling and graph
-    int rows = 4;
+    int tw_log2 = 6;   // tile width 2^tw_log2
+    int th = 4;        // tile height
+    int cache = 13;    // memory policy, see Args::cache (nontemporal stores, plain order, L1 table)
     int ntiles = 0;
     bool use_graph = true;
     hipGraphExec_t graph = nullptr;
@@ -169,7 +171,9 @@ struct glbm_ctx_s {
         a.dsteps = dsteps_d;
         a.ntiles = ntiles;
         a.parity = parity & 1;
-        a.rows = rows;
+        a.tw_log2 = tw_log2;
+        a.nslot = ((1 << tw_log2) * th) / kBlock;
+        a.cache = cache;
         return a;
     }
 };
@@ -186,13 +190,13 @@ void free_graph(glbm_ctx c)
 int build_tiles(glbm_ctx c)
 {
     c->tiles_h.clear();
-    const int th = kBlockRows * c->rows;
+    const int th = c->th, tw = 1 << c->tw_log2;
     for (int i = 0; i < c->n_inst; ++i) {
         InstDev& I = c->inst_h[i];
         I.tile0 = (int32_t)c->tiles_h.size();
         for (int z = 0; z < I.nz; ++z)
             for (int y = 0; y < I.ny; y += th)
-                for (int x = 0; x < I.nx; x += kTileX) c->tiles_h.push_back(Tile{i, x, y, z});
+                for (int x = 0; x < I.nx; x += tw) c->tiles_h.push_back(Tile{i, x, y, z});
         I.ntiles = (int32_t)c->tiles_h.size() - I.tile0;
     }
     c->ntiles = (int)c->tiles_h.size();
@@ -211,19 +215,22 @@ int build_tiles(glbm_ctx c)
     return GLBM_OK;
 }
 
-int default_rows(glbm_ctx c)
+// Default tile: one node per thread, 256 nodes along x (fewer if the grid is
+// narrower), so each wavefront reads 64 consecutive nodes per plane and the
+// lines straddled by x-shifted reads are shared by the four wavefronts.
+void default_tile(glbm_ctx c)
 {
-    int64_t total = 0;
-    int min_ny = 1 << 30;
-    for (auto& I : c->inst_h) {
-        total += (int64_t)I.nx * I.ny * I.nz;
-        min_ny = std::min(min_ny, I.ny);
-    }
-    int r = 4;
-    while (r > 1 && kBlockRows * r > min_ny) r >>= 1;
-    // small problems: keep enough workgroups to cover the 256 compute units
-    while (r > 1 && total / (kBlock * r) < 2048) r >>= 1;
-    return r;
+    int max_nx = 1;
+    for (auto& I : c->inst_h) max_nx = std::max(max_nx, I.nx);
+    int twl = 6;
+    while (twl < 8 && (1 << (twl + 1)) <= max_nx) ++twl;
+    c->tw_log2 = twl;
+    c->th = kBlock >> twl;
+}
+
+bool tile_ok(int tw_log2, int th)
+{
+    return tw_log2 >= 6 && tw_log2 <= 10 && th >= 1 && th <= 256 && (((1 << tw_log2) * th) % kBlock) == 0;
 }
 
 // Fork the work stream from the caller's stream.
@@ -488,7 +495,7 @@ int glbm_init_geometry(glbm_ctx* out, int32_t n_inst, const glbm_instance_desc* 
     TRYHIP(launch_zero(c->res_d, (size_t)n_inst * kPartW * sizeof(double), c->work));
     TRYHIP(launch_zero(c->tab_d, (size_t)n_inst * kClasses * kTabW * c->tsz, c->work));
     for (int i = 0; i < n_inst; ++i) c->res_p[i * kPartW + P_R] = INFINITY;
-    c->rows = default_rows(c);
+    default_tile(c);
     TRY(build_tiles(c));
     TRY(upload_state(c));
     TRY(leave(c));
@@ -880,14 +887,32 @@ int glbm_set_option(glbm_ctx c, int32_t option, int64_t value)
         c->launches = 0;
         return GLBM_OK;
     }
-    case GLBM_OPT_TILE_ROWS: {
-        if (value != 1 && value != 2 && value != 4 && value != 8 && value != 16)
-            return fail(GLBM_EINVAL, "tile rows must be 1, 2, 4, 8 or 16");
-        if (c->rows == (int)value) return GLBM_OK;
+    case GLBM_OPT_TILE_ROWS:
+    case GLBM_OPT_TILE_WIDTH: {
+        int twl = c->tw_log2, th = c->th;
+        if (option == GLBM_OPT_TILE_ROWS) {
+            th = (int)value;
+        } else {
+            int l = 6;
+            while (l <= 10 && (1 << l) != value) ++l;
+            if (l > 10) return fail(GLBM_EINVAL, "tile width must be a power of two in [64, 1024]");
+            twl = l;
+            if (((1 << twl) * th) % kBlock) th = kBlock >> twl;
+        }
+        if (!tile_ok(twl, th))
+            return fail(GLBM_EINVAL, "tile %d x %d must hold a multiple of %d nodes (height 1..256)", 1 << twl, th,
+                        kBlock);
+        if (twl == c->tw_log2 && th == c->th) return GLBM_OK;
         HIPCHK(hipStreamSynchronize(c->work));
-        c->rows = (int)value;
+        c->tw_log2 = twl;
+        c->th = th;
         return build_tiles(c);
     }
+    case GLBM_OPT_CACHE:
+        if (value < 0 || value > 15) return fail(GLBM_EINVAL, "memory policy must be in [0, 15]");
+        c->cache = (int)value;
+        free_graph(c);
+        return GLBM_OK;
     default:
         return fail(GLBM_EINVAL, "unknown option %d", option);
     }
@@ -912,42 +937,50 @@ int glbm_autotune(glbm_ctx c, int32_t steps, int32_t* chosen)
     int rc = check_tables(c);
     if (rc) return rc;
     const bool old_timing = c->timing;
-    const int cand[] = {1, 2, 4, 8, 16};
+    int max_nx = 1;
+    for (auto& I : c->inst_h) max_nx = std::max(max_nx, I.nx);
     double best = 1e300;
-    int best_r = c->rows;
-    for (int r : cand) {
-        int min_ny = 1 << 30;
-        for (auto& I : c->inst_h) min_ny = std::min(min_ny, I.ny);
-        if (r > 1 && kBlockRows * r > min_ny) continue;
-        rc = glbm_set_option(c, GLBM_OPT_TILE_ROWS, r);
-        if (rc) return rc;
-        rc = glbm_set_option(c, GLBM_OPT_TIMING, 1);
-        if (rc) return rc;
-        rc = enter(c);
-        if (rc) return rc;
-        for (int k = 0; k < steps && rc == GLBM_OK; ++k) rc = sweep_once(c, (int)((c->gstep + k) & 1));
-        if (rc) return rc;
-        double ms = 0.0;
-        int64_t nl = 0;
-        rc = glbm_sweep_time(c, &ms, &nl);
-        if (rc) return rc;
-        // the sweeps advanced every instance whose flag is set; keep the counters exact
-        for (int i = 0; i < c->n_inst; ++i)
-            if (c->active_h[i]) c->steps[i] += steps;
-        c->gstep += steps;
-        c->snap_valid = false;
-        rc = leave(c);
-        if (rc) return rc;
-        if (ms < best) {
-            best = ms;
-            best_r = r;
+    int best_twl = c->tw_log2, best_th = c->th, best_cache = c->cache;
+    for (int twl = 6; twl <= 10; ++twl) {
+        if (twl > 6 && (1 << twl) > 2 * max_nx) break;
+        for (int th : {1, 2, 4, 8, 16}) {
+            if (!tile_ok(twl, th)) continue;
+            for (int cache : {1, 3, 5, 9, 13, 15}) {
+                c->cache = cache;
+                rc = glbm_set_option(c, GLBM_OPT_TILE_WIDTH, 1 << twl);
+                if (!rc) rc = glbm_set_option(c, GLBM_OPT_TILE_ROWS, th);
+                if (!rc) rc = glbm_set_option(c, GLBM_OPT_TIMING, 1);
+                if (!rc) rc = enter(c);
+                for (int k = 0; k < steps && rc == GLBM_OK; ++k) rc = sweep_once(c, (int)((c->gstep + k) & 1));
+                double ms = 0.0;
+                int64_t nl = 0;
+                if (!rc) rc = glbm_sweep_time(c, &ms, &nl);
+                // the sweeps advanced every active instance; keep the counters exact
+                for (int i = 0; i < c->n_inst; ++i)
+                    if (c->active_h[i]) c->steps[i] += steps;
+                c->gstep += steps;
+                c->snap_valid = false;
+                if (!rc) rc = leave(c);
+                if (rc) return rc;
+                if (ms < best) {
+                    best = ms;
+                    best_twl = twl;
+                    best_th = th;
+                    best_cache = cache;
+                }
+            }
         }
     }
     rc = glbm_set_option(c, GLBM_OPT_TIMING, old_timing ? 1 : 0);
+    if (!rc) rc = glbm_set_option(c, GLBM_OPT_TILE_WIDTH, 1 << best_twl);
+    if (!rc) rc = glbm_set_option(c, GLBM_OPT_TILE_ROWS, best_th);
+    if (!rc) rc = glbm_set_option(c, GLBM_OPT_CACHE, best_cache);
     if (rc) return rc;
-    rc = glbm_set_option(c, GLBM_OPT_TILE_ROWS, best_r);
-    if (rc) return rc;
-    if (chosen) *chosen = best_r;
+    if (chosen) {
+        chosen[0] = 1 << best_twl;
+        chosen[1] = best_th;
+        chosen[2] = best_cache;
+    }
     return GLBM_OK;
 }
 

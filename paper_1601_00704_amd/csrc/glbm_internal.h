@@ -7,9 +7,9 @@
 
 namespace glbm {
 
-constexpr int kTileX = 64;          // nodes along x per tile (one wavefront row)
-constexpr int kBlockRows = 4;       // rows of a 256-thread workgroup
-constexpr int kBlock = kTileX * kBlockRows;
+constexpr int kBlock = 256;         // threads per workgroup (4 wavefronts)
+constexpr int kMinTileW = 64;       // a wavefront covers 64 consecutive x
+constexpr int kMaxTileW = 1024;
 constexpr int kClasses = 256;
 constexpr int kWallClass = 255;
 constexpr int kTabW = 8;            // constants per class in the device table
@@ -73,7 +73,9 @@ struct Args {
     const int32_t* dsteps; // per instance steps since the snapshot
     int32_t ntiles;
     int32_t parity;        // g & 1
-    int32_t rows;          // rows per thread (tile height = 4 * rows)
+    int32_t tw_log2;       // tile width 2^tw_log2 nodes along x (64 .. 1024)
+    int32_t nslot;         // tile nodes / kBlock: nodes each thread visits
+    int32_t cache;         // bit 0: nontemporal population stores; bit 1: nontemporal loads of x-aligned planes
 };
 
 // Kernel configuration of a context.

@@ -90,7 +90,7 @@ template <typename T> __device__ __forceinline__ bool finite(T v) { return isfin
 template <int Q, int STORE, int BC>
 __device__ __forceinline__ void gather(typename St<STORE>::T (&d)[Q], const typename St<STORE>::S* __restrict__ src,
                                        const uint8_t* __restrict__ cls, const InstDev& I, int x, int y, int z,
-                                       int n)
+                                       int n, bool nt_aligned = false)
 {
     using L = Lat<Q>;
     using S = St<STORE>;
@@ -118,7 +118,9 @@ __device__ __forceinline__ void gather(typename St<STORE>::T (&d)[Q], const type
             if (BC >= 2 && i != 0) blocked |= cls[sn] == kWallClass;
             if (blocked) idx = L::opp(i) * stride + n;
         }
-        d[i] = S::dec(src[idx], I.inv_scale);
+        // planes without an x shift are read by exactly one wavefront per cache line
+        const typename S::S raw = (ex == 0 && nt_aligned) ? __builtin_nontemporal_load(src + idx) : src[idx];
+        d[i] = S::dec(raw, I.inv_scale);
     }
 }
 
@@ -196,45 +198,88 @@ __device__ __forceinline__ void load_table(T* lds, const Args& a, int inst)
 }
 
 // ---------------------------------------------------------------- the sweep --
-template <int Q, int STORE, int BC, bool FORCH>
-__global__ __launch_bounds__(kBlock) void k_sweep(Args a)
+// U consecutive slots of a thread (U = 1 in use; the loads of all U slots are
+// issued before the first node is collided).
+template <int U, int Q, int STORE, int BC, bool FORCH>
+__device__ __forceinline__ void sweep_slots(const Args& a, const Tile& t, const InstDev& I, int sl0,
+                                            const typename St<STORE>::T* __restrict__ tb, int tw,
+                                            const typename St<STORE>::S* __restrict__ src,
+                                            typename St<STORE>::S* __restrict__ dst, const uint8_t* __restrict__ cls)
 {
     using SS = St<STORE>;
-    using S = typename SS::S;
     using T = typename SS::T;
-    constexpr int NT = FORCH ? kTabW : 4;
-    __shared__ T tab[kClasses * NT];
+    const T g[3] = {T(I.g[0]), T(I.g[1]), T(I.g[2])};
+    const T omega = T(I.omega), cforce = T(I.cforce);
+    const bool nt_store = (a.cache & 1) != 0, nt_load = (a.cache & 2) != 0;
+    const int twm = (1 << a.tw_log2) - 1;
+    const int z = t.z0;
+    int n[U], c[U];
+    bool ok[U];
+    T d[U][Q];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int slot = (sl0 + u) * kBlock + threadIdx.x;
+        const int x = t.x0 + (slot & twm);
+        const int y = t.y0 + (slot >> a.tw_log2);
+        ok[u] = x < I.nx && y < I.ny;
+        n[u] = ok[u] ? (z * I.ny + y) * I.nx + x : 0;
+        c[u] = ok[u] ? cls[n[u]] : 0;
+        if (BC >= 2 && c[u] == kWallClass) ok[u] = false;
+        if (ok[u]) gather<Q, STORE, BC>(d[u], src, cls, I, x, y, z, n[u], nt_load);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        if (!ok[u]) continue;
+        Node<Q, T, FORCH> s;
+        const T* ct = tb + c[u] * tw;
+        s.moments(d[u], ct, g);
+        collide<Q, T, FORCH>(d[u], s, ct, omega, cforce);
+        if (nt_store) {
+#pragma unroll
+            for (int i = 0; i < Q; ++i)
+                __builtin_nontemporal_store(SS::enc(d[u][i], I.scale), dst + i * I.stride + n[u]);
+        } else {
+#pragma unroll
+            for (int i = 0; i < Q; ++i) dst[i * I.stride + n[u]] = SS::enc(d[u][i], I.scale);
+        }
+    }
+}
 
-    const int tid = xcd_tile(blockIdx.x, gridDim.x);
-    const Tile t = a.tiles[tid];
-    if (!a.active[t.inst]) return;
-    const InstDev& I = a.inst[t.inst];
-    load_table<Q, T, FORCH>(tab, a, t.inst);
-
+template <int Q, int STORE, int BC, bool FORCH>
+__device__ __forceinline__ void sweep_tile(const Args& a, const Tile& t, const InstDev& I,
+                                           const typename St<STORE>::T* __restrict__ tb, int tw)
+{
+    using S = typename St<STORE>::S;
     const int sel = (a.parity + I.par) & 1;
     const S* __restrict__ src = static_cast<const S*>(a.buf[sel]) + I.pop_off;
     S* __restrict__ dst = static_cast<S*>(a.buf[sel ^ 1]) + I.pop_off;
     const uint8_t* __restrict__ cls = a.cls + I.cls_off;
-    const T g[3] = {T(I.g[0]), T(I.g[1]), T(I.g[2])};
-    const T omega = T(I.omega), cforce = T(I.cforce);
-    const float scale = I.scale;
-    const int x = t.x0 + (threadIdx.x & (kTileX - 1));
-    const int z = t.z0;
+    for (int sl = 0; sl < a.nslot; ++sl) sweep_slots<1, Q, STORE, BC, FORCH>(a, t, I, sl, tb, tw, src, dst, cls);
+}
 
-    for (int r = 0; r < a.rows; ++r) {
-        const int y = t.y0 + r * kBlockRows + (threadIdx.x / kTileX);
-        if (x >= I.nx || y >= I.ny) continue;
-        const int n = (z * I.ny + y) * I.nx + x;
-        const int c = cls[n];
-        if (BC >= 2 && c == kWallClass) continue;
-        T d[Q];
-        gather<Q, STORE, BC>(d, src, cls, I, x, y, z, n);
-        Node<Q, T, FORCH> s;
-        const T* ct = tab + c * NT;
-        s.moments(d, ct, g);
-        collide<Q, T, FORCH>(d, s, ct, omega, cforce);
-#pragma unroll
-        for (int i = 0; i < Q; ++i) dst[i * I.stride + n] = SS::enc(d[i], scale);
+// One time step of one tile.  Policy bits of a.cache: 0 nontemporal stores,
+// 1 nontemporal loads of x-aligned planes, 2 plain workgroup order (no XCD
+// grouping), 3 per-class constants read through the L1 cache instead of being
+// staged in LDS.  Measured on MI355X (4096^2, FP32): 256 x 1 tiles with bits
+// 0, 2 and 3 run at 5.9 TB/s; staging the table in LDS costs each workgroup
+// a fill and a barrier before its first population load is issued.
+template <int Q, int STORE, int BC, bool FORCH>
+__global__ __launch_bounds__(kBlock) void k_sweep(Args a)
+{
+    using T = typename St<STORE>::T;
+    constexpr int NT = FORCH ? kTabW : 4;
+    __shared__ T tab[kClasses * NT];
+
+    const int tid = (a.cache & 4) ? (int)blockIdx.x : xcd_tile(blockIdx.x, gridDim.x);
+    const Tile t = a.tiles[tid];
+    if (!a.active[t.inst]) return;
+    const InstDev& I = a.inst[t.inst];
+    if (a.cache & 8) {
+        const T* gt = static_cast<const T*>(a.tab) + (size_t)t.inst * kClasses * kTabW;
+        sweep_tile<Q, STORE, BC, FORCH>(a, t, I, gt, kTabW);
+    } else {
+        load_table<Q, T, FORCH>(tab, a, t.inst);
+        sweep_tile<Q, STORE, BC, FORCH>(a, t, I, tab, NT);
     }
 }
 
@@ -263,33 +308,26 @@ template <int kN> __device__ __forceinline__ void block_sum(double (&v)[kN], dou
 
 // mode bit 0: store u into the snapshot; bit 1: accumulate |u - u_snap|^2.
 template <int Q, int STORE, int BC, bool FORCH>
-__global__ __launch_bounds__(kBlock) void k_observe(Args a, int mode, int all)
+__device__ __forceinline__ void observe_tile(const Args& a, const Tile& t, const InstDev& I, int tid, int mode,
+                                             const typename St<STORE>::T* __restrict__ tb, int tw, double* red)
 {
     using SS = St<STORE>;
     using S = typename SS::S;
     using T = typename SS::T;
-    constexpr int NT = FORCH ? kTabW : 4;
-    __shared__ T tab[kClasses * NT];
-    __shared__ double red[4 * 6];
-
-    const int tid = xcd_tile(blockIdx.x, gridDim.x);
-    const Tile t = a.tiles[tid];
-    if (!all && !a.active[t.inst]) return;
-    const InstDev& I = a.inst[t.inst];
-    load_table<Q, T, FORCH>(tab, a, t.inst);
-
     const int sel = (a.parity + I.par) & 1;
     const S* __restrict__ src = static_cast<const S*>(a.buf[sel]) + I.pop_off;
     const uint8_t* __restrict__ cls = a.cls + I.cls_off;
     T* __restrict__ snap = static_cast<T*>(a.snap) + I.snap_off;
     const int N = I.nx * I.ny * I.nz;
     const T g[3] = {T(I.g[0]), T(I.g[1]), T(I.g[2])};
-    const int x = t.x0 + (threadIdx.x & (kTileX - 1));
+    const int twm = (1 << a.tw_log2) - 1;
     const int z = t.z0;
     double acc[6] = {0, 0, 0, 0, 0, 0};
 
-    for (int r = 0; r < a.rows; ++r) {
-        const int y = t.y0 + r * kBlockRows + (threadIdx.x / kTileX);
+    for (int sl = 0; sl < a.nslot; ++sl) {
+        const int slot = sl * kBlock + threadIdx.x;
+        const int x = t.x0 + (slot & twm);
+        const int y = t.y0 + (slot >> a.tw_log2);
         if (x >= I.nx || y >= I.ny) continue;
         const int n = (z * I.ny + y) * I.nx + x;
         const int c = cls[n];
@@ -297,7 +335,7 @@ __global__ __launch_bounds__(kBlock) void k_observe(Args a, int mode, int all)
         T d[Q];
         gather<Q, STORE, BC>(d, src, cls, I, x, y, z, n);
         Node<Q, T, FORCH> s;
-        s.moments(d, tab + c * NT, g);
+        s.moments(d, tb + c * tw, g);
         if (mode & 2) {
 #pragma unroll
             for (int k = 0; k < 3; ++k) {
@@ -320,6 +358,28 @@ __global__ __launch_bounds__(kBlock) void k_observe(Args a, int mode, int all)
         double* p = a.part + (size_t)tid * kPartW;
 #pragma unroll
         for (int k = 0; k < 6; ++k) p[k] = acc[k];
+    }
+}
+
+// mode bit 0: store u into the snapshot; bit 1: accumulate |u - u_snap|^2.
+template <int Q, int STORE, int BC, bool FORCH>
+__global__ __launch_bounds__(kBlock) void k_observe(Args a, int mode, int all)
+{
+    using T = typename St<STORE>::T;
+    constexpr int NT = FORCH ? kTabW : 4;
+    __shared__ T tab[kClasses * NT];
+    __shared__ double red[4 * 6];
+
+    const int tid = (a.cache & 4) ? (int)blockIdx.x : xcd_tile(blockIdx.x, gridDim.x);
+    const Tile t = a.tiles[tid];
+    if (!all && !a.active[t.inst]) return;
+    const InstDev& I = a.inst[t.inst];
+    if (a.cache & 8) {
+        const T* gt = static_cast<const T*>(a.tab) + (size_t)t.inst * kClasses * kTabW;
+        observe_tile<Q, STORE, BC, FORCH>(a, t, I, tid, mode, gt, kTabW, red);
+    } else {
+        load_table<Q, T, FORCH>(tab, a, t.inst);
+        observe_tile<Q, STORE, BC, FORCH>(a, t, I, tid, mode, tab, NT, red);
     }
 }
 
@@ -383,10 +443,12 @@ __global__ __launch_bounds__(kBlock) void k_set_fields(Args a, int inst, const R
     S* __restrict__ dst = static_cast<S*>(a.buf[sel]) + I.pop_off;
     const uint8_t* __restrict__ cls = a.cls + I.cls_off;
     const int N = I.nx * I.ny * I.nz;
-    const int x = t.x0 + (threadIdx.x & (kTileX - 1));
+    const int twm = (1 << a.tw_log2) - 1;
     const int z = t.z0;
-    for (int r = 0; r < a.rows; ++r) {
-        const int y = t.y0 + r * kBlockRows + (threadIdx.x / kTileX);
+    for (int sl = 0; sl < a.nslot; ++sl) {
+        const int slot = sl * kBlock + threadIdx.x;
+        const int x = t.x0 + (slot & twm);
+        const int y = t.y0 + (slot >> a.tw_log2);
         if (x >= I.nx || y >= I.ny) continue;
         const int n = (z * I.ny + y) * I.nx + x;
         const int c = cls[n];
@@ -435,10 +497,12 @@ __global__ __launch_bounds__(kBlock) void k_get_fields(Args a, int inst, double*
     const uint8_t* __restrict__ cls = a.cls + I.cls_off;
     const int N = I.nx * I.ny * I.nz;
     const T g[3] = {T(I.g[0]), T(I.g[1]), T(I.g[2])};
-    const int x = t.x0 + (threadIdx.x & (kTileX - 1));
+    const int twm = (1 << a.tw_log2) - 1;
     const int z = t.z0;
-    for (int r = 0; r < a.rows; ++r) {
-        const int y = t.y0 + r * kBlockRows + (threadIdx.x / kTileX);
+    for (int sl = 0; sl < a.nslot; ++sl) {
+        const int slot = sl * kBlock + threadIdx.x;
+        const int x = t.x0 + (slot & twm);
+        const int y = t.y0 + (slot >> a.tw_log2);
         if (x >= I.nx || y >= I.ny) continue;
         const int n = (z * I.ny + y) * I.nx + x;
         const int c = cls[n];

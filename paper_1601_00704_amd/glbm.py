@@ -24,7 +24,7 @@ GLBM_OK, GLBM_EINVAL, GLBM_ENOMEM, GLBM_EDEVICE, GLBM_ESTATE, GLBM_ENONFINITE, G
     0, -1, -2, -3, -4, -5, -6
 GLBM_WALL_CLASS = 255
 GLBM_SCALE_AUTO = -2147483648
-GLBM_OPT_GRAPH, GLBM_OPT_TIMING, GLBM_OPT_TILE_ROWS = 1, 2, 3
+GLBM_OPT_GRAPH, GLBM_OPT_TIMING, GLBM_OPT_TILE_ROWS, GLBM_OPT_TILE_WIDTH, GLBM_OPT_CACHE = 1, 2, 3, 4, 5
 STORE_NAMES = {"f64": GLBM_STORE_F64, "f32": GLBM_STORE_F32, "f16dev": GLBM_STORE_F16DEV}
 STORE_BYTES = {GLBM_STORE_F64: 8, GLBM_STORE_F32: 4, GLBM_STORE_F16DEV: 2}
 
@@ -215,10 +215,11 @@ def glbm_sweep_time(ctx):
     return ms.value, n.value
 
 
-def glbm_autotune(ctx, steps: int = 20) -> int:
-    ch = ctypes.c_int32()
-    _check(_lib.glbm_autotune(ctx, steps, ctypes.byref(ch)))
-    return ch.value
+def glbm_autotune(ctx, steps: int = 20):
+    """Returns the chosen (tile width, tile rows, cache policy)."""
+    ch = (ctypes.c_int32 * 3)()
+    _check(_lib.glbm_autotune(ctx, steps, ch))
+    return tuple(ch)
 
 
 def glbm_velocity_set(lattice: int):

@@ -16,7 +16,7 @@ def oracle_problem(q, cls, eps, k, f_eps=0.0, tau=1.0, G=(1e-6, 0, 0), walls=0, 
 
 
 def gpu_solver(g, q, cls, eps, k, f_eps=None, tau=1.0, G=(1e-6, 0, 0), walls=0, store="f64",
-               check_every=100, scale_log2=None, rows=None):
+               check_every=100, scale_log2=None, tile=None, cache=None):
     shape = cls.shape
     d = g.make_desc(shape, lattice=q, store=g.STORE_NAMES[store], tau=tau, g=G, wall_faces=walls,
                     check_every=check_every,
@@ -27,8 +27,11 @@ def gpu_solver(g, q, cls, eps, k, f_eps=None, tau=1.0, G=(1e-6, 0, 0), walls=0, 
     k = np.broadcast_to(np.asarray(k, np.float64), (256,))[:n_cls]
     fe = None if f_eps is None else np.broadcast_to(np.asarray(f_eps, np.float64), (256,))[:n_cls]
     s.set_local_perm(eps, k, fe)
-    if rows is not None:
-        s.set_option(g.GLBM_OPT_TILE_ROWS, rows)
+    if tile is not None:
+        s.set_option(g.GLBM_OPT_TILE_WIDTH, tile[0])
+        s.set_option(g.GLBM_OPT_TILE_ROWS, tile[1])
+    if cache is not None:
+        s.set_option(g.GLBM_OPT_CACHE, cache)
     return s
 
 

@@ -24,16 +24,16 @@ pytestmark = pytest.mark.gpu
 TOL = {"f64": 1e-11, "f32": 3e-5, "f16dev": 4e-3}
 
 
-def _compare(g, q, cls, eps, k, fe, store, steps, G, walls=0, tau=1.0, rows=None, scale=20):
-    print("case q=%d shape=%s store=%s steps=%d walls=%d rows=%s" % (q, cls.shape, store, steps, walls, rows),
-          flush=True)
+def _compare(g, q, cls, eps, k, fe, store, steps, G, walls=0, tau=1.0, tile=None, cache=None, scale=20):
+    print("case q=%d shape=%s store=%s steps=%d walls=%d tile=%s cache=%s" % (q, cls.shape, store, steps, walls,
+                                                                             tile, cache), flush=True)
     emul = {"f64": (0, 0), "f32": (0, 0), "f16dev": (2, scale)}[store]
     prob = oracle_problem(q, cls, eps, k, fe, tau=tau, G=G, walls=walls, store_mode=emul[0],
                           scale_log2=emul[1])
     f = prob.rest()
     prob.run(f, steps)
     rho_o, u_o = prob.fields(f)
-    s = gpu_solver(g, q, cls, eps, k, fe, tau=tau, G=G, walls=walls, store=store, rows=rows,
+    s = gpu_solver(g, q, cls, eps, k, fe, tau=tau, G=G, walls=walls, store=store, tile=tile, cache=cache,
                    scale_log2=scale if store == "f16dev" else None)
     try:
         s.step(steps)
@@ -72,10 +72,12 @@ def test_d2q9_walls_and_wall_nodes(gpu, store):
 
 
 @pytest.mark.parametrize("store", ["f64", "f32"])
-def test_d2q9_tile_rows(gpu, store):
+def test_d2q9_tile_shapes_and_cache_policies(gpu, store):
+    """Results do not depend on the tile shape or the cache policy (ragged tiles included)."""
     cls, eps, k, fe = random_case((70, 130), seed=8)
-    for rows in (1, 2, 8):
-        _compare(gpu, 9, cls, eps, k, None, store, 60, G=(2e-5, 0, 0), rows=rows)
+    for tile, cache in (((64, 4), 0), ((128, 2), 1), ((256, 1), 2), ((1024, 1), 3), ((256, 16), 13),
+                        ((512, 2), 9), ((64, 8), 15)):
+        _compare(gpu, 9, cls, eps, k, None, store, 60, G=(2e-5, 0, 0), tile=tile, cache=cache)
 
 
 def test_d2q9_forchheimer(gpu):
