@@ -92,7 +92,7 @@ def pmc_summary(fetch_dir, write_dir, cfetch_dir, cwrite_dir, store, side):
     read = sf * 1024.0 * f_scale
     write = sw * 1024.0 * w_scale
     n = side * side
-    bpl = 2 * 9 * {"f32": 4, "f16dev": 2, "f64": 8}[store] + 1
+    bpl = {"f32": 73, "f16dev": 37, "f16loc": 45, "f64": 145}[store]
     rec = {"kernel": "k_sweep<9,%s> on %dx%d" % (store, side, side),
            "kernel_source_hash": kernel_source_hash(),
            "fetch_kib_per_launch": sf, "write_kib_per_launch": sw, "launches": [nf, nw],
@@ -125,7 +125,7 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--side", type=int, default=4096)
-    ap.add_argument("--store", default="f32", choices=("f32", "f16dev", "f64"))
+    ap.add_argument("--store", default="f32", choices=("f32", "f16dev", "f16loc", "f64"))
     ap.add_argument("--cpu-steps", type=int, default=1000)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -184,7 +184,7 @@ def main():
 
     lups = N * N_C * args.steps
     mlups = lups / wall / 1e6
-    bytes_per_lu = 2 * 9 * g.STORE_BYTES[store] + 1
+    bytes_per_lu = g.bytes_per_update(9, store)
     per_launch = sweep_ms / max(launches, 1)
     achieved = bytes_per_lu * N / (per_launch * 1e-3) / 1e9
     traffic = traffic_from_profile(args.store, args.side)
@@ -199,7 +199,8 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"f32": "f32", "f16dev": "f32 math / f16 storage", "f64": "f64"}[args.store],
+        "dtype": {"f32": "f32", "f16dev": "f32 math / f16 storage", "f16loc": "f32 math / f16 storage",
+                  "f64": "f64"}[args.store],
         "data": "synthetic (seeded QSGS shale map, generated in-process)",
         "config": {"workload": "D2Q9 GLBM %dx%d, QSGS 60%% solid, TOC 0.10, CH4 400 K 10 MPa, %s "
                                "populations, n_c=%d sweeps + FP64 residual/flux per step"

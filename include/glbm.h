@@ -42,10 +42,16 @@ enum { GLBM_D2Q9 = 9, GLBM_D3Q19 = 19 };
 
 /* Population storage.  Arithmetic is FP64 for F64 and FP32 otherwise; the
  * residual and flux reductions are always accumulated in FP64.
- *   F64     f_i - w_i stored as double
- *   F32     f_i - w_i stored as float
- *   F16DEV  (f_i - w_i) * 2^s stored as IEEE half, rounded to nearest even */
-enum { GLBM_STORE_F64 = 0, GLBM_STORE_F32 = 1, GLBM_STORE_F16DEV = 2 };
+ *   F64     f_i - w_i stored as double                       (145 B per D2Q9 update)
+ *   F32     f_i - w_i stored as float                        (73 B)
+ *   F16DEV  (f_i - w_i) 2^s stored as IEEE half, rounded to nearest even (37 B).
+ *           The velocity part of f is then resolved only relative to the
+ *           density deviation: on the 128^2 shale map k is off by ~5%.
+ *   F16LOC  (f_i - w_i rho(x)) 2^s as IEEE half, with rho(x) - 1 of the node
+ *           x that wrote the value kept in an extra float plane (45 B).
+ *           Removing the node's own density leaves the velocity and
+ *           non-equilibrium parts at full half precision (k within ~1e-4). */
+enum { GLBM_STORE_F64 = 0, GLBM_STORE_F32 = 1, GLBM_STORE_F16DEV = 2, GLBM_STORE_F16LOC = 3 };
 
 enum {
     GLBM_OK = 0,

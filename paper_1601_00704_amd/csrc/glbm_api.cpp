@@ -38,6 +38,9 @@ int fail(int code, const char* fmt, ...)
     } while (0)
 
 size_t store_bytes(int store) { return store == GLBM_STORE_F64 ? 8 : (store == GLBM_STORE_F32 ? 4 : 2); }
+// planes per instance and buffer: q populations, plus a float density plane
+// (two half-width planes) for F16LOC
+int planes_of(const glbm_instance_desc& d) { return d.lattice + (d.store == GLBM_STORE_F16LOC ? 2 : 0); }
 size_t compute_bytes(int store) { return store == GLBM_STORE_F64 ? 8 : 4; }
 int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
 
@@ -53,10 +56,10 @@ int validate(int32_t n_inst, const glbm_instance_desc* d)
         const glbm_instance_desc& x = d[i];
         if (x.lattice != GLBM_D2Q9 && x.lattice != GLBM_D3Q19)
             return fail(GLBM_EINVAL, "instance %d: lattice must be 9 or 19", i);
-        if (x.store < 0 || x.store > 2) return fail(GLBM_EINVAL, "instance %d: bad store %d", i, x.store);
+        if (x.store < 0 || x.store > 3) return fail(GLBM_EINVAL, "instance %d: bad store %d", i, x.store);
         if (x.nx < 1 || x.ny < 1 || x.nz < 1) return fail(GLBM_EINVAL, "instance %d: empty grid", i);
         if (x.lattice == GLBM_D2Q9 && x.nz != 1) return fail(GLBM_EINVAL, "instance %d: D2Q9 needs nz = 1", i);
-        if ((int64_t)x.nx * x.ny * x.nz * x.lattice >= (int64_t)1 << 30)
+        if ((int64_t)x.nx * x.ny * x.nz * (x.lattice + 3) >= (int64_t)1 << 31)
             return fail(GLBM_EINVAL, "instance %d: grid too large for 32-bit plane indexing", i);
         if (!(x.tau > 0.5) || !std::isfinite(x.tau)) return fail(GLBM_EINVAL, "instance %d: tau must be > 1/2", i);
         for (int a = 0; a < 3; ++a)
@@ -67,7 +70,7 @@ int validate(int32_t n_inst, const glbm_instance_desc* d)
         for (int a = 0; a < 3; ++a)
             if (((x.wall_faces >> (2 * a)) & 1u) != ((x.wall_faces >> (2 * a + 1)) & 1u))
                 return fail(GLBM_EINVAL, "instance %d: wall faces must come in pairs per axis", i);
-        if (x.store == GLBM_STORE_F16DEV && x.dev_scale_log2 != GLBM_SCALE_AUTO &&
+        if ((x.store == GLBM_STORE_F16DEV || x.store == GLBM_STORE_F16LOC) && x.dev_scale_log2 != GLBM_SCALE_AUTO &&
             (x.dev_scale_log2 < 0 || x.dev_scale_log2 > 30))
             return fail(GLBM_EINVAL, "instance %d: dev_scale_log2 must be in [0, 30]", i);
         if (x.lattice != d[0].lattice || x.store != d[0].store || x.check_every != d[0].check_every)
@@ -90,17 +93,18 @@ Layout layout_of(int32_t n_inst, const glbm_instance_desc* d)
         const int64_t s = plane_stride(n);
         L.off.push_back(L.elems);
         L.stride.push_back(s);
-        L.elems += round_up(s * d[i].lattice, 256);
+        L.elems += round_up(s * planes_of(d[i]), 256);
     }
     return L;
 }
 
 int auto_scale(const glbm_instance_desc& d)
 {
-    // Deviations |f_i - w_i| of a slow body-force-driven flow stay far below
-    // 2^-5; 2^20 keeps everything above 2^-34 in the normal FP16 range.
-    (void)d;
-    return 20;
+    // F16DEV: deviations |f_i - w_i| of a slow body-force-driven flow stay far
+    // below 2^-5; 2^20 keeps everything above 2^-34 in the normal FP16 range.
+    // F16LOC: the stored part (velocity and non-equilibrium) is smaller still;
+    // 2^24 covers 4e-12 .. 4e-3.
+    return d.store == GLBM_STORE_F16LOC ? 24 : 20;
 }
 
 }  // namespace
@@ -434,9 +438,8 @@ int glbm_init_geometry(glbm_ctx* out, int32_t n_inst, const glbm_instance_desc* 
         I.omega = 1.0 / d.tau;
         I.cforce = 1.0 - 0.5 / d.tau;
         I.nu = (d.tau - 0.5) / 3.0;
-        const int s = d.store == GLBM_STORE_F16DEV ? (d.dev_scale_log2 == GLBM_SCALE_AUTO ? auto_scale(d)
-                                                                                         : d.dev_scale_log2)
-                                                   : 0;
+        const bool half = d.store == GLBM_STORE_F16DEV || d.store == GLBM_STORE_F16LOC;
+        const int s = half ? (d.dev_scale_log2 == GLBM_SCALE_AUTO ? auto_scale(d) : d.dev_scale_log2) : 0;
         I.scale = std::ldexp(1.0f, s);
         I.inv_scale = std::ldexp(1.0f, -s);
         c->inst_h.push_back(I);

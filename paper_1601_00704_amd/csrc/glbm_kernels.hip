@@ -56,24 +56,44 @@ template <> struct Lat<19> {
 
 // ----------------------------------------------------------------- storage --
 template <int STORE> struct St;
+// kRho: the stored value is relative to w_i rho(x) of the node that wrote it,
+// whose rho - 1 sits in a float plane after the q population planes.
 template <> struct St<GLBM_STORE_F64> {
+    static constexpr bool kRho = false;
     using S = double;
     using T = double;
     __device__ static T dec(S s, float) { return s; }
     __device__ static S enc(T d, float) { return d; }
 };
 template <> struct St<GLBM_STORE_F32> {
+    static constexpr bool kRho = false;
     using S = float;
     using T = float;
     __device__ static T dec(S s, float) { return s; }
     __device__ static S enc(T d, float) { return d; }
 };
 template <> struct St<GLBM_STORE_F16DEV> {
+    static constexpr bool kRho = false;
     using S = uint16_t;
     using T = float;
     __device__ static T dec(S s, float inv_scale) { return __half2float(__ushort_as_half(s)) * inv_scale; }
     __device__ static S enc(T d, float scale) { return __half_as_ushort(__float2half_rn(d * scale)); }
 };
+template <> struct St<GLBM_STORE_F16LOC> : St<GLBM_STORE_F16DEV> {
+    static constexpr bool kRho = true;
+};
+
+// The float plane of rho - 1 of a kRho buffer (after the q planes).
+template <int STORE>
+__device__ __forceinline__ const float* rho_plane(const typename St<STORE>::S* base, int q, int stride)
+{
+    return reinterpret_cast<const float*>(base + (size_t)q * stride);
+}
+template <int STORE>
+__device__ __forceinline__ float* rho_plane(typename St<STORE>::S* base, int q, int stride)
+{
+    return reinterpret_cast<float*>(base + (size_t)q * stride);
+}
 
 // Workgroups are dispatched round-robin over the 8 XCDs.  Map them so that
 // each XCD walks a contiguous range of tiles: x-neighbouring tiles share the
@@ -94,6 +114,7 @@ __device__ __forceinline__ void gather(typename St<STORE>::T (&d)[Q], const type
 {
     using L = Lat<Q>;
     using S = St<STORE>;
+    using T = typename S::T;
     const int nx = I.nx, ny = I.ny, nz = I.nz, stride = I.stride;
     const int xm = x == 0 ? nx - 1 : x - 1, xp = x == nx - 1 ? 0 : x + 1;
     const int ym = y == 0 ? ny - 1 : y - 1, yp = y == ny - 1 ? 0 : y + 1;
@@ -106,6 +127,7 @@ __device__ __forceinline__ void gather(typename St<STORE>::T (&d)[Q], const type
         const int sz = ez > 0 ? zm : (ez < 0 ? zp : z);
         const int sn = (sz * ny + sy) * nx + sx;
         int idx = i * stride + sn;
+        int node = sn;
         if (BC >= 1) {
             const uint32_t w = I.walls;
             bool blocked = false;
@@ -116,11 +138,15 @@ __device__ __forceinline__ void gather(typename St<STORE>::T (&d)[Q], const type
             if (ez > 0) blocked |= (z == 0) && (w & 16u);
             if (ez < 0) blocked |= (z == nz - 1) && (w & 32u);
             if (BC >= 2 && i != 0) blocked |= cls[sn] == kWallClass;
-            if (blocked) idx = L::opp(i) * stride + n;
+            if (blocked) {
+                idx = L::opp(i) * stride + n;
+                node = n;
+            }
         }
         // planes without an x shift are read by exactly one wavefront per cache line
         const typename S::S raw = (ex == 0 && nt_aligned) ? __builtin_nontemporal_load(src + idx) : src[idx];
         d[i] = S::dec(raw, I.inv_scale);
+        if (S::kRho) d[i] += T(L::w(i)) * rho_plane<STORE>(src, Q, stride)[node];
     }
 }
 
@@ -130,14 +156,23 @@ template <int Q, typename T, bool FORCH> struct Node {
     __device__ __forceinline__ void moments(const T (&d)[Q], const T* tab, const T g[3])
     {
         using L = Lat<Q>;
+        // Opposite populations share their density part w_i drho; summing the
+        // momentum as differences of opposite pairs cancels it exactly (each
+        // difference of two close values is exact in floating point) before
+        // anything is rounded.
         T j[3] = {0, 0, 0};
         drho = 0;
 #pragma unroll
-        for (int i = 0; i < Q; ++i) {
-            drho += d[i];
-            if (L::ex(i)) j[0] += L::ex(i) > 0 ? d[i] : -d[i];
-            if (L::ey(i)) j[1] += L::ey(i) > 0 ? d[i] : -d[i];
-            if (L::ez(i)) j[2] += L::ez(i) > 0 ? d[i] : -d[i];
+        for (int i = 0; i < Q; ++i) drho += d[i];
+#pragma unroll
+        for (int i = 1; i < Q; ++i) {
+            const int o = L::opp(i);
+            const bool lead = L::ex(i) > 0 || (L::ex(i) == 0 && (L::ey(i) > 0 || (L::ey(i) == 0 && L::ez(i) > 0)));
+            if (!lead) continue;
+            const T diff = d[i] - d[o];
+            if (L::ex(i)) j[0] += L::ex(i) > 0 ? diff : -diff;
+            if (L::ey(i)) j[1] += L::ey(i) > 0 ? diff : -diff;
+            if (L::ez(i)) j[2] += L::ez(i) > 0 ? diff : -diff;
         }
         rho = T(1) + drho;
         const T irho = T(1) / rho;
@@ -177,15 +212,22 @@ __device__ __forceinline__ void collide(T (&d)[Q], const Node<Q, T, FORCH>& s, c
     const T A = T(-1.5) * ieps * uu;
     const T B = T(-3) * ieps * uF;
     const T omw = T(1) - omega;
-    const T odr = omega * s.drho;
+    // Equilibrium and forcing parts of the moving directions; the rest direction
+    // takes what closes the zeroth moments (sum_i feq_i = rho, sum_i F_i = 0), so
+    // rounded weights cannot create or destroy mass.
+    T eq0 = s.drho, f0 = T(0);
 #pragma unroll
-    for (int i = 0; i < Q; ++i) {
+    for (int i = 1; i < Q; ++i) {
         const T eu = T(L::ex(i)) * s.u[0] + T(L::ey(i)) * s.u[1] + T(L::ez(i)) * s.u[2];
         const T eF = T(L::ex(i)) * s.F[0] + T(L::ey(i)) * s.F[1] + T(L::ez(i)) * s.F[2];
-        const T teq = T(3) * eu + T(4.5) * ieps * eu * eu + A;
-        const T tF = cforce * (T(3) * eF + T(9) * ieps * eu * eF + B);
-        d[i] = omw * d[i] + T(L::w(i)) * (odr + s.rho * (omega * teq + tF));
+        const T w = T(L::w(i));
+        const T deq = w * (s.drho + s.rho * (T(3) * eu + T(4.5) * ieps * eu * eu + A));
+        const T frc = w * s.rho * cforce * (T(3) * eF + T(9) * ieps * eu * eF + B);
+        eq0 -= deq;
+        f0 -= frc;
+        d[i] = omw * d[i] + omega * deq + frc;
     }
+    d[0] = omw * d[0] + omega * eq0 + f0;
 }
 
 template <int Q, typename T, bool FORCH>
@@ -234,6 +276,13 @@ __device__ __forceinline__ void sweep_slots(const Args& a, const Tile& t, const 
         const T* ct = tb + c[u] * tw;
         s.moments(d[u], ct, g);
         collide<Q, T, FORCH>(d[u], s, ct, omega, cforce);
+        if (SS::kRho) {
+            // collision conserves mass: the post-collision density is s.rho
+            const T dr = s.drho;
+            rho_plane<STORE>(dst, Q, I.stride)[n[u]] = dr;
+#pragma unroll
+            for (int i = 0; i < Q; ++i) d[u][i] -= T(Lat<Q>::w(i)) * dr;
+        }
         if (nt_store) {
 #pragma unroll
             for (int i = 0; i < Q; ++i)
@@ -455,6 +504,7 @@ __global__ __launch_bounds__(kBlock) void k_set_fields(Args a, int inst, const R
         if (c == kWallClass) continue;
         const T rho = T(rho_in[n]);
         const T u[3] = {T(u_in[n]), T(u_in[N + n]), T(u_in[2 * N + n])};
+        if (SS::kRho) rho_plane<STORE>(dst, Q, I.stride)[n] = T(rho_in[n] - R(1));
         const T ieps = tabg[c * kTabW + TAB_INV_EPS];
         const T uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
 #pragma unroll
@@ -476,7 +526,9 @@ __global__ __launch_bounds__(kBlock) void k_set_fields(Args a, int inst, const R
             const int sn = (sz * I.ny + sy) * I.nx + sx;
             if (BC >= 2 && !blocked && i != 0) blocked = cls[sn] == kWallClass;
             const int idx = blocked ? L::opp(i) * I.stride + n : i * I.stride + sn;
-            dst[idx] = SS::enc(dq, I.scale);
+            // a kRho value is decoded with the density of the node whose slot it occupies
+            const T dr = SS::kRho ? T(rho_in[blocked ? n : sn] - R(1)) : T(0);
+            dst[idx] = SS::enc(dq - T(L::w(i)) * dr, I.scale);
         }
     }
 }
@@ -560,7 +612,9 @@ hipError_t dispatch(const Config& c, A... args)
     if (c.q == QQ && c.store == SS && c.bc == BB && c.forch == FF) return K<QQ, SS, BB, FF>::go(args...);
 #define GLBM_F(QQ, SS, BB) GLBM_CASE(QQ, SS, BB, false) GLBM_CASE(QQ, SS, BB, true)
 #define GLBM_B(QQ, SS) GLBM_F(QQ, SS, 0) GLBM_F(QQ, SS, 1) GLBM_F(QQ, SS, 2)
-#define GLBM_S(QQ) GLBM_B(QQ, GLBM_STORE_F64) GLBM_B(QQ, GLBM_STORE_F32) GLBM_B(QQ, GLBM_STORE_F16DEV)
+#define GLBM_S(QQ)                                                                                 \
+    GLBM_B(QQ, GLBM_STORE_F64) GLBM_B(QQ, GLBM_STORE_F32) GLBM_B(QQ, GLBM_STORE_F16DEV)              \
+    GLBM_B(QQ, GLBM_STORE_F16LOC)
     GLBM_S(9)
     GLBM_S(19)
 #undef GLBM_S
@@ -619,7 +673,9 @@ hipError_t launch_set_fields(const Config& c, const Args& a, int inst, int ntile
                    : set_fields_go<QQ, SS, BB, float>(a, s, inst, ntiles, static_cast<const float*>(rho),   \
                                                       static_cast<const float*>(u));
 #define GLBM_SF_B(QQ, SS) GLBM_SF(QQ, SS, 0) GLBM_SF(QQ, SS, 1) GLBM_SF(QQ, SS, 2)
-#define GLBM_SF_S(QQ) GLBM_SF_B(QQ, GLBM_STORE_F64) GLBM_SF_B(QQ, GLBM_STORE_F32) GLBM_SF_B(QQ, GLBM_STORE_F16DEV)
+#define GLBM_SF_S(QQ)                                                                              \
+    GLBM_SF_B(QQ, GLBM_STORE_F64) GLBM_SF_B(QQ, GLBM_STORE_F32) GLBM_SF_B(QQ, GLBM_STORE_F16DEV)     \
+    GLBM_SF_B(QQ, GLBM_STORE_F16LOC)
     GLBM_SF_S(9)
     GLBM_SF_S(19)
 #undef GLBM_SF_S

@@ -1,0 +1,66 @@
+"""Write the stored oracle results the GPU tests compare against.
+
+Calls only the CPU oracle (oracle/) and the seeded input generators
+(shale_inputs/); nothing here touches the GPU path.  Run from the repository
+root:  python tests/golden/make_golden.py [case ...]
+"""
+import hashlib
+import json
+import os
+import sys
+import time
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
+
+import numpy as np  # noqa: E402
+
+import oracle  # noqa: E402
+from oracle import kapp  # noqa: E402
+import shale_inputs as si  # noqa: E402
+
+
+def map_sha(cls):
+    return hashlib.sha256(np.ascontiguousarray(cls).tobytes()).hexdigest()[:16]
+
+
+def solve_case(name, inst, cls, tol, max_steps, precision="ext"):
+    e, k, fe = kapp.class_table(inst)
+    prob = oracle.Problem(q=9 if len(cls.shape) == 2 else 19, cls=cls, eps=e, k=k, f_eps=fe, tau=inst.tau,
+                          G=inst.gvec(), walls=inst.wall_faces, precision=precision)
+    t0 = time.time()
+    sol = oracle.solve(prob, tol=tol, max_steps=max_steps, check_every=100)
+    dt = time.time() - t0
+    rng = np.random.default_rng(12345)
+    idx = np.sort(rng.choice(cls.size, size=32, replace=False))
+    rec = {
+        "case": name, "shape": list(cls.shape), "map_sha": map_sha(cls), "precision": precision,
+        "tol": tol, "check_every": 100, "steps": sol.steps, "residual": sol.residual,
+        "k_lattice": [None if not np.isfinite(v) else float(v) for v in sol.k],
+        "history": sol.history[::10] + [sol.history[-1]],
+        "sample_nodes": idx.tolist(),
+        "sample_u": sol.u[:, idx].T.tolist(), "sample_rho": sol.rho[idx].tolist(),
+        "oracle_seconds": round(dt, 1), "oracle_threads": oracle.num_threads(),
+    }
+    with open(os.path.join(HERE, name + ".json"), "w") as fh:
+        json.dump(rec, fh, indent=1)
+    print(name, "steps", sol.steps, "r", sol.residual, "k", sol.k, "%.1fs" % dt, flush=True)
+
+
+def case_cfg0():
+    inst = si.cfg0()
+    solve_case("cfg0_128_oracle", inst, inst.classes(), 1e-8, 400000)
+
+
+def case_crop():
+    inst = si.cfg1(4096)
+    cls = inst.classes()
+    crop = np.ascontiguousarray(cls[:512, :512])
+    solve_case("cfg1_crop512_oracle", inst, crop, 1e-8, 2000000, precision="f64")
+
+
+CASES = {"cfg0": case_cfg0, "crop": case_crop}
+
+if __name__ == "__main__":
+    for c in (sys.argv[1:] or ["cfg0"]):
+        CASES[c]()

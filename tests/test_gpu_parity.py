@@ -8,9 +8,10 @@ Tolerances, relative to the largest population deviation max|f - w| of the
 oracle state:
   F64 storage    1e-11  (FP64 arithmetic, different summation order)
   F32 storage    3e-5   (FP32 arithmetic: ~6e-8 per operation, a few hundred steps)
-  F16DEV storage 4e-3 vs the oracle that rounds every stored value through
-                 FP16 the same way (a rounding tie may break differently in
-                 FP32 than in FP64, a 2^-11 step that then diffuses)
+  F16DEV / F16LOC storage 4e-3 vs the oracle that rounds every stored value
+                 through FP16 the same way (a rounding tie may break
+                 differently in FP32 than in FP64, a 2^-11 step that then
+                 diffuses)
 """
 import numpy as np
 import pytest
@@ -21,20 +22,22 @@ from helpers import gpu_solver, oracle_order, oracle_problem, random_case
 
 pytestmark = pytest.mark.gpu
 
-TOL = {"f64": 1e-11, "f32": 3e-5, "f16dev": 4e-3}
+TOL = {"f64": 1e-11, "f32": 3e-5, "f16dev": 4e-3, "f16loc": 4e-3}
 
 
 def _compare(g, q, cls, eps, k, fe, store, steps, G, walls=0, tau=1.0, tile=None, cache=None, scale=20):
     print("case q=%d shape=%s store=%s steps=%d walls=%d tile=%s cache=%s" % (q, cls.shape, store, steps, walls,
                                                                              tile, cache), flush=True)
-    emul = {"f64": (0, 0), "f32": (0, 0), "f16dev": (2, scale)}[store]
+    if store == "f16loc" and scale == 20:
+        scale = 24
+    emul = {"f64": (0, 0), "f32": (0, 0), "f16dev": (2, scale), "f16loc": (3, scale)}[store]
     prob = oracle_problem(q, cls, eps, k, fe, tau=tau, G=G, walls=walls, store_mode=emul[0],
                           scale_log2=emul[1])
     f = prob.rest()
     prob.run(f, steps)
     rho_o, u_o = prob.fields(f)
     s = gpu_solver(g, q, cls, eps, k, fe, tau=tau, G=G, walls=walls, store=store, tile=tile, cache=cache,
-                   scale_log2=scale if store == "f16dev" else None)
+                   scale_log2=scale if store in ("f16dev", "f16loc") else None)
     try:
         s.step(steps)
         fg = s.populations()
@@ -54,18 +57,18 @@ def _compare(g, q, cls, eps, k, fe, store, steps, G, walls=0, tau=1.0, tile=None
     assert dev > 0
     assert err <= TOL[store] * dev
     assert uerr <= 10 * TOL[store]
-    if store != "f16dev":
+    if store not in ("f16dev", "f16loc"):
         assert np.abs(rho_g[fluid] - rho_o[fluid]).max() <= TOL[store] * dev * q
 
 
-@pytest.mark.parametrize("store", ["f64", "f32", "f16dev"])
+@pytest.mark.parametrize("store", ["f64", "f32", "f16dev", "f16loc"])
 @pytest.mark.parametrize("shape", [(48, 64), (37, 100)])
 def test_d2q9_periodic_fixed_steps(gpu, store, shape):
     cls, eps, k, fe = random_case(shape, seed=11 + shape[1])
     _compare(gpu, 9, cls, eps, k, None, store, 120, G=(2e-5, 7e-6, 0))
 
 
-@pytest.mark.parametrize("store", ["f64", "f32"])
+@pytest.mark.parametrize("store", ["f64", "f32", "f16loc"])
 def test_d2q9_walls_and_wall_nodes(gpu, store):
     cls, eps, k, fe = random_case((40, 70), seed=5, wall_frac=0.12)
     _compare(gpu, 9, cls, eps, k, None, store, 150, G=(3e-5, -1e-5, 0), walls=0b1100)
@@ -92,7 +95,7 @@ def test_d2q9_tau(gpu):
     _compare(gpu, 9, cls, eps, k, None, "f64", 100, G=(2e-5, 0, 0), tau=0.8)
 
 
-@pytest.mark.parametrize("store", ["f64", "f32", "f16dev"])
+@pytest.mark.parametrize("store", ["f64", "f32", "f16dev", "f16loc"])
 def test_d3q19_walls(gpu, store):
     cls, eps, k, fe = random_case((12, 20, 70), seed=31, wall_frac=0.05)
     _compare(gpu, 19, cls, eps, k, None, store, 60, G=(0, 0, 3e-5), walls=0b001111)
