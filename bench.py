@@ -119,7 +119,133 @@ def cpu_baseline(cls_crop, table, steps):
     return cls_crop.size * steps / dt / 1e6, dt, oracle.num_threads()
 
 
+def _json_line(metric_unit_value, steps, warmup, ms_per_step, dtype, config, roofline, extra=None):
+    out = {"metric": METRIC, "value": round(metric_unit_value, 1), "unit": "MLUPS", "n_gpus": 1,
+           "steps": steps, "warmup": warmup, "ms_per_step": round(ms_per_step, 3), "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": dtype,
+           "data": "synthetic (seeded QSGS shale maps, generated in-process)", "config": config,
+           "roofline": roofline}
+    if extra:
+        out.update(extra)
+    return out
+
+
+DTYPE = {"f32": "f32", "f16dev": "f32 math / f16 storage", "f16loc": "f32 math / f16 storage", "f64": "f64"}
+
+
+def _timed_chunks(s, g, steps, warmup, graph):
+    """Warm up, then time `steps` chunks of N_C sweeps + the FP64 check."""
+    import torch
+    s.set_option(g.GLBM_OPT_GRAPH, 1 if graph else 0)
+    s.set_option(g.GLBM_OPT_TIMING, 0 if graph else 1)
+    for _ in range(warmup):
+        s.step(N_C)
+    torch.cuda.synchronize()
+    s.set_option(g.GLBM_OPT_TIMING, 0 if graph else 1)  # resets the sweep timer
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        s.step(N_C)
+        print("step %d/%d done" % (k + 1, steps), file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0
+
+
+def _sweep_mean_ms(s, g, chunks=1):
+    """Mean sweep launch time from HIP events on the library stream (eager launches)."""
+    s.set_option(g.GLBM_OPT_GRAPH, 0)
+    s.set_option(g.GLBM_OPT_TIMING, 1)
+    for _ in range(chunks):
+        s.step(N_C)
+    ms, n = g.glbm_sweep_time(s.ctx)
+    s.set_option(g.GLBM_OPT_TIMING, 0)
+    return ms / max(n, 1), n
+
+
+def run_batch(args):
+    """Uneven batch: 256 instances, sides from {256..1024}, per-instance gas and
+    Langmuir parameters, one HIP graph per n_c-step chunk over all instances."""
+    import numpy as np
+    import shale_inputs as si
+    insts = si.cfg2_batch(args.batch)
+    t0 = time.perf_counter()
+    maps = si.batch_classes(insts)
+    t_geom = time.perf_counter() - t0
+    import torch
+    import paper_1601_00704_amd.glbm as g
+    torch.cuda.set_device(0)
+    store = g.STORE_NAMES[args.store]
+    descs = [g.make_desc(m.shape, store=store, tau=i.tau, g=i.gvec(), check_every=N_C) for i, m in zip(insts, maps)]
+    s = g.Solver(descs, maps)
+    for k, inst in enumerate(insts):
+        r_iom, r_om = inst.radii()
+        eps, kl = g.glbm_class_table(g.gas_params(inst), r_iom, r_om)
+        s.set_local_perm(eps[:255], kl[:255], inst=k)
+    N = int(sum(m.size for m in maps))
+    print("setup: %d instances, %d nodes, maps in %.1fs, store %s" % (len(maps), N, t_geom, args.store),
+          file=sys.stderr, flush=True)
+    wall = _timed_chunks(s, g, args.steps, args.warmup, graph=True)
+    per_launch, launches = _sweep_mean_ms(s, g)
+    r, st = s.residual()
+    s.close()
+    bpl = g.bytes_per_update(9, store)
+    achieved = bpl * N / (per_launch * 1e-3) / 1e9
+    sides = sorted(set(int(m.shape[0]) for m in maps))
+    cfg = {"workload": "batched D2Q9 GLBM: %d QSGS instances, sides %s, TOC U(0.05,0.30), P log-U(1,30) MPa, "
+                       "P_L U(2,8) MPa, V_L U(0.002,0.008) m3/kg; %s populations; one HIP graph per "
+                       "n_c=%d-sweep chunk + FP64 per-instance checks" % (len(maps), sides, args.store.upper(), N_C),
+           "instances": len(maps), "nodes": N, "sweeps_per_step": N_C, "graph": True,
+           "median_residual": float(np.median(r)), "steps_total": int(st.max())}
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+            "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None,
+            "kernel": "k_sweep<9,%s> over the flat tile list" % args.store, "bytes_per_lu": bpl,
+            "mean_launch_ms": round(per_launch, 5), "launches": launches}
+    return _json_line(N * N_C * args.steps / wall / 1e6, args.steps, args.warmup, wall / args.steps * 1e3,
+                      DTYPE[args.store], cfg, roof)
+
+
+def run_d3q19(args):
+    """256^3 D3Q19: 3-D QSGS (55% solid, TOC 0.20, 20 MPa), drive along z,
+    halfway bounce-back on the x and y faces."""
+    import shale_inputs as si
+    inst = si.cfg3(args.side3)
+    t0 = time.perf_counter()
+    cls = inst.classes()
+    t_geom = time.perf_counter() - t0
+    import torch
+    import paper_1601_00704_amd.glbm as g
+    torch.cuda.set_device(0)
+    store = g.STORE_NAMES[args.store]
+    r_iom, r_om = inst.radii()
+    eps, kl = g.glbm_class_table(g.gas_params(inst), r_iom, r_om)
+    d = g.make_desc(cls.shape, lattice=g.GLBM_D3Q19, store=store, tau=inst.tau, g=inst.gvec(),
+                    wall_faces=inst.wall_faces, check_every=N_C)
+    s = g.Solver([d], [cls])
+    s.set_local_perm(eps[:255], kl[:255])
+    N = cls.size
+    print("setup: %s map in %.1fs" % (cls.shape, t_geom), file=sys.stderr, flush=True)
+    wall = _timed_chunks(s, g, args.steps, args.warmup, graph=False)
+    ms, n = g.glbm_sweep_time(s.ctx)
+    per_launch = ms / max(n, 1)
+    r, st = s.residual()
+    kk = s.permeability()[0]
+    s.close()
+    bpl = g.bytes_per_update(19, store)
+    achieved = bpl * N / (per_launch * 1e-3) / 1e9
+    cfg = {"workload": "D3Q19 GLBM %d^3, 3-D QSGS 55%% solid, TOC 0.20, CH4 400 K 20 MPa, drive z, walls on x/y "
+                       "faces, %s populations" % (args.side3, args.store.upper()),
+           "nodes": N, "sweeps_per_step": N_C, "steps_total": int(st[0]), "residual": float(r[0]),
+           "k_lattice_z": float(kk[2])}
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+            "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None,
+            "kernel": "k_sweep<19,%s>" % args.store, "bytes_per_lu": bpl,
+            "mean_launch_ms": round(per_launch, 5), "launches": n}
+    return _json_line(N * N_C * args.steps / wall / 1e6, args.steps, args.warmup, wall / args.steps * 1e3,
+                      DTYPE[args.store], cfg, roof)
+
+
 def main():
+
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
@@ -128,6 +254,10 @@ def main():
     ap.add_argument("--store", default="f32", choices=("f32", "f16dev", "f16loc", "f64"))
     ap.add_argument("--cpu-steps", type=int, default=1000)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--workload", default="shale4096", choices=("shale4096", "batch", "d3q19"),
+                    help="shale4096: the benchmark line; batch / d3q19: supplementary workloads")
+    ap.add_argument("--batch", type=int, default=256)
+    ap.add_argument("--side3", type=int, default=256)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run only a plain 1 GiB elementwise copy (counter calibration)")
     ap.add_argument("--pmc-summary", nargs=4, metavar=("FETCH", "WRITE", "COPY_FETCH", "COPY_WRITE"),
@@ -138,6 +268,12 @@ def main():
         return
     if args.calibrate_copy:
         calibrate_copy()
+        return
+    if args.workload == "batch":
+        print(json.dumps(run_batch(args)), flush=True)
+        return
+    if args.workload == "d3q19":
+        print(json.dumps(run_d3q19(args)), flush=True)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the GLBM hot path here is built and timed on a single "

@@ -432,25 +432,40 @@ __global__ __launch_bounds__(kBlock) void k_observe(Args a, int mode, int all)
     }
 }
 
-// One workgroup per instance: sum its tile partials in a fixed order.
-__global__ __launch_bounds__(kBlock) void k_finalize(Args a, double tol, int with_r, int count_check, int all)
+// One 1024-thread workgroup per instance sums its tile partials: thread t adds
+// tiles t, t + 1024, ... (eight loads in flight), then a fixed-order tree over
+// the threads.  The order depends only on the tile count, so results are
+// deterministic and equal between a batch and a single-instance run.
+constexpr int kFinBlock = 1024;
+__global__ __launch_bounds__(kFinBlock) void k_finalize(Args a, double tol, int with_r, int count_check, int all)
 {
-    __shared__ double red[kBlock];
+    __shared__ double red[kFinBlock];
     const int inst = blockIdx.x;
     if (!all && !a.active[inst]) return;
     const InstDev& I = a.inst[inst];
     double acc[6] = {0, 0, 0, 0, 0, 0};
-    for (int t = threadIdx.x; t < I.ntiles; t += kBlock) {
-        const double* p = a.part + (size_t)(I.tile0 + t) * kPartW;
+    const double* base = a.part + (size_t)I.tile0 * kPartW;
+    int t = threadIdx.x;
+    for (; t + 7 * kFinBlock < I.ntiles; t += 8 * kFinBlock) {
+        double v[8][6];
 #pragma unroll
-        for (int k = 0; k < 6; ++k) acc[k] += p[k];
+        for (int u = 0; u < 8; ++u)
+#pragma unroll
+            for (int k = 0; k < 6; ++k) v[u][k] = base[(size_t)(t + u * kFinBlock) * kPartW + k];
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+#pragma unroll
+            for (int k = 0; k < 6; ++k) acc[k] += v[u][k];
     }
+    for (; t < I.ntiles; t += kFinBlock)
+#pragma unroll
+        for (int k = 0; k < 6; ++k) acc[k] += base[(size_t)t * kPartW + k];
     double out[6];
 #pragma unroll
     for (int k = 0; k < 6; ++k) {
         red[threadIdx.x] = acc[k];
         __syncthreads();
-        for (int s = kBlock / 2; s > 0; s >>= 1) {
+        for (int s = kFinBlock / 2; s > 0; s >>= 1) {
             if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
             __syncthreads();
         }
@@ -648,7 +663,7 @@ hipError_t launch_observe(const Config& c, const Args& a, int mode, hipStream_t 
 hipError_t launch_finalize(const Args& a, int n_inst, double tol, int with_r, int count_check, hipStream_t s)
 {
     const int all = with_r ? 0 : 1;
-    hipLaunchKernelGGL(k_finalize, dim3(n_inst), dim3(kBlock), 0, s, a, tol, with_r, count_check, all);
+    hipLaunchKernelGGL(k_finalize, dim3(n_inst), dim3(kFinBlock), 0, s, a, tol, with_r, count_check, all);
     return hipGetLastError();
 }
 

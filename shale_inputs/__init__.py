@@ -240,6 +240,28 @@ def cfg4_instance(seed: int, side: int = 512) -> Instance:
     return inst
 
 
+def _classes_of(inst: "Instance") -> np.ndarray:
+    return inst.classes()
+
+
+def batch_classes(instances: Sequence["Instance"], processes: Optional[int] = None):
+    """Class maps of many instances, generated in worker processes (fork).
+    Call before the process touches the GPU."""
+    import multiprocessing as mp
+    n = processes or min(16, os.cpu_count() or 1)
+    if n <= 1 or len(instances) < 2:
+        return [i.classes() for i in instances]
+    ctx = mp.get_context("fork")
+    with ctx.Pool(n) as pool:
+        return pool.map(_classes_of, list(instances), chunksize=1)
+
+
+def cfg2_batch(n: int = 256):
+    """The uneven batch: instances 0 .. n-1, largest first (longest-processing-time order)."""
+    insts = [cfg2_instance(k) for k in range(n)]
+    return sorted(insts, key=lambda i: -int(np.prod(i.shape)))
+
+
 def uniform_classes(shape: Sequence[int], cls: int = 1) -> np.ndarray:
     return np.full(tuple(shape), cls, dtype=np.uint8)
 
