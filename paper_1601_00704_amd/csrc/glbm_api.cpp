@@ -1,6 +1,7 @@
 // Host side of libglbm: contexts, the C ABI of include/glbm.h, chunked stepping
 // with HIP graph replay, checks and timing.
 #include "glbm.h"
+#include "glbm_cnn.h"
 #include "glbm_internal.h"
 
 #include <algorithm>
@@ -109,6 +110,8 @@ int auto_scale(const glbm_instance_desc& d)
 
 }  // namespace
 
+void glbm::set_error(const char* msg) { g_err = msg; }
+
 struct glbm_ctx_s {
     int n_inst = 0;
     Config cfg{};
@@ -122,6 +125,7 @@ struct glbm_ctx_s {
     std::vector<int64_t> n_fluid, steps, snap_step;
     std::vector<int32_t> active_h, dsteps_h, has_table;
     std::vector<std::vector<uint8_t>> cls_h;
+    std::vector<std::vector<double>> eps_h, k_h;  // per-instance class tables as given
     int64_t gstep = 0;
     bool snap_valid = false;
     // device memory
@@ -461,6 +465,8 @@ int glbm_init_geometry(glbm_ctx* out, int32_t n_inst, const glbm_instance_desc* 
     c->active_h.assign(n_inst, 1);
     c->dsteps_h.assign(n_inst, c->n_c);
     c->has_table.assign(n_inst, 0);
+    c->eps_h.assign(n_inst, std::vector<double>(kClasses, 1.0));
+    c->k_h.assign(n_inst, std::vector<double>(kClasses, INFINITY));
     c->snap_elems = snap_total;
 
     // population buffers
@@ -562,6 +568,10 @@ int glbm_set_local_perm(glbm_ctx c, int32_t inst, int32_t n_classes, const doubl
         }
         HIPCHK(hipStreamSynchronize(c->work));
         c->has_table[i] = 1;
+        for (int k = 0; k < n_classes; ++k) {
+            c->eps_h[i][k] = eps[k];
+            c->k_h[i][k] = k_lattice[k];
+        }
     }
     if (forch && !c->cfg.forch) {
         c->cfg.forch = true;
@@ -1011,6 +1021,84 @@ int glbm_destroy(glbm_ctx c)
     if (c->work) (void)hipStreamDestroy(c->work);
     delete c;
     return GLBM_OK;
+}
+
+int glbm_cnn_features(glbm_ctx c, int32_t inst, double log10_pressure_mpa, uint16_t* x)
+{
+    g_err.clear();
+    if (!c || !x) return fail(GLBM_EINVAL, "null argument");
+    if (inst < 0 || inst >= c->n_inst) return fail(GLBM_EINVAL, "instance %d out of range", inst);
+    int rc = check_tables(c);
+    if (rc) return rc;
+    std::vector<float> tab((size_t)kClasses * 8, 0.f);
+    for (int k = 0; k < kClasses; ++k) {
+        float* t = &tab[(size_t)k * 8];
+        const int phase = k == 0 ? 0 : (k < 128 ? 1 : (k < kWallClass ? 2 : -1));
+        if (phase >= 0) t[phase] = 1.f;
+        const double kk = c->k_h[inst][k];
+        t[3] = k == kWallClass ? 0.f : (float)c->eps_h[inst][k];
+        t[4] = k == kWallClass ? 0.f : (std::isfinite(kk) ? (float)std::log10(kk) : 3.f);
+        t[5] = (float)log10_pressure_mpa;
+    }
+    rc = enter(c);
+    if (rc) return rc;
+    float* d = nullptr;
+    HIPCHK(hipMalloc(&d, tab.size() * sizeof(float)));
+    const InstDev& I = c->inst_h[inst];
+    const long long n = (long long)I.nx * I.ny * I.nz;
+    hipError_t e = hipMemcpyAsync(d, tab.data(), tab.size() * sizeof(float), hipMemcpyHostToDevice, c->work);
+    if (e == hipSuccess) e = launch_cnn_features(c->cls_d + I.cls_off, n, d, x, c->work);
+    hipError_t es = hipStreamSynchronize(c->work);
+    (void)hipFree(d);
+    if (e != hipSuccess) return fail(GLBM_EDEVICE, "features: %s", hipGetErrorString(e));
+    HIPCHK(es);
+    return leave(c);
+}
+
+int glbm_cnn_targets(glbm_ctx c, int32_t inst, double rho_scale, double u_scale, float* target, uint8_t* mask)
+{
+    g_err.clear();
+    if (!c || !target || !mask) return fail(GLBM_EINVAL, "null argument");
+    if (inst < 0 || inst >= c->n_inst) return fail(GLBM_EINVAL, "instance %d out of range", inst);
+    if (!(rho_scale > 0) || !(u_scale > 0)) return fail(GLBM_EINVAL, "scales must be > 0");
+    int rc = check_tables(c);
+    if (rc) return rc;
+    rc = enter(c);
+    if (rc) return rc;
+    const InstDev& I = c->inst_h[inst];
+    const long long n = (long long)I.nx * I.ny * I.nz;
+    double* d = nullptr;
+    HIPCHK(hipMalloc(&d, (size_t)4 * n * sizeof(double)));
+    hipError_t e = launch_get_fields(c->cfg, c->args(c->gstep), inst, I.ntiles, d, d + n, nullptr, c->work);
+    if (e == hipSuccess)
+        e = launch_cnn_targets(d, d + n, c->cls_d + I.cls_off, n, rho_scale, u_scale, target, mask, c->work);
+    hipError_t es = hipStreamSynchronize(c->work);
+    (void)hipFree(d);
+    if (e != hipSuccess) return fail(GLBM_EDEVICE, "targets: %s", hipGetErrorString(e));
+    HIPCHK(es);
+    return leave(c);
+}
+
+int glbm_cnn_apply(glbm_ctx c, int32_t inst, const float* y, double rho_scale, double u_scale)
+{
+    g_err.clear();
+    if (!c || !y) return fail(GLBM_EINVAL, "null argument");
+    if (inst < 0 || inst >= c->n_inst) return fail(GLBM_EINVAL, "instance %d out of range", inst);
+    int rc = check_tables(c);
+    if (rc) return rc;
+    rc = enter(c);
+    if (rc) return rc;
+    const InstDev& I = c->inst_h[inst];
+    const long long n = (long long)I.nx * I.ny * I.nz;
+    float* d = nullptr;
+    HIPCHK(hipMalloc(&d, (size_t)4 * n * sizeof(float)));
+    hipError_t e = launch_cnn_apply(y, n, rho_scale, u_scale, d, d + n, c->work);
+    rc = e == hipSuccess ? set_fields_impl(c, inst, d, d + n, 0) : fail(GLBM_EDEVICE, "apply: %s", hipGetErrorString(e));
+    hipError_t es = hipStreamSynchronize(c->work);
+    (void)hipFree(d);
+    if (rc) return rc;
+    HIPCHK(es);
+    return leave(c);
 }
 
 int glbm_velocity_set(int32_t lattice, int32_t* e, double* w)

@@ -101,4 +101,13 @@ hipError_t launch_set_fields(const Config& c, const Args& a, int inst, int ntile
 hipError_t launch_get_fields(const Config& c, const Args& a, int inst, int ntiles, double* rho, double* u,
                              double* pops, hipStream_t s);
 
+// Warm-start coupling kernels (glbm_cnn.hip).
+hipError_t launch_cnn_features(const uint8_t* cls, long long n, const float* table, uint16_t* x, hipStream_t s);
+hipError_t launch_cnn_targets(const double* rho, const double* u, const uint8_t* cls, long long n, double rs,
+                              double us, float* target, uint8_t* mask, hipStream_t s);
+hipError_t launch_cnn_apply(const float* y, long long n, double rs, double us, float* rho, float* u, hipStream_t s);
+
+// Error message of the calling thread (glbm_api.cpp).
+void set_error(const char* msg);
+
 }  // namespace glbm

@@ -39,7 +39,12 @@ EXPORTS = ("glbm_required_bytes", "glbm_init_geometry", "glbm_set_local_perm", "
            "glbm_residual", "glbm_permeability", "glbm_set_fields", "glbm_set_fields_device",
            "glbm_get_fields", "glbm_get_populations", "glbm_state_bytes", "glbm_save_state",
            "glbm_load_state", "glbm_set_option", "glbm_sweep_time", "glbm_autotune",
-           "glbm_velocity_set", "glbm_destroy", "glbm_last_error", "glbm_class_table")
+           "glbm_velocity_set", "glbm_destroy", "glbm_last_error", "glbm_class_table",
+           "glbm_conv3x3_forward", "glbm_conv3x3_flip_weights", "glbm_conv3x3_wgrad_workspace",
+           "glbm_conv3x3_backward_weight", "glbm_cnn_create", "glbm_cnn_destroy", "glbm_cnn_num_params",
+           "glbm_cnn_get_params", "glbm_cnn_set_params", "glbm_cnn_get_grads", "glbm_cnn_forward",
+           "glbm_cnn_backward", "glbm_cnn_train_step", "glbm_cnn_features", "glbm_cnn_targets",
+           "glbm_cnn_apply")
 
 
 class GlbmError(RuntimeError):
@@ -88,6 +93,24 @@ def _load():
         "glbm_destroy": (i32, [vp]),
         "glbm_last_error": (ctypes.c_char_p, []),
         "glbm_class_table": (i32, [vp, i32, vp, i32, vp, vp, vp]),
+        "glbm_conv3x3_forward": (i32, [vp, i32, i32, i32, vp, vp, vp, i32, i32, i32, i32, i32, i32, i32, i32, i32,
+                                       vp]),
+        "glbm_conv3x3_flip_weights": (i32, [vp, i32, i32, vp, vp]),
+        "glbm_conv3x3_wgrad_workspace": (sz, [i32, i32, i32, i32, i32]),
+        "glbm_conv3x3_backward_weight": (i32, [vp, i32, i32, i32, vp, i32, i32, i32, vp, vp, vp, i32, i32, i32,
+                                               vp]),
+        "glbm_cnn_create": (i32, [vp, i32, i32, i32, ctypes.c_uint64, vp]),
+        "glbm_cnn_destroy": (i32, [vp]),
+        "glbm_cnn_num_params": (i64, [vp]),
+        "glbm_cnn_get_params": (i32, [vp, vp]),
+        "glbm_cnn_set_params": (i32, [vp, vp]),
+        "glbm_cnn_get_grads": (i32, [vp, vp]),
+        "glbm_cnn_forward": (i32, [vp, vp, vp, i32]),
+        "glbm_cnn_backward": (i32, [vp, vp, vp, vp, i32, vp]),
+        "glbm_cnn_train_step": (i32, [vp, vp, vp, vp, i32, ctypes.c_float, vp]),
+        "glbm_cnn_features": (i32, [vp, i32, f64, vp]),
+        "glbm_cnn_targets": (i32, [vp, i32, f64, f64, vp, vp]),
+        "glbm_cnn_apply": (i32, [vp, i32, vp, f64, f64]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -268,6 +291,104 @@ def gas_params(inst, molar_mass=0.016043) -> glbm_gas_params:
     p.langmuir_vl = inst.langmuir_vl if inst.langmuir_vl is not None else 0.0
     p.toc, p.d_s = inst.toc, inst.d_s
     return p
+
+
+# ------------------------------------------------------------ warm-start network
+def _stream():
+    return torch.cuda.current_stream().cuda_stream
+
+
+def glbm_conv3x3_forward(x, x_pitch, x_off, cin, w, bias, y, y_pitch, y_off, cout, relu, y_is_f32, accumulate,
+                         batch, height, width, stream=None):
+    """Device pointers (ints) in, see glbm_cnn.h."""
+    _check(_lib.glbm_conv3x3_forward(x, x_pitch, x_off, cin, w, bias, y, y_pitch, y_off, cout, int(relu),
+                                     int(y_is_f32), int(accumulate), batch, height, width,
+                                     _stream() if stream is None else stream))
+
+
+def glbm_conv3x3_flip_weights(w, cin, cout, wt, stream=None):
+    _check(_lib.glbm_conv3x3_flip_weights(w, cin, cout, wt, _stream() if stream is None else stream))
+
+
+def glbm_conv3x3_wgrad_workspace(cin, cout, batch, height, width) -> int:
+    return int(_lib.glbm_conv3x3_wgrad_workspace(cin, cout, batch, height, width))
+
+
+def glbm_conv3x3_backward_weight(x, x_pitch, x_off, cin, dy, dy_pitch, dy_off, cout, dw, db, workspace, batch,
+                                 height, width, stream=None):
+    _check(_lib.glbm_conv3x3_backward_weight(x, x_pitch, x_off, cin, dy, dy_pitch, dy_off, cout, dw, db, workspace,
+                                             batch, height, width, _stream() if stream is None else stream))
+
+
+def glbm_cnn_create(max_batch, height, width, seed=0, stream=None):
+    out = ctypes.c_void_p()
+    _check(_lib.glbm_cnn_create(ctypes.byref(out), max_batch, height, width, seed,
+                                _stream() if stream is None else stream))
+    return out.value
+
+
+def glbm_cnn_destroy(cnn):
+    _check(_lib.glbm_cnn_destroy(cnn))
+
+
+def glbm_cnn_num_params(cnn) -> int:
+    return int(_lib.glbm_cnn_num_params(cnn))
+
+
+def glbm_cnn_get_params(cnn) -> np.ndarray:
+    a = np.zeros(glbm_cnn_num_params(cnn), dtype=np.float32)
+    _check(_lib.glbm_cnn_get_params(cnn, _ptr(a)))
+    return a
+
+
+def glbm_cnn_set_params(cnn, params):
+    a = np.ascontiguousarray(params, dtype=np.float32)
+    _check(_lib.glbm_cnn_set_params(cnn, _ptr(a)))
+
+
+def glbm_cnn_get_grads(cnn) -> np.ndarray:
+    a = np.zeros(glbm_cnn_num_params(cnn), dtype=np.float32)
+    _check(_lib.glbm_cnn_get_grads(cnn, _ptr(a)))
+    return a
+
+
+def glbm_cnn_forward(cnn, x, y, batch):
+    _check(_lib.glbm_cnn_forward(cnn, x, y, batch))
+
+
+def glbm_cnn_backward(cnn, x, target, mask, batch) -> float:
+    loss = ctypes.c_double()
+    _check(_lib.glbm_cnn_backward(cnn, x, target, mask, batch, ctypes.byref(loss)))
+    return loss.value
+
+
+def glbm_cnn_train_step(cnn, x, target, mask, batch, lr) -> float:
+    loss = ctypes.c_double()
+    _check(_lib.glbm_cnn_train_step(cnn, x, target, mask, batch, float(lr), ctypes.byref(loss)))
+    return loss.value
+
+
+def glbm_cnn_features(ctx, inst, log10_pressure_mpa, x):
+    _check(_lib.glbm_cnn_features(ctx, inst, float(log10_pressure_mpa), x))
+
+
+def glbm_cnn_targets(ctx, inst, rho_scale, u_scale, target, mask):
+    _check(_lib.glbm_cnn_targets(ctx, inst, float(rho_scale), float(u_scale), target, mask))
+
+
+def glbm_cnn_apply(ctx, inst, y, rho_scale, u_scale):
+    _check(_lib.glbm_cnn_apply(ctx, inst, y, float(rho_scale), float(u_scale)))
+
+
+def to_bf16_bits(a: np.ndarray) -> np.ndarray:
+    """float array -> bfloat16 bit patterns (uint16), nearest even."""
+    u = np.ascontiguousarray(a, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) >> 16
+    return u.astype(np.uint16)
+
+
+def from_bf16_bits(b: np.ndarray) -> np.ndarray:
+    return (np.asarray(b, dtype=np.uint16).astype(np.uint32) << 16).view(np.float32)
 
 
 class Solver:

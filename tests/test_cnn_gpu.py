@@ -1,0 +1,213 @@
+"""BF16 MFMA convolution kernels and the warm-start network vs the FP64 oracle.
+
+Inputs are drawn in FP32, rounded to bfloat16 for the GPU, and the oracle
+gets the same rounded values in FP64.  FP32 outputs must agree to 1e-5 of the
+sum of absolute products (FP32 accumulation over at most 1728 terms); BF16
+outputs additionally to the bfloat16 step (2^-8 relative).  The network
+forward, loss and gradients are compared with the oracle emulating the same
+bfloat16 storage of activations.
+"""
+import numpy as np
+import pytest
+
+from oracle import cnn_ref as C
+
+pytestmark = pytest.mark.gpu
+
+
+def _dev(a, dtype):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).to(dtype=dtype, device="cuda")
+
+
+def _pack_w(w):
+    """oracle w [cout][cin][3][3] -> device bf16 [cout_pad][k_pad], k = tap * cin + ci."""
+    co, ci = w.shape[:2]
+    cp, kp = -(-co // 16) * 16, -(-(9 * ci) // 32) * 32
+    out = np.zeros((cp, kp), np.float32)
+    out[:co, :9 * ci] = w.transpose(0, 2, 3, 1).reshape(co, 9 * ci)
+    return out
+
+
+def _bf(a):
+    return C.round_bf16(a)
+
+
+def _u16(t):
+    import torch
+    return t.view(torch.int16) if t.dtype == torch.bfloat16 else t
+
+
+def _conv_case(g, B, H, W, cin, cout, x_pitch, x_off, y_pitch, y_off, relu, f32, acc, seed):
+    import torch
+    rng = np.random.default_rng(seed)
+    xfull = _bf(rng.standard_normal((B, H, W, x_pitch)))
+    w = _bf(rng.standard_normal((cout, cin, 3, 3)) / np.sqrt(9 * cin))
+    bias = rng.standard_normal(cout).astype(np.float32).astype(np.float64)
+    x = xfull[..., x_off:x_off + cin]
+    ref = C.conv3x3(x, w, bias)
+    if relu:
+        ref = np.maximum(ref, 0)
+    bound = C.conv3x3(np.abs(x), np.abs(w)) + np.abs(bias)
+    y0 = _bf(rng.standard_normal((B, H, W, y_pitch))) if acc else np.zeros((B, H, W, y_pitch))
+    if acc:
+        ref = ref + y0[..., y_off:y_off + cout]
+        bound = bound + np.abs(y0[..., y_off:y_off + cout])
+    xd = _dev(g.to_bf16_bits(xfull).view(np.int16), torch.int16)
+    wd = _dev(g.to_bf16_bits(_pack_w(w)).view(np.int16), torch.int16)
+    bd = _dev(bias, torch.float32)
+    if f32:
+        yd = _dev(y0, torch.float32)
+    else:
+        yd = _dev(g.to_bf16_bits(y0).view(np.int16), torch.int16)
+    g.glbm_conv3x3_forward(xd.data_ptr(), x_pitch, x_off, cin, wd.data_ptr(), bd.data_ptr(), yd.data_ptr(),
+                           y_pitch, y_off, cout, relu, f32, acc, B, H, W)
+    torch.cuda.synchronize()
+    if f32:
+        yg = yd.cpu().numpy().astype(np.float64)
+    else:
+        yg = g.from_bf16_bits(yd.cpu().numpy().view(np.uint16)).astype(np.float64)
+    got = yg[..., y_off:y_off + cout]
+    tol = 1e-5 * bound + (0 if f32 else 2.0 ** -8 * np.abs(ref))
+    err = np.abs(got - ref)
+    print("conv cin=%d cout=%d f32=%d max err/tol %.3f" % (cin, cout, f32, (err / (tol + 1e-30)).max()))
+    assert np.all(err <= tol + 1e-30)
+    # channels outside the slice are untouched
+    if not acc:
+        rest = np.delete(yg, np.s_[y_off:y_off + cout], axis=3)
+        assert np.all(rest == 0)
+
+
+@pytest.mark.parametrize("cin,cout", [(8, 32), (32, 3), (32, 64), (96, 32), (192, 64), (64, 128), (128, 128)])
+def test_conv_forward_f32(gpu, cin, cout):
+    _conv_case(gpu, 2, 5, 64, cin, cout, cin, 0, cout + 4, 4, relu=False, f32=True, acc=False, seed=cin + cout)
+
+
+@pytest.mark.parametrize("relu,acc", [(True, False), (False, True)])
+def test_conv_forward_bf16_slices(gpu, relu, acc):
+    # input is channels [32, 96) of a 192-wide buffer, output channels [64, 128) of a 192-wide one
+    _conv_case(gpu, 1, 4, 128, 64, 64, 192, 32, 192, 64, relu=relu, f32=False, acc=acc, seed=7)
+
+
+def test_conv_forward_full_tile_grid(gpu):
+    _conv_case(gpu, 2, 256, 256, 32, 32, 32, 0, 32, 0, relu=True, f32=False, acc=False, seed=9)
+
+
+@pytest.mark.parametrize("cin,cout", [(32, 3), (96, 32), (64, 128)])
+def test_conv_data_gradient(gpu, cin, cout):
+    import torch
+    g = gpu
+    rng = np.random.default_rng(cin * cout)
+    B, H, W = 2, 4, 64
+    cp = -(-cout // 16) * 16
+    w = _bf(rng.standard_normal((cout, cin, 3, 3)) / np.sqrt(9 * cin))
+    gy = np.zeros((B, H, W, cp))
+    gy[..., :cout] = _bf(rng.standard_normal((B, H, W, cout)))
+    ref = C.conv3x3_data_grad(gy[..., :cout], w)
+    bound = C.conv3x3_data_grad(np.abs(gy[..., :cout]), np.abs(w))
+    wd = _dev(g.to_bf16_bits(_pack_w(w)).view(np.int16), torch.int16)
+    rows, kp = -(-cin // 16) * 16, -(-(9 * cp) // 32) * 32
+    wt = torch.zeros(rows * kp, dtype=torch.int16, device="cuda")
+    g.glbm_conv3x3_flip_weights(wd.data_ptr(), cin, cout, wt.data_ptr())
+    gyd = _dev(g.to_bf16_bits(gy).view(np.int16), torch.int16)
+    gx = torch.zeros(B * H * W * cin, dtype=torch.float32, device="cuda")
+    g.glbm_conv3x3_forward(gyd.data_ptr(), cp, 0, cp, wt.data_ptr(), 0, gx.data_ptr(), cin, 0, cin, 0, 1, 0, B, H, W)
+    torch.cuda.synchronize()
+    got = gx.cpu().numpy().reshape(B, H, W, cin)
+    assert np.all(np.abs(got - ref) <= 1e-5 * bound + 1e-30)
+
+
+@pytest.mark.parametrize("cin,cout,B,H,W", [(8, 32, 2, 6, 64), (32, 3, 1, 40, 128), (192, 64, 1, 8, 64),
+                                             (128, 128, 2, 64, 64)])
+def test_conv_weight_gradient(gpu, cin, cout, B, H, W):
+    import torch
+    g = gpu
+    rng = np.random.default_rng(cin + 3 * cout)
+    x = _bf(rng.standard_normal((B, H, W, cin)))
+    gy = _bf(rng.standard_normal((B, H, W, cout)))
+    gw_ref, gb_ref = C.conv3x3_weight_grad(x, gy)
+    bw, bb = C.conv3x3_weight_grad(np.abs(x), np.abs(gy))
+    xd = _dev(g.to_bf16_bits(x).view(np.int16), torch.int16)
+    gyd = _dev(g.to_bf16_bits(gy).view(np.int16), torch.int16)
+    dw = torch.zeros(cout * 9 * cin, dtype=torch.float32, device="cuda")
+    db = torch.zeros(cout, dtype=torch.float32, device="cuda")
+    ws = torch.empty(g.glbm_conv3x3_wgrad_workspace(cin, cout, B, H, W), dtype=torch.uint8, device="cuda")
+    g.glbm_conv3x3_backward_weight(xd.data_ptr(), cin, 0, cin, gyd.data_ptr(), cout, 0, cout, dw.data_ptr(),
+                                   db.data_ptr(), ws.data_ptr(), B, H, W)
+    torch.cuda.synchronize()
+    got = dw.cpu().numpy().reshape(cout, 3, 3, cin).transpose(0, 3, 1, 2)
+    assert np.all(np.abs(got - gw_ref) <= 1e-5 * bw + 1e-30)
+    assert np.all(np.abs(db.cpu().numpy() - gb_ref) <= 1e-5 * bb + 1e-30)
+
+
+def _network_inputs(B, H, W, seed):
+    rng = np.random.default_rng(seed)
+    x = np.zeros((B, H, W, 8))
+    x[..., :6] = rng.standard_normal((B, H, W, 6))
+    x = _bf(x)
+    yy, xx = np.meshgrid(np.arange(H), np.arange(W), indexing="ij")
+    target = np.zeros((B, H, W, 4))
+    for b in range(B):
+        target[b, ..., 0] = np.sin(2 * np.pi * (xx + 7 * b) / W)
+        target[b, ..., 1] = np.cos(2 * np.pi * yy / H) * x[b, ..., 0]
+        target[b, ..., 2] = 0.5 * x[b, ..., 1]
+    mask = rng.random((B, H, W)) > 0.3
+    return x, target.astype(np.float32).astype(np.float64), mask
+
+
+def test_network_forward_and_gradients(gpu):
+    import torch
+    g = gpu
+    B, H, W = 2, 256, 256
+    cnn = g.glbm_cnn_create(B, H, W, seed=11)
+    try:
+        params = g.glbm_cnn_get_params(cnn).astype(np.float64)
+        x, target, mask = _network_inputs(B, H, W, 5)
+        xd = _dev(g.to_bf16_bits(x).view(np.int16), torch.int16)
+        td = _dev(target, torch.float32)
+        md = _dev(mask.astype(np.uint8), torch.uint8)
+        yd = torch.zeros(B * H * W * 4, dtype=torch.float32, device="cuda")
+        g.glbm_cnn_forward(cnn, xd.data_ptr(), yd.data_ptr(), B)
+        loss = g.glbm_cnn_backward(cnn, xd.data_ptr(), td.data_ptr(), md.data_ptr(), B)
+        grads = g.glbm_cnn_get_grads(cnn).astype(np.float64)
+        torch.cuda.synchronize()
+        out = yd.cpu().numpy().reshape(B, H, W, 4)[..., :3].astype(np.float64)
+    finally:
+        g.glbm_cnn_destroy(cnn)
+    # the parameters the GPU uses are their bf16 roundings
+    pq = params.copy()
+    o = 0
+    for ci, co, _ in C.SPEC:
+        pq[o:o + co * ci * 9] = _bf(params[o:o + co * ci * 9])
+        o += co * ci * 9 + co
+    lref, gref, oref = C.loss_and_grads(pq, x, target, mask, bf16=True)
+    fe = np.linalg.norm(out - oref) / np.linalg.norm(oref)
+    le = abs(loss - lref) / lref
+    ge = np.linalg.norm(grads - gref) / np.linalg.norm(gref)
+    print("network: forward rel L2 %.2e  loss rel %.2e  grad rel L2 %.2e" % (fe, le, ge))
+    assert fe < 5e-3 and le < 5e-3 and ge < 2e-2
+    # per layer
+    o = 0
+    for i, (ci, co, _) in enumerate(C.SPEC):
+        n = co * ci * 9 + co
+        e = np.linalg.norm(grads[o:o + n] - gref[o:o + n]) / np.linalg.norm(gref[o:o + n])
+        print("  layer %d grad rel L2 %.2e" % (i, e))
+        assert e < 3e-2
+        o += n
+
+
+def test_training_reduces_loss(gpu):
+    import torch
+    g = gpu
+    B, H, W = 2, 256, 256
+    cnn = g.glbm_cnn_create(B, H, W, seed=3)
+    try:
+        x, target, mask = _network_inputs(B, H, W, 8)
+        xd = _dev(g.to_bf16_bits(x).view(np.int16), torch.int16)
+        td = _dev(target, torch.float32)
+        md = _dev(mask.astype(np.uint8), torch.uint8)
+        losses = [g.glbm_cnn_train_step(cnn, xd.data_ptr(), td.data_ptr(), md.data_ptr(), B, 2e-3) for _ in range(60)]
+    finally:
+        g.glbm_cnn_destroy(cnn)
+    print("loss %.4f -> %.4f" % (losses[0], losses[-1]))
+    assert losses[-1] < 0.5 * losses[0]
