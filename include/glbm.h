@@ -50,8 +50,13 @@ enum { GLBM_D2Q9 = 9, GLBM_D3Q19 = 19 };
  *   F16LOC  (f_i - w_i rho(x)) 2^s as IEEE half, with rho(x) - 1 of the node
  *           x that wrote the value kept in an extra float plane (45 B).
  *           Removing the node's own density leaves the velocity and
- *           non-equilibrium parts at full half precision (k within ~1e-4). */
-enum { GLBM_STORE_F64 = 0, GLBM_STORE_F32 = 1, GLBM_STORE_F16DEV = 2, GLBM_STORE_F16LOC = 3 };
+ *           non-equilibrium parts at full half precision (k within ~1e-4).
+ *   F32LOC  (f_i - w_i rho(x)) as float with the same float density plane
+ *           (81 B): FP32 storage whose rounding no longer scales with the
+ *           density deviation, so the residual can fall further before
+ *           rounding noise stops it. */
+enum { GLBM_STORE_F64 = 0, GLBM_STORE_F32 = 1, GLBM_STORE_F16DEV = 2, GLBM_STORE_F16LOC = 3,
+       GLBM_STORE_F32LOC = 4 };
 
 enum {
     GLBM_OK = 0,

@@ -136,7 +136,8 @@ static double round_half(double x)
 
 /* mode 1: (f - w) through float; mode 2: (f - w) 2^s through float16;
  * mode 3: (f - w rho_x) 2^s through float16 with rho_x - 1 through float,
- * rho_x the density of the node the value leaves. */
+ * rho_x the density of the node the value leaves; mode 4: the same through
+ * float32. */
 static real store_round(real f, real w, int mode, int scale_log2, real rho_x)
 {
     if (mode == 1) return (real)(float)(f - w) + w;
@@ -148,6 +149,10 @@ static real store_round(real f, real w, int mode, int scale_log2, real rho_x)
         double s = ldexp(1.0, scale_log2);
         real r32 = 1 + (real)(float)(rho_x - 1);
         return (real)(round_half((double)((f - w * r32) * s)) / s) + w * r32;
+    }
+    if (mode == 4) {
+        real r32 = 1 + (real)(float)(rho_x - 1);
+        return (real)(float)(f - w * r32) + w * r32;
     }
     return f;
 }

@@ -38,10 +38,16 @@ int fail(int code, const char* fmt, ...)
                         __LINE__);                                                                \
     } while (0)
 
-size_t store_bytes(int store) { return store == GLBM_STORE_F64 ? 8 : (store == GLBM_STORE_F32 ? 4 : 2); }
+size_t store_bytes(int store)
+{
+    return store == GLBM_STORE_F64 ? 8 : ((store == GLBM_STORE_F32 || store == GLBM_STORE_F32LOC) ? 4 : 2);
+}
 // planes per instance and buffer: q populations, plus a float density plane
 // (two half-width planes) for F16LOC
-int planes_of(const glbm_instance_desc& d) { return d.lattice + (d.store == GLBM_STORE_F16LOC ? 2 : 0); }
+int planes_of(const glbm_instance_desc& d)
+{
+    return d.lattice + (d.store == GLBM_STORE_F16LOC ? 2 : (d.store == GLBM_STORE_F32LOC ? 1 : 0));
+}
 size_t compute_bytes(int store) { return store == GLBM_STORE_F64 ? 8 : 4; }
 int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
 
@@ -57,7 +63,7 @@ int validate(int32_t n_inst, const glbm_instance_desc* d)
         const glbm_instance_desc& x = d[i];
         if (x.lattice != GLBM_D2Q9 && x.lattice != GLBM_D3Q19)
             return fail(GLBM_EINVAL, "instance %d: lattice must be 9 or 19", i);
-        if (x.store < 0 || x.store > 3) return fail(GLBM_EINVAL, "instance %d: bad store %d", i, x.store);
+        if (x.store < 0 || x.store > 4) return fail(GLBM_EINVAL, "instance %d: bad store %d", i, x.store);
         if (x.nx < 1 || x.ny < 1 || x.nz < 1) return fail(GLBM_EINVAL, "instance %d: empty grid", i);
         if (x.lattice == GLBM_D2Q9 && x.nz != 1) return fail(GLBM_EINVAL, "instance %d: D2Q9 needs nz = 1", i);
         if ((int64_t)x.nx * x.ny * x.nz * (x.lattice + 3) >= (int64_t)1 << 31)

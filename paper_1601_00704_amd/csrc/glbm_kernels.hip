@@ -82,6 +82,9 @@ template <> struct St<GLBM_STORE_F16DEV> {
 template <> struct St<GLBM_STORE_F16LOC> : St<GLBM_STORE_F16DEV> {
     static constexpr bool kRho = true;
 };
+template <> struct St<GLBM_STORE_F32LOC> : St<GLBM_STORE_F32> {
+    static constexpr bool kRho = true;
+};
 
 // The float plane of rho - 1 of a kRho buffer (after the q planes).
 template <int STORE>
@@ -107,8 +110,12 @@ __device__ __forceinline__ int xcd_tile(int bid, int G)
 template <typename T> __device__ __forceinline__ bool finite(T v) { return isfinite(v); }
 
 // Pull the q post-collision values that stream into node (x, y, z).
+// For a kRho store, d[i] receives the stored part (f_i - w_i rho_s) and r[i]
+// the density deviation rho_s - 1 of the source node s; otherwise d[i] is the
+// full deviation f_i - w_i and r is not touched.
 template <int Q, int STORE, int BC>
-__device__ __forceinline__ void gather(typename St<STORE>::T (&d)[Q], const typename St<STORE>::S* __restrict__ src,
+__device__ __forceinline__ void gather(typename St<STORE>::T (&d)[Q], typename St<STORE>::T (&r)[Q],
+                                       const typename St<STORE>::S* __restrict__ src,
                                        const uint8_t* __restrict__ cls, const InstDev& I, int x, int y, int z,
                                        int n, bool nt_aligned = false)
 {
@@ -146,8 +153,27 @@ __device__ __forceinline__ void gather(typename St<STORE>::T (&d)[Q], const type
         // planes without an x shift are read by exactly one wavefront per cache line
         const typename S::S raw = (ex == 0 && nt_aligned) ? __builtin_nontemporal_load(src + idx) : src[idx];
         d[i] = S::dec(raw, I.inv_scale);
-        if (S::kRho) d[i] += T(L::w(i)) * rho_plane<STORE>(src, Q, stride)[node];
+        if constexpr (S::kRho) r[i] = rho_plane<STORE>(src, Q, stride)[node];
     }
+}
+
+// Local form of a kRho node: drho = sum_i (w_i r_i + d_i), and d becomes
+// e_i = f_i - w_i rho(x) = d_i + w_i (r_i - drho): only differences of
+// neighbouring densities are formed, never the full density part.
+template <int Q, typename T>
+__device__ __forceinline__ T localize(T (&d)[Q], const T (&r)[Q])
+{
+    using L = Lat<Q>;
+    T a = 0, b = 0;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        a += T(L::w(i)) * r[i];
+        b += d[i];
+    }
+    const T drho = a + b;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) d[i] += T(L::w(i)) * (r[i] - drho);
+    return drho;
 }
 
 // Moments and force of one node: Eq. (32)-(35) and (27)-(28) on deviations.
@@ -155,15 +181,21 @@ template <int Q, typename T, bool FORCH> struct Node {
     T drho, rho, u[3], F[3];
     __device__ __forceinline__ void moments(const T (&d)[Q], const T* tab, const T g[3])
     {
+        T dr = 0;
+#pragma unroll
+        for (int i = 0; i < Q; ++i) dr += d[i];
+        moments_with(d, dr, tab, g);
+    }
+    // d: deviations (or local parts e_i, whose momentum is the same), dr: rho - 1
+    __device__ __forceinline__ void moments_with(const T (&d)[Q], T dr, const T* tab, const T g[3])
+    {
         using L = Lat<Q>;
         // Opposite populations share their density part w_i drho; summing the
         // momentum as differences of opposite pairs cancels it exactly (each
         // difference of two close values is exact in floating point) before
         // anything is rounded.
         T j[3] = {0, 0, 0};
-        drho = 0;
-#pragma unroll
-        for (int i = 0; i < Q; ++i) drho += d[i];
+        drho = dr;
 #pragma unroll
         for (int i = 1; i < Q; ++i) {
             const int o = L::opp(i);
@@ -230,6 +262,46 @@ __device__ __forceinline__ void collide(T (&d)[Q], const Node<Q, T, FORCH>& s, c
     d[0] = omw * d[0] + omega * eq0 + f0;
 }
 
+// 1 - sum of the weights as rounded to T (exactly representable: a sum of a
+// few floats computed in double).
+template <int Q, typename T> __device__ __forceinline__ T weight_defect()
+{
+    double sw = 0.0;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) sw += double(T(Lat<Q>::w(i)));
+    return T(1.0 - sw);
+}
+
+// The same relaxation on local parts e_i = f_i - w_i rho(x) (kRho stores):
+// e*_i = (1 - omega) e_i + omega w_i rho teq_i + F_i; the rest direction
+// closes the zeroth moments as in collide() and also takes drho (1 - sum w),
+// so that the values leaving the node, w_i drho + e*_i with the rounded
+// weights, carry exactly its mass.
+template <int Q, typename T, bool FORCH>
+__device__ __forceinline__ void collide_local(T (&e)[Q], const Node<Q, T, FORCH>& s, const T* tab, T omega, T cforce)
+{
+    using L = Lat<Q>;
+    const T ieps = tab[TAB_INV_EPS];
+    const T uu = s.u[0] * s.u[0] + s.u[1] * s.u[1] + s.u[2] * s.u[2];
+    const T uF = s.u[0] * s.F[0] + s.u[1] * s.F[1] + s.u[2] * s.F[2];
+    const T A = T(-1.5) * ieps * uu;
+    const T B = T(-3) * ieps * uF;
+    const T omw = T(1) - omega;
+    T eq0 = T(0), f0 = T(0);
+#pragma unroll
+    for (int i = 1; i < Q; ++i) {
+        const T eu = T(L::ex(i)) * s.u[0] + T(L::ey(i)) * s.u[1] + T(L::ez(i)) * s.u[2];
+        const T eF = T(L::ex(i)) * s.F[0] + T(L::ey(i)) * s.F[1] + T(L::ez(i)) * s.F[2];
+        const T w = T(L::w(i));
+        const T deq = w * s.rho * (T(3) * eu + T(4.5) * ieps * eu * eu + A);
+        const T frc = w * s.rho * cforce * (T(3) * eF + T(9) * ieps * eu * eF + B);
+        eq0 -= deq;
+        f0 -= frc;
+        e[i] = omw * e[i] + omega * deq + frc;
+    }
+    e[0] = omw * e[0] + omega * eq0 + f0 + weight_defect<Q, T>() * s.drho;
+}
+
 template <int Q, typename T, bool FORCH>
 __device__ __forceinline__ void load_table(T* lds, const Args& a, int inst)
 {
@@ -257,7 +329,7 @@ __device__ __forceinline__ void sweep_slots(const Args& a, const Tile& t, const 
     const int z = t.z0;
     int n[U], c[U];
     bool ok[U];
-    T d[U][Q];
+    T d[U][Q], r[U][Q];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
         const int slot = (sl0 + u) * kBlock + threadIdx.x;
@@ -267,21 +339,23 @@ __device__ __forceinline__ void sweep_slots(const Args& a, const Tile& t, const 
         n[u] = ok[u] ? (z * I.ny + y) * I.nx + x : 0;
         c[u] = ok[u] ? cls[n[u]] : 0;
         if (BC >= 2 && c[u] == kWallClass) ok[u] = false;
-        if (ok[u]) gather<Q, STORE, BC>(d[u], src, cls, I, x, y, z, n[u], nt_load);
+        if (ok[u]) gather<Q, STORE, BC>(d[u], r[u], src, cls, I, x, y, z, n[u], nt_load);
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
         if (!ok[u]) continue;
         Node<Q, T, FORCH> s;
         const T* ct = tb + c[u] * tw;
-        s.moments(d[u], ct, g);
-        collide<Q, T, FORCH>(d[u], s, ct, omega, cforce);
-        if (SS::kRho) {
-            // collision conserves mass: the post-collision density is s.rho
-            const T dr = s.drho;
+        if constexpr (SS::kRho) {
+            // local form; collision conserves mass, so the node writes its
+            // density and the parts relative to it
+            const T dr = localize<Q, T>(d[u], r[u]);
+            s.moments_with(d[u], dr, ct, g);
+            collide_local<Q, T, FORCH>(d[u], s, ct, omega, cforce);
             rho_plane<STORE>(dst, Q, I.stride)[n[u]] = dr;
-#pragma unroll
-            for (int i = 0; i < Q; ++i) d[u][i] -= T(Lat<Q>::w(i)) * dr;
+        } else {
+            s.moments(d[u], ct, g);
+            collide<Q, T, FORCH>(d[u], s, ct, omega, cforce);
         }
         if (nt_store) {
 #pragma unroll
@@ -381,10 +455,15 @@ __device__ __forceinline__ void observe_tile(const Args& a, const Tile& t, const
         const int n = (z * I.ny + y) * I.nx + x;
         const int c = cls[n];
         if (BC >= 2 && c == kWallClass) continue;
-        T d[Q];
-        gather<Q, STORE, BC>(d, src, cls, I, x, y, z, n);
+        T d[Q], rr[Q];
+        gather<Q, STORE, BC>(d, rr, src, cls, I, x, y, z, n);
         Node<Q, T, FORCH> s;
-        s.moments(d, tb + c * tw, g);
+        if constexpr (SS::kRho) {
+            const T dr = localize<Q, T>(d, rr);
+            s.moments_with(d, dr, tb + c * tw, g);
+        } else {
+            s.moments(d, tb + c * tw, g);
+        }
         if (mode & 2) {
 #pragma unroll
             for (int k = 0; k < 3; ++k) {
@@ -580,13 +659,20 @@ __global__ __launch_bounds__(kBlock) void k_get_fields(Args a, int inst, double*
                 for (int i = 0; i < Q; ++i) pops[(size_t)i * N + n] = 0.0;
             continue;
         }
-        T d[Q];
-        gather<Q, STORE, BC>(d, src, cls, I, x, y, z, n);
+        T d[Q], rr[Q];
+        gather<Q, STORE, BC>(d, rr, src, cls, I, x, y, z, n);
         T ct[kTabW];
 #pragma unroll
         for (int k = 0; k < kTabW; ++k) ct[k] = tabg[c * kTabW + k];
         Node<Q, T, FORCH> s;
-        s.moments(d, ct, g);
+        if constexpr (SS::kRho) {
+            const T dr = localize<Q, T>(d, rr);
+            s.moments_with(d, dr, ct, g);
+#pragma unroll
+            for (int i = 0; i < Q; ++i) d[i] += T(L::w(i)) * dr;  // back to f_i - w_i for the readback
+        } else {
+            s.moments(d, ct, g);
+        }
         if (rho_out) rho_out[n] = 1.0 + double(s.drho);
         if (u_out)
             for (int k = 0; k < 3; ++k) u_out[k * N + n] = double(s.u[k]);
@@ -629,7 +715,7 @@ hipError_t dispatch(const Config& c, A... args)
 #define GLBM_B(QQ, SS) GLBM_F(QQ, SS, 0) GLBM_F(QQ, SS, 1) GLBM_F(QQ, SS, 2)
 #define GLBM_S(QQ)                                                                                 \
     GLBM_B(QQ, GLBM_STORE_F64) GLBM_B(QQ, GLBM_STORE_F32) GLBM_B(QQ, GLBM_STORE_F16DEV)              \
-    GLBM_B(QQ, GLBM_STORE_F16LOC)
+    GLBM_B(QQ, GLBM_STORE_F16LOC) GLBM_B(QQ, GLBM_STORE_F32LOC)
     GLBM_S(9)
     GLBM_S(19)
 #undef GLBM_S
@@ -690,7 +776,7 @@ hipError_t launch_set_fields(const Config& c, const Args& a, int inst, int ntile
 #define GLBM_SF_B(QQ, SS) GLBM_SF(QQ, SS, 0) GLBM_SF(QQ, SS, 1) GLBM_SF(QQ, SS, 2)
 #define GLBM_SF_S(QQ)                                                                              \
     GLBM_SF_B(QQ, GLBM_STORE_F64) GLBM_SF_B(QQ, GLBM_STORE_F32) GLBM_SF_B(QQ, GLBM_STORE_F16DEV)     \
-    GLBM_SF_B(QQ, GLBM_STORE_F16LOC)
+    GLBM_SF_B(QQ, GLBM_STORE_F16LOC) GLBM_SF_B(QQ, GLBM_STORE_F32LOC)
     GLBM_SF_S(9)
     GLBM_SF_S(19)
 #undef GLBM_SF_S

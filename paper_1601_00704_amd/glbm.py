@@ -19,21 +19,22 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "lib", "libglbm.so")
 
 GLBM_D2Q9, GLBM_D3Q19 = 9, 19
-GLBM_STORE_F64, GLBM_STORE_F32, GLBM_STORE_F16DEV, GLBM_STORE_F16LOC = 0, 1, 2, 3
+GLBM_STORE_F64, GLBM_STORE_F32, GLBM_STORE_F16DEV, GLBM_STORE_F16LOC, GLBM_STORE_F32LOC = 0, 1, 2, 3, 4
 GLBM_OK, GLBM_EINVAL, GLBM_ENOMEM, GLBM_EDEVICE, GLBM_ESTATE, GLBM_ENONFINITE, GLBM_ENOTCONVERGED = \
     0, -1, -2, -3, -4, -5, -6
 GLBM_WALL_CLASS = 255
 GLBM_SCALE_AUTO = -2147483648
 GLBM_OPT_GRAPH, GLBM_OPT_TIMING, GLBM_OPT_TILE_ROWS, GLBM_OPT_TILE_WIDTH, GLBM_OPT_CACHE = 1, 2, 3, 4, 5
 STORE_NAMES = {"f64": GLBM_STORE_F64, "f32": GLBM_STORE_F32, "f16dev": GLBM_STORE_F16DEV,
-               "f16loc": GLBM_STORE_F16LOC}
-STORE_BYTES = {GLBM_STORE_F64: 8, GLBM_STORE_F32: 4, GLBM_STORE_F16DEV: 2, GLBM_STORE_F16LOC: 2}
+               "f16loc": GLBM_STORE_F16LOC, "f32loc": GLBM_STORE_F32LOC}
+STORE_BYTES = {GLBM_STORE_F64: 8, GLBM_STORE_F32: 4, GLBM_STORE_F16DEV: 2, GLBM_STORE_F16LOC: 2,
+               GLBM_STORE_F32LOC: 4}
 
 
 def bytes_per_update(q: int, store: int) -> int:
     """Algorithmic HBM bytes of one lattice update: read and write q populations
-    and the class byte (F16LOC adds the float density: 4 B written, 4 B read)."""
-    return 2 * q * STORE_BYTES[store] + 1 + (8 if store == GLBM_STORE_F16LOC else 0)
+    and the class byte (F16LOC / F32LOC add the float density: 4 B written, 4 B read)."""
+    return 2 * q * STORE_BYTES[store] + 1 + (8 if store in (GLBM_STORE_F16LOC, GLBM_STORE_F32LOC) else 0)
 
 EXPORTS = ("glbm_required_bytes", "glbm_init_geometry", "glbm_set_local_perm", "glbm_step_n",
            "glbm_residual", "glbm_permeability", "glbm_set_fields", "glbm_set_fields_device",

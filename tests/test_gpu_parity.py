@@ -22,7 +22,7 @@ from helpers import gpu_solver, oracle_order, oracle_problem, random_case
 
 pytestmark = pytest.mark.gpu
 
-TOL = {"f64": 1e-11, "f32": 3e-5, "f16dev": 4e-3, "f16loc": 4e-3}
+TOL = {"f64": 1e-11, "f32": 3e-5, "f16dev": 4e-3, "f16loc": 4e-3, "f32loc": 3e-5}
 
 
 def _compare(g, q, cls, eps, k, fe, store, steps, G, walls=0, tau=1.0, tile=None, cache=None, scale=20):
@@ -30,7 +30,7 @@ def _compare(g, q, cls, eps, k, fe, store, steps, G, walls=0, tau=1.0, tile=None
                                                                              tile, cache), flush=True)
     if store == "f16loc" and scale == 20:
         scale = 24
-    emul = {"f64": (0, 0), "f32": (0, 0), "f16dev": (2, scale), "f16loc": (3, scale)}[store]
+    emul = {"f64": (0, 0), "f32": (0, 0), "f16dev": (2, scale), "f16loc": (3, scale), "f32loc": (4, 0)}[store]
     prob = oracle_problem(q, cls, eps, k, fe, tau=tau, G=G, walls=walls, store_mode=emul[0],
                           scale_log2=emul[1])
     f = prob.rest()
@@ -57,18 +57,18 @@ def _compare(g, q, cls, eps, k, fe, store, steps, G, walls=0, tau=1.0, tile=None
     assert dev > 0
     assert err <= TOL[store] * dev
     assert uerr <= 10 * TOL[store]
-    if store not in ("f16dev", "f16loc"):
+    if store not in ("f16dev", "f16loc", "f32loc"):
         assert np.abs(rho_g[fluid] - rho_o[fluid]).max() <= TOL[store] * dev * q
 
 
-@pytest.mark.parametrize("store", ["f64", "f32", "f16dev", "f16loc"])
+@pytest.mark.parametrize("store", ["f64", "f32", "f16dev", "f16loc", "f32loc"])
 @pytest.mark.parametrize("shape", [(48, 64), (37, 100)])
 def test_d2q9_periodic_fixed_steps(gpu, store, shape):
     cls, eps, k, fe = random_case(shape, seed=11 + shape[1])
     _compare(gpu, 9, cls, eps, k, None, store, 120, G=(2e-5, 7e-6, 0))
 
 
-@pytest.mark.parametrize("store", ["f64", "f32", "f16loc"])
+@pytest.mark.parametrize("store", ["f64", "f32", "f16loc", "f32loc"])
 def test_d2q9_walls_and_wall_nodes(gpu, store):
     cls, eps, k, fe = random_case((40, 70), seed=5, wall_frac=0.12)
     _compare(gpu, 9, cls, eps, k, None, store, 150, G=(3e-5, -1e-5, 0), walls=0b1100)
@@ -95,7 +95,7 @@ def test_d2q9_tau(gpu):
     _compare(gpu, 9, cls, eps, k, None, "f64", 100, G=(2e-5, 0, 0), tau=0.8)
 
 
-@pytest.mark.parametrize("store", ["f64", "f32", "f16dev", "f16loc"])
+@pytest.mark.parametrize("store", ["f64", "f32", "f16dev", "f16loc", "f32loc"])
 def test_d3q19_walls(gpu, store):
     cls, eps, k, fe = random_case((12, 20, 70), seed=31, wall_frac=0.05)
     _compare(gpu, 19, cls, eps, k, None, store, 60, G=(0, 0, 3e-5), walls=0b001111)

@@ -42,7 +42,7 @@ def _cfg0_solver(g, store):
     return s, ref
 
 
-@pytest.mark.parametrize("store,tol", [("f64", 1e-11), ("f32", 1e-5), ("f16loc", 1e-3)])
+@pytest.mark.parametrize("store,tol", [("f64", 1e-11), ("f32", 1e-5), ("f32loc", 1e-5), ("f16loc", 1e-3)])
 def test_cfg0_permeability_matches_oracle(gpu, store, tol):
     """k after the oracle's converged step count (r <= 1e-8) matches the oracle."""
     s, ref = _cfg0_solver(gpu, store)
