@@ -24,6 +24,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -40,10 +42,21 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def traffic_from_profile(store: str, side: int):
+def workload_key(args):
+    """(profile key, lattice Q, nodes) of the workload the arguments select."""
+    if args.workload == "batch":
+        import shale_inputs as si
+        nodes = sum(int(np.prod(i.shape)) for i in si.cfg2_batch(args.batch))
+        return "sweep_batch%d_d2q9_%s" % (args.batch, args.store), 9, nodes
+    if args.workload == "d3q19":
+        return "sweep_d3q19_%s_%d" % (args.store, args.side3), 19, args.side3 ** 3
+    return "sweep_d2q9_%s_%d" % (args.store, args.side), 9, args.side * args.side
+
+
+def traffic_from_profile(key):
     """HBM bytes per sweep launch from a committed rocprofv3 counter summary, if it
     was taken on the current kernel source; else None."""
-    path = os.path.join(ROOT, "profiles", "sweep_d2q9_%s_%d_traffic.json" % (store, side))
+    path = os.path.join(ROOT, "profiles", "%s_traffic.json" % key)
     if not os.path.exists(path):
         return None
     with open(path) as fh:
@@ -75,7 +88,7 @@ def _pmc_per_kernel(path):
     return out
 
 
-def pmc_summary(fetch_dir, write_dir, cfetch_dir, cwrite_dir, store, side):
+def pmc_summary(fetch_dir, write_dir, cfetch_dir, cwrite_dir, args):
     """Turn four rocprofv3 --pmc runs (FETCH_SIZE / WRITE_SIZE of the bench and of
     calibrate_copy) into HBM bytes per sweep launch.  Counters are KiB per
     dispatch; each is scaled by (known copy bytes) / (counter on the copy)."""
@@ -91,9 +104,10 @@ def pmc_summary(fetch_dir, write_dir, cfetch_dir, cwrite_dir, store, side):
     sw, nw = pick(_pmc_per_kernel(write_dir), "k_sweep")
     read = sf * 1024.0 * f_scale
     write = sw * 1024.0 * w_scale
-    n = side * side
-    bpl = {"f32": 73, "f16dev": 37, "f16loc": 45, "f64": 145}[store]
-    rec = {"kernel": "k_sweep<9,%s> on %dx%d" % (store, side, side),
+    import paper_1601_00704_amd.glbm as g
+    key, q, n = workload_key(args)
+    bpl = g.bytes_per_update(q, g.STORE_NAMES[args.store])
+    rec = {"kernel": "k_sweep<%d,%s>, %s, %d nodes" % (q, args.store, args.workload, n),
            "kernel_source_hash": kernel_source_hash(),
            "fetch_kib_per_launch": sf, "write_kib_per_launch": sw, "launches": [nf, nw],
            "copy_fetch_kib": cf, "copy_write_kib": cw, "fetch_scale": f_scale, "write_scale": w_scale,
@@ -101,7 +115,7 @@ def pmc_summary(fetch_dir, write_dir, cfetch_dir, cwrite_dir, store, side):
            "hbm_bytes_per_launch": read + write,
            "algorithmic_bytes_per_launch": bpl * n,
            "traffic_over_algorithmic": (read + write) / (bpl * n)}
-    path = os.path.join(ROOT, "profiles", "sweep_d2q9_%s_%d_traffic.json" % (store, side))
+    path = os.path.join(ROOT, "profiles", "%s_traffic.json" % key)
     with open(path, "w") as fh:
         json.dump(rec, fh, indent=1)
     print(json.dumps(rec))
@@ -130,7 +144,8 @@ def _json_line(metric_unit_value, steps, warmup, ms_per_step, dtype, config, roo
     return out
 
 
-DTYPE = {"f32": "f32", "f16dev": "f32 math / f16 storage", "f16loc": "f32 math / f16 storage", "f64": "f64"}
+DTYPE = {"f32": "f32", "f16dev": "f32 math / f16 storage", "f16loc": "f32 math / f16 storage", "f32loc": "f32",
+         "f64": "f64"}
 
 
 def _timed_chunks(s, g, steps, warmup, graph):
@@ -169,7 +184,7 @@ def run_batch(args):
     import shale_inputs as si
     insts = si.cfg2_batch(args.batch)
     t0 = time.perf_counter()
-    maps = si.batch_classes(insts)
+    maps = si.batch_classes(insts, processes=args.map_procs or None)
     t_geom = time.perf_counter() - t0
     import torch
     import paper_1601_00704_amd.glbm as g
@@ -184,6 +199,16 @@ def run_batch(args):
     N = int(sum(m.size for m in maps))
     print("setup: %d instances, %d nodes, maps in %.1fs, store %s" % (len(maps), N, t_geom, args.store),
           file=sys.stderr, flush=True)
+    chosen = None
+    if args.tile:
+        s.set_option(g.GLBM_OPT_TILE_WIDTH, args.tile[0])
+        s.set_option(g.GLBM_OPT_TILE_ROWS, args.tile[1])
+        s.set_option(g.GLBM_OPT_CACHE, args.tile[2])
+    elif not args.no_autotune:
+        t0 = time.perf_counter()
+        chosen = g.glbm_autotune(s.ctx, 10)
+        print("autotune: width %d rows %d cache %d (%.1fs)" % (chosen[0], chosen[1], chosen[2],
+                                                            time.perf_counter() - t0), file=sys.stderr, flush=True)
     wall = _timed_chunks(s, g, args.steps, args.warmup, graph=True)
     per_launch, launches = _sweep_mean_ms(s, g)
     r, st = s.residual()
@@ -195,9 +220,13 @@ def run_batch(args):
                        "P_L U(2,8) MPa, V_L U(0.002,0.008) m3/kg; %s populations; one HIP graph per "
                        "n_c=%d-sweep chunk + FP64 per-instance checks" % (len(maps), sides, args.store.upper(), N_C),
            "instances": len(maps), "nodes": N, "sweeps_per_step": N_C, "graph": True,
+           "tile": ({"width": args.tile[0], "rows": args.tile[1], "cache_policy": args.tile[2], "by": "--tile"}
+                    if args.tile else None if chosen is None else
+                    {"width": int(chosen[0]), "rows": int(chosen[1]), "cache_policy": int(chosen[2]),
+                     "by": "glbm_autotune"}),
            "median_residual": float(np.median(r)), "steps_total": int(st.max())}
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-            "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None,
+            "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic_from_profile(workload_key(args)[0]),
             "kernel": "k_sweep<9,%s> over the flat tile list" % args.store, "bytes_per_lu": bpl,
             "mean_launch_ms": round(per_launch, 5), "launches": launches}
     return _json_line(N * N_C * args.steps / wall / 1e6, args.steps, args.warmup, wall / args.steps * 1e3,
@@ -227,6 +256,27 @@ def run_d3q19(args):
     wall = _timed_chunks(s, g, args.steps, args.warmup, graph=False)
     ms, n = g.glbm_sweep_time(s.ctx)
     per_launch = ms / max(n, 1)
+    conv = None
+    if args.converge_tol > 0:
+        # time to converge, from rest, with graph replays of the n_c-sweep chunks
+        import numpy as np
+        s.set_fields(np.ones(N), np.zeros((3, N)))
+        s.set_option(g.GLBM_OPT_TIMING, 0)
+        s.set_option(g.GLBM_OPT_GRAPH, 1)
+        _, st0 = s.residual()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        done, rc = 0, g.GLBM_ENOTCONVERGED
+        while done < args.max_steps and rc != g.GLBM_OK:
+            rc = s.step(min(20000, args.max_steps - done), tol=args.converge_tol)
+            done += 20000
+            rr, stt = s.residual()
+            print("converge: %d steps, r %.3e" % (int(stt[0] - st0[0]), rr[0]), file=sys.stderr, flush=True)
+        torch.cuda.synchronize()
+        rr, stt = s.residual()
+        conv = {"tol": args.converge_tol, "converged": rc == g.GLBM_OK, "steps": int(stt[0] - st0[0]),
+                "residual": float(rr[0]), "wall_s": round(time.perf_counter() - t0, 2),
+                "k_lattice": [float(v) for v in s.permeability()[0]]}
     r, st = s.residual()
     kk = s.permeability()[0]
     s.close()
@@ -236,12 +286,86 @@ def run_d3q19(args):
                        "faces, %s populations" % (args.side3, args.store.upper()),
            "nodes": N, "sweeps_per_step": N_C, "steps_total": int(st[0]), "residual": float(r[0]),
            "k_lattice_z": float(kk[2])}
+    if conv:
+        cfg["time_to_converge"] = conv
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-            "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None,
+            "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic_from_profile(workload_key(args)[0]),
             "kernel": "k_sweep<19,%s>" % args.store, "bytes_per_lu": bpl,
             "mean_launch_ms": round(per_launch, 5), "launches": n}
     return _json_line(N * N_C * args.steps / wall / 1e6, args.steps, args.warmup, wall / args.steps * 1e3,
                       DTYPE[args.store], cfg, roof)
+
+
+# (cin, cout, level) of the ten convolutions of the warm-start network; level l runs at H/2^l
+CNN_LAYERS = [(8, 32, 0), (32, 32, 0), (32, 64, 1), (64, 64, 1), (64, 128, 2), (128, 128, 2),
+              (192, 64, 1), (64, 64, 1), (96, 32, 0), (32, 3, 0)]
+
+
+def run_cnn(args):
+    """Warm-start network on the GPU: whole-network inference and training-step
+    throughput at B x side x side, and the dominant convolution on its own
+    (BF16 MFMA, FP32 accumulate) against the dense BF16 peak."""
+    import numpy as np
+    import torch
+    import paper_1601_00704_amd.glbm as g
+    torch.cuda.set_device(0)
+    B, H = args.cnn_batch, args.cnn_side
+    W = H
+    flops = sum(2.0 * (H >> l) * (W >> l) * co * 9 * ci for ci, co, l in CNN_LAYERS)
+    rng = np.random.default_rng(0)
+    x = np.zeros((B, H, W, 8), np.float32)
+    x[..., :6] = rng.standard_normal((B, H, W, 6))
+    xd = torch.from_numpy(g.to_bf16_bits(x).view(np.int16)).cuda()
+    yd = torch.zeros(B * H * W * 4, dtype=torch.float32, device="cuda")
+    td = torch.from_numpy(rng.standard_normal((B, H, W, 4)).astype(np.float32)).cuda()
+    md = torch.ones((B, H, W), dtype=torch.uint8, device="cuda")
+    cnn = g.glbm_cnn_create(B, H, W, seed=7)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+
+    def timed(fn, reps):
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        ev[0].record()
+        for _ in range(reps):
+            fn()
+        ev[1].record()
+        torch.cuda.synchronize()
+        return ev[0].elapsed_time(ev[1]) / reps
+
+    fwd_ms = timed(lambda: g.glbm_cnn_forward(cnn, xd.data_ptr(), yd.data_ptr(), B), args.steps)
+    print("forward %.3f ms per batch of %d" % (fwd_ms, B), file=sys.stderr, flush=True)
+    train_ms = timed(lambda: g.glbm_cnn_train_step(cnn, xd.data_ptr(), td.data_ptr(), md.data_ptr(), B, 1e-4),
+                     args.steps)
+    print("train step %.3f ms per batch of %d" % (train_ms, B), file=sys.stderr, flush=True)
+    g.glbm_cnn_destroy(cnn)
+    # the dominant convolution alone: 96 -> 32 channels at full resolution
+    ci, co = 96, 32
+    kp = -(-(9 * ci) // 32) * 32
+    xc = torch.from_numpy(g.to_bf16_bits(rng.standard_normal((B, H, W, ci)).astype(np.float32)).view(np.int16)).cuda()
+    wc = torch.from_numpy(g.to_bf16_bits((0.03 * rng.standard_normal((co, kp))).astype(np.float32))
+                          .view(np.int16)).cuda()
+    bc = torch.zeros(co, dtype=torch.float32, device="cuda")
+    yc = torch.empty(B * H * W * co, dtype=torch.int16, device="cuda")
+    conv_ms = timed(lambda: g.glbm_conv3x3_forward(xc.data_ptr(), ci, 0, ci, wc.data_ptr(), bc.data_ptr(),
+                                                    yc.data_ptr(), co, 0, co, 1, 0, 0, B, H, W), args.steps)
+    conv_flops = 2.0 * B * H * W * co * 9 * ci
+    achieved = conv_flops / (conv_ms * 1e-3) / 1e12
+    cfg = {"workload": "warm-start encoder-decoder (32/64/128 channels, 3x3, BF16 activations and weights, "
+                       "FP32 accumulate), batch %d at %dx%d" % (B, H, W),
+           "flop_per_sample": flops, "forward_ms_per_batch": round(fwd_ms, 3),
+           "train_step_ms_per_batch": round(train_ms, 3),
+           "forward_tflops": round(flops * B / (fwd_ms * 1e-3) / 1e12, 1),
+           "train_tflops": round(3 * flops * B / (train_ms * 1e-3) / 1e12, 1)}
+    roof = {"bound": "mfma", "achieved": round(achieved, 1), "peak": 2500.0, "unit": "TFLOP/s",
+            "frac": round(achieved / 2500.0, 4), "traffic": None,
+            "kernel": "conv3x3 forward 96->32 channels, %d x %dx%d, bf16 MFMA 16x16x32" % (B, H, W),
+            "flop_per_launch": conv_flops, "mean_launch_ms": round(conv_ms, 4)}
+    out = {"metric": "warm-start network inference throughput", "value": round(B / (fwd_ms * 1e-3), 1),
+           "unit": "samples/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": round(fwd_ms, 3), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "bf16", "data": "synthetic (random features)", "config": cfg, "roofline": roof}
+    return out
 
 
 def main():
@@ -251,20 +375,30 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--side", type=int, default=4096)
-    ap.add_argument("--store", default="f32", choices=("f32", "f16dev", "f16loc", "f64"))
+    ap.add_argument("--store", default="f32", choices=("f32", "f16dev", "f16loc", "f32loc", "f64"))
     ap.add_argument("--cpu-steps", type=int, default=1000)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--workload", default="shale4096", choices=("shale4096", "batch", "d3q19"),
-                    help="shale4096: the benchmark line; batch / d3q19: supplementary workloads")
+    ap.add_argument("--workload", default="shale4096", choices=("shale4096", "batch", "d3q19", "cnn"),
+                    help="shale4096: the benchmark line; batch / d3q19 / cnn: supplementary workloads")
+    ap.add_argument("--cnn-batch", type=int, default=8)
+    ap.add_argument("--cnn-side", type=int, default=512)
     ap.add_argument("--batch", type=int, default=256)
+    ap.add_argument("--no-autotune", action="store_true", help="batch: keep the default tile shape")
+    ap.add_argument("--tile", type=int, nargs=3, metavar=("WIDTH", "ROWS", "CACHE"),
+                    help="batch: use this tile shape and cache policy instead of the autotuner's")
+    ap.add_argument("--map-procs", type=int, default=0,
+                    help="worker processes for the batch's maps (0: one per core, at most 16)")
     ap.add_argument("--side3", type=int, default=256)
+    ap.add_argument("--converge-tol", type=float, default=0.0,
+                    help="d3q19: after the timed steps, solve from rest to this residual and report it")
+    ap.add_argument("--max-steps", type=int, default=400000)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run only a plain 1 GiB elementwise copy (counter calibration)")
     ap.add_argument("--pmc-summary", nargs=4, metavar=("FETCH", "WRITE", "COPY_FETCH", "COPY_WRITE"),
                     help="summarise rocprofv3 --pmc output directories into profiles/")
     args = ap.parse_args()
     if args.pmc_summary:
-        pmc_summary(*args.pmc_summary, store=args.store, side=args.side)
+        pmc_summary(*args.pmc_summary, args)
         return
     if args.calibrate_copy:
         calibrate_copy()
@@ -274,6 +408,9 @@ def main():
         return
     if args.workload == "d3q19":
         print(json.dumps(run_d3q19(args)), flush=True)
+        return
+    if args.workload == "cnn":
+        print(json.dumps(run_cnn(args)), flush=True)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the GLBM hot path here is built and timed on a single "
@@ -323,7 +460,7 @@ def main():
     bytes_per_lu = g.bytes_per_update(9, store)
     per_launch = sweep_ms / max(launches, 1)
     achieved = bytes_per_lu * N / (per_launch * 1e-3) / 1e9
-    traffic = traffic_from_profile(args.store, args.side)
+    traffic = traffic_from_profile(workload_key(args)[0])
     out = {
         "metric": METRIC,
         "value": round(mlups, 1),
@@ -335,8 +472,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"f32": "f32", "f16dev": "f32 math / f16 storage", "f16loc": "f32 math / f16 storage",
-                  "f64": "f64"}[args.store],
+        "dtype": DTYPE[args.store],
         "data": "synthetic (seeded QSGS shale map, generated in-process)",
         "config": {"workload": "D2Q9 GLBM %dx%d, QSGS 60%% solid, TOC 0.10, CH4 400 K 10 MPa, %s "
                                "populations, n_c=%d sweeps + FP64 residual/flux per step"
