@@ -211,3 +211,37 @@ def test_training_reduces_loss(gpu):
         g.glbm_cnn_destroy(cnn)
     print("loss %.4f -> %.4f" % (losses[0], losses[-1]))
     assert losses[-1] < 0.5 * losses[0]
+
+
+def test_warm_start_end_to_end(gpu):
+    """Generate GLBM solutions, train the network on them with the library's kernels, then solve
+    held-out problems cold and warm to r <= 1e-8: k must agree within 1e-4 and the warm solve
+    may not be slower than cold by more than 10 %.  Prints the gain it measures."""
+    import torch
+    import shale_inputs as si
+    from paper_1601_00704_amd import warmstart as ws
+    side, n_train, n_test = 256, 32, 4
+    tr = [si.cfg4_instance(100000 + k, side) for k in range(n_train)]
+    te = [si.cfg4_instance(200000 + k, side) for k in range(n_test)]
+    tr_maps, te_maps = si.batch_classes(tr, processes=1), si.batch_classes(te, processes=1)
+    G = tr[0].g
+    x = torch.zeros((n_train, side, side, 8), dtype=torch.int16, device="cuda")
+    t = torch.zeros((n_train, side, side, 4), dtype=torch.float32, device="cuda")
+    m = torch.zeros((n_train, side, side), dtype=torch.uint8, device="cuda")
+    gen = ws.generate(tr, tr_maps, 1e-8, 400000, n_train, x, t, m, 0, G, "f32loc")
+    assert all(r["residual"] <= 1e-8 for r in gen)
+    cnn = gpu.glbm_cnn_create(8, side, side, seed=7)
+    try:
+        hist, _, _ = ws.train(cnn, x, t, m, n_train, 24, 8, 1e-3, side, side)
+        res, cw, ww, iw, _ = ws.evaluate(cnn, te, te_maps, 1e-8, 400000, n_test, G, side, side, "f64")
+    finally:
+        gpu.glbm_cnn_destroy(cnn)
+    cold = np.array([r["cold_steps"] for r in res], float)
+    warm = np.array([r["warm_steps"] for r in res], float)
+    kd = max(r["k_rel_diff"] for r in res)
+    print("loss %.3f -> %.3f; cold steps %s warm steps %s; wall %.2fs vs %.2fs + %.3fs; max k diff %.1e"
+          % (hist[0], hist[-1], cold.tolist(), warm.tolist(), cw, ww, iw, kd))
+    assert hist[-1] < hist[0]
+    assert all(r["cold_residual"] <= 1e-8 and r["warm_residual"] <= 1e-8 for r in res)
+    assert kd <= 1e-4
+    assert np.median(warm) <= 1.1 * np.median(cold)
