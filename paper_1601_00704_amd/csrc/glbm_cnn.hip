@@ -142,6 +142,112 @@ __global__ __launch_bounds__(kConvBlock) void k_conv_fwd(ConvArgs a)
     }
 }
 
+// ------------------------------------------------ forward, tap-major path --
+// For cin = 32 CI (every layer but the first, and the data gradient of every
+// layer with at least 32 output channels).  K runs tap by tap: a pixel's
+// neighbour address is formed once per tap, and the tap's weights [64
+// channels][cin] sit in one of two LDS buffers (one barrier per tap).  Each
+// wavefront covers MB blocks of 16 pixels, so a 32-wide slice of one tap
+// costs MB global loads, nt LDS reads and MB * nt MFMAs.  The A operands of a
+// whole tap are loaded before the barrier, overlapping their latency with the
+// staging of the weights.
+template <int CI, int MB, bool OUT_F32, bool RELU, bool ACC>
+__global__ __launch_bounds__(kConvBlock) void k_conv_fwd_tap(ConvArgs a)
+{
+    constexpr int kCin = 32 * CI;
+    constexpr int kRow = kCin + 8;  // padded LDS row (bf16)
+    __shared__ __attribute__((aligned(16))) uint16_t wt[2][kChTile * kRow];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int m = lane & 15, kq = lane >> 4;
+    const long long pw = (long long)blockIdx.x * (64 * MB) + wave * (16 * MB);
+    const int n0 = blockIdx.y * kChTile;
+    const int nt = min(kChTile, a.cout_pad - n0) >> 4;  // 16-channel blocks (1..4)
+    const int HW = a.H * a.W;
+
+    int py[MB], px[MB];
+    bool ok[MB];
+    const uint16_t* xb[MB];
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb) {
+        const long long p = pw + 16 * mb + m;
+        ok[mb] = p < a.npix;
+        const long long pc = ok[mb] ? p : 0;
+        const int b = int(pc / HW);
+        const int rem = int(pc - (long long)b * HW);
+        py[mb] = rem / a.W;
+        px[mb] = rem - py[mb] * a.W;
+        xb[mb] = a.x + (size_t)b * HW * a.x_pitch + a.x_off + 8 * kq;
+    }
+    f32x4 acc[MB][4];
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[mb][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+    for (int tap = 0; tap < 9; ++tap) {
+        uint16_t* w = wt[tap & 1];
+        // weights of this tap: rows n0 .. n0 + 63, columns tap * cin .. + cin
+        for (int e = threadIdx.x; e < kChTile * (kCin / 8); e += kConvBlock) {
+            const int r = e / (kCin / 8), c8 = (e % (kCin / 8)) * 8;
+            uint4 v = make_uint4(0, 0, 0, 0);
+            if (n0 + r < a.cout_pad)
+                v = *reinterpret_cast<const uint4*>(a.w + (size_t)(n0 + r) * a.k_pad + tap * kCin + c8);
+            *reinterpret_cast<uint4*>(&w[r * kRow + c8]) = v;
+        }
+        const int dy = tap / 3 - 1, dx = tap - 3 * (tap / 3) - 1;
+        uint4 av[MB][CI];
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb) {
+            int yy = py[mb] + dy, xx = px[mb] + dx;
+            yy += yy < 0 ? a.H : (yy >= a.H ? -a.H : 0);
+            xx += xx < 0 ? a.W : (xx >= a.W ? -a.W : 0);
+            const uint16_t* src = xb[mb] + (size_t)(yy * a.W + xx) * a.x_pitch;
+#pragma unroll
+            for (int c = 0; c < CI; ++c)
+                av[mb][c] = ok[mb] ? *reinterpret_cast<const uint4*>(src + 32 * c) : make_uint4(0, 0, 0, 0);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int c = 0; c < CI; ++c) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                if (j < nt) {
+                    const uint4 bv = *reinterpret_cast<const uint4*>(&w[(16 * j + m) * kRow + 32 * c + 8 * kq]);
+                    const bf16x8 bf = __builtin_bit_cast(bf16x8, bv);
+#pragma unroll
+                    for (int mb = 0; mb < MB; ++mb)
+                        acc[mb][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, av[mb][c]),
+                                                                             bf, acc[mb][j], 0, 0, 0);
+                }
+            }
+        }
+    }
+    // epilogue: lane holds D[4 kq + i][m] of each 16 x 16 block
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            if (j >= nt) continue;
+            const int n = n0 + 16 * j + m;
+            if (n >= a.cout) continue;
+            const float bias = a.bias ? a.bias[n] : 0.f;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const long long q = pw + 16 * mb + 4 * kq + i;
+                if (q >= a.npix) continue;
+                float v = acc[mb][j][i] + bias;
+                if (RELU) v = fmaxf(v, 0.f);
+                if (OUT_F32) {
+                    static_cast<float*>(a.y)[(size_t)q * a.y_pitch + a.y_off + n] = v;
+                } else {
+                    uint16_t* yp = static_cast<uint16_t*>(a.y) + (size_t)q * a.y_pitch + a.y_off + n;
+                    if (ACC) v += bf2f(*yp);
+                    *yp = f2bf(v);
+                }
+            }
+        }
+}
+
 // -------------------------------------------------------------- flip weights --
 __global__ void k_flip(const uint16_t* w, int cin, int cout, int k_pad_w, int cout_pad, uint16_t* wt, int k_pad_t,
                        int rows_t)
@@ -530,20 +636,54 @@ int conv_fwd(const uint16_t* x, int xp, int xo, int cin, const uint16_t* w, cons
     a.H = H;
     a.W = W;
     a.npix = (long long)B * H * W;
-    dim3 grid((unsigned)(a.npix / kPixTile), (unsigned)((a.cout_pad + kChTile - 1) / kChTile));
-#define LAUNCH(F, R, A)                                                                                \
-    hipLaunchKernelGGL((k_conv_fwd<F, R, A>), grid, dim3(kConvBlock), 0, s, a)
-    if (yf32) {
-        if (relu) LAUNCH(true, true, false);
-        else LAUNCH(true, false, false);
-    } else if (acc) {
-        if (relu) LAUNCH(false, true, true);
-        else LAUNCH(false, false, true);
+    const unsigned gy = (unsigned)((a.cout_pad + kChTile - 1) / kChTile);
+    const int ci32 = cin % 32 == 0 ? cin / 32 : 0;
+    const int mb = a.cout_pad <= 32 && ci32 <= 3 ? 4 : 2;
+    const bool tap_path = ci32 == 1 || ci32 == 2 || ci32 == 3 || ci32 == 4 || ci32 == 6;
+    if (tap_path) {
+        dim3 grid((unsigned)((a.npix + 64 * mb - 1) / (64 * mb)), gy);
+#define LAUNCH_T(C, M, F, R, A) hipLaunchKernelGGL((k_conv_fwd_tap<C, M, F, R, A>), grid, dim3(kConvBlock), 0, s, a)
+#define EPI_T(C, M)                                                                                    \
+    do {                                                                                               \
+        if (yf32) {                                                                                    \
+            if (relu) LAUNCH_T(C, M, true, true, false);                                               \
+            else LAUNCH_T(C, M, true, false, false);                                                   \
+        } else if (acc) {                                                                              \
+            if (relu) LAUNCH_T(C, M, false, true, true);                                               \
+            else LAUNCH_T(C, M, false, false, true);                                                   \
+        } else {                                                                                       \
+            if (relu) LAUNCH_T(C, M, false, true, false);                                              \
+            else LAUNCH_T(C, M, false, false, false);                                                  \
+        }                                                                                              \
+    } while (0)
+        if (mb == 4) {
+            if (ci32 == 1) EPI_T(1, 4);
+            else if (ci32 == 2) EPI_T(2, 4);
+            else EPI_T(3, 4);
+        } else {
+            if (ci32 == 1) EPI_T(1, 2);
+            else if (ci32 == 2) EPI_T(2, 2);
+            else if (ci32 == 3) EPI_T(3, 2);
+            else if (ci32 == 4) EPI_T(4, 2);
+            else EPI_T(6, 2);
+        }
+#undef EPI_T
+#undef LAUNCH_T
     } else {
-        if (relu) LAUNCH(false, true, false);
-        else LAUNCH(false, false, false);
-    }
+        dim3 grid((unsigned)(a.npix / kPixTile), gy);
+#define LAUNCH(F, R, A) hipLaunchKernelGGL((k_conv_fwd<F, R, A>), grid, dim3(kConvBlock), 0, s, a)
+        if (yf32) {
+            if (relu) LAUNCH(true, true, false);
+            else LAUNCH(true, false, false);
+        } else if (acc) {
+            if (relu) LAUNCH(false, true, true);
+            else LAUNCH(false, false, true);
+        } else {
+            if (relu) LAUNCH(false, true, false);
+            else LAUNCH(false, false, false);
+        }
 #undef LAUNCH
+    }
     CHK(hipGetLastError());
     return GLBM_OK;
 }
