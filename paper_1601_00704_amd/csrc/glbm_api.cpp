@@ -448,6 +448,9 @@ int glbm_init_geometry(glbm_ctx* out, int32_t n_inst, const glbm_instance_desc* 
         I.omega = 1.0 / d.tau;
         I.cforce = 1.0 - 0.5 / d.tau;
         I.nu = (d.tau - 0.5) / 3.0;
+        for (int a = 0; a < 3; ++a) I.gf[a] = (float)I.g[a];
+        I.omegaf = (float)I.omega;
+        I.cforcef = (float)I.cforce;
         const bool half = d.store == GLBM_STORE_F16DEV || d.store == GLBM_STORE_F16LOC;
         const int s = half ? (d.dev_scale_log2 == GLBM_SCALE_AUTO ? auto_scale(d) : d.dev_scale_log2) : 0;
         I.scale = std::ldexp(1.0f, s);

@@ -268,19 +268,23 @@ __global__ void k_flip(const uint16_t* w, int cin, int cout, int k_pad_w, int co
 // pixels 32 at a time.  dy and the shifted x are staged transposed in LDS
 // ([channel][pixel]) so that each lane reads 8 consecutive pixels.
 constexpr int kWgPix = 32;
-constexpr int kWgSplit = 2048;  // pixels per split
+constexpr int kBgradCh = 128;        // channel slots per split of the bias partials
+constexpr int kWgMinSplit = 512;     // fewest pixels per split
+constexpr int kWgTargetBlocks = 2048;  // workgroups the split count aims for
 constexpr int kWtRow = kWgPix + 8;
 
 struct WgradArgs {
     const uint16_t* x;
     const uint16_t* dy;
-    float* part;  // [nsplit][cout_pad16][kreal]
+    float* part;   // [nsplit][cout_pad16][kreal]
+    float* bpart;  // [nsplit][kBgradCh] bias partials, or null
     int x_pitch, x_off, cin;
     int dy_pitch, dy_off, cout;
     int cout_pad, k_real;
     int H, W;
     long long npix;
     int nsplit;
+    long long split_pix;  // pixels per split (a multiple of kWgPix)
 };
 
 __global__ __launch_bounds__(kConvBlock) void k_conv_wgrad(WgradArgs a)
@@ -292,8 +296,11 @@ __global__ __launch_bounds__(kConvBlock) void k_conv_wgrad(WgradArgs a)
     const int k0 = blockIdx.x * 64;   // K columns
     const int c0 = blockIdx.y * 64;   // output channels
     const int split = blockIdx.z;
-    const long long pbeg = (long long)split * kWgSplit;
-    const long long pend = min(pbeg + (long long)kWgSplit, a.npix);
+    const long long pbeg = (long long)split * a.split_pix;
+    const long long pend = min(pbeg + a.split_pix, a.npix);
+    // the blocks of the first K range also sum dy per channel: the bias gradient
+    const bool bias = a.bpart && blockIdx.x == 0;
+    double bsum = 0.0;
     const int HW = a.H * a.W;
     // wave tile: channels c0 + 32 (wave >> 1) .. +32, K columns k0 + 32 (wave & 1) .. +32
     const int wc = 32 * (wave >> 1), wk = 32 * (wave & 1);
@@ -344,6 +351,11 @@ __global__ __launch_bounds__(kConvBlock) void k_conv_wgrad(WgradArgs a)
             }
         }
         __syncthreads();
+        if (bias && threadIdx.x < 64) {
+            // fixed order: pixels of the chunk in sequence
+#pragma unroll 8
+            for (int q = 0; q < kWgPix; ++q) bsum += double(bf2f(dyt[threadIdx.x * kWtRow + q]));
+        }
 #pragma unroll
         for (int i = 0; i < 2; ++i) {
             const uint4 av = *reinterpret_cast<const uint4*>(&dyt[(wc + 16 * i + m) * kWtRow + 8 * kq]);
@@ -355,6 +367,8 @@ __global__ __launch_bounds__(kConvBlock) void k_conv_wgrad(WgradArgs a)
             }
         }
     }
+    if (bias && threadIdx.x < 64 && c0 + threadIdx.x < a.cout)
+        a.bpart[(size_t)split * kBgradCh + c0 + threadIdx.x] = float(bsum);
     // D[4 kq + r][m]: row = output channel, column = K column
     float* out = a.part + (size_t)split * a.cout_pad * a.k_real;
 #pragma unroll
@@ -380,31 +394,22 @@ __global__ void k_wgrad_reduce(const float* part, int nsplit, int cout, int cout
     dw[idx] = float(sd);
 }
 
-// bias gradient: per-workgroup sums over a pixel range (up to 128 channels,
-// two pixel lanes per channel), then a fixed-order reduction over ranges
-constexpr int kBgradCh = 128;
-__global__ void k_bgrad_part(const uint16_t* dy, int dy_pitch, int dy_off, int cout, long long npix, float* part)
+// bias gradient: the per-split channel sums written by k_conv_wgrad, reduced
+// per channel by one workgroup in a fixed order (strided partial sums, then a
+// tree)
+__global__ __launch_bounds__(256) void k_bgrad_reduce(const float* part, int nsplit, float* db)
 {
-    const int c = threadIdx.x & (kBgradCh - 1), lane2 = threadIdx.x >> 7;
-    const long long pbeg = (long long)blockIdx.x * kWgSplit;
-    const long long pend = min(pbeg + (long long)kWgSplit, npix);
-    __shared__ float red[256];
-    float s = 0.f;
-    if (c < cout)
-        for (long long p = pbeg + lane2; p < pend; p += 2) s += bf2f(dy[(size_t)p * dy_pitch + dy_off + c]);
+    __shared__ double red[256];
+    const int c = blockIdx.x;
+    double s = 0.0;
+    for (int t = threadIdx.x; t < nsplit; t += 256) s += part[(size_t)t * kBgradCh + c];
     red[threadIdx.x] = s;
     __syncthreads();
-    if (threadIdx.x < kBgradCh && threadIdx.x < cout)
-        part[(size_t)blockIdx.x * kBgradCh + threadIdx.x] = red[threadIdx.x] + red[threadIdx.x + kBgradCh];
-}
-
-__global__ void k_bgrad_reduce(const float* part, int nsplit, int cout, float* db)
-{
-    const int c = threadIdx.x;
-    if (c >= cout) return;
-    double s = 0.0;
-    for (int t = 0; t < nsplit; ++t) s += part[(size_t)t * kBgradCh + c];
-    db[c] = float(s);
+    for (int h = 128; h > 0; h >>= 1) {
+        if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) db[c] = float(red[0]);
 }
 
 // ----------------------------------------------------------- pooling / upsampling --
@@ -699,10 +704,26 @@ int flip_weights(const uint16_t* w, int cin, int cout, uint16_t* wt, hipStream_t
     return GLBM_OK;
 }
 
+// Split of the pixel range of a weight gradient: enough splits for about
+// kWgTargetBlocks workgroups, none shorter than kWgMinSplit pixels.  Depends
+// only on the shapes, so the reduction order (and the result) is fixed.
+void wgrad_split(int cin, int cout, long long npix, int* nsplit, long long* split_pix)
+{
+    const long long blocks = (long long)((9 * cin + 63) / 64) * ((rup(cout, 16) + 63) / 64);
+    long long ns = std::max(1LL, std::min((npix + kWgMinSplit - 1) / kWgMinSplit,
+                                          (kWgTargetBlocks + blocks - 1) / blocks));
+    long long sp = (npix + ns - 1) / ns;
+    sp = (sp + kWgPix - 1) / kWgPix * kWgPix;
+    *split_pix = sp;
+    *nsplit = (int)((npix + sp - 1) / sp);
+}
+
 size_t wgrad_workspace(int cin, int cout, long long npix)
 {
-    const long long nsplit = (npix + kWgSplit - 1) / kWgSplit;
-    return (size_t)nsplit * rup(cout, 16) * 9 * cin * sizeof(float) + (size_t)nsplit * kBgradCh * sizeof(float) + 256;
+    int ns;
+    long long sp;
+    wgrad_split(cin, cout, npix, &ns, &sp);
+    return (size_t)ns * rup(cout, 16) * 9 * cin * sizeof(float) + (size_t)ns * kBgradCh * sizeof(float) + 256;
 }
 
 int conv_wgrad(const uint16_t* x, int xp, int xo, int cin, const uint16_t* dy, int dp, int dof, int cout, float* dw,
@@ -724,9 +745,9 @@ int conv_wgrad(const uint16_t* x, int xp, int xo, int cin, const uint16_t* dy, i
     a.H = H;
     a.W = W;
     a.npix = (long long)B * H * W;
-    a.nsplit = (int)((a.npix + kWgSplit - 1) / kWgSplit);
+    wgrad_split(cin, cout, a.npix, &a.nsplit, &a.split_pix);
     a.part = static_cast<float*>(ws);
-    float* bpart = a.part + (size_t)a.nsplit * a.cout_pad * a.k_real;
+    a.bpart = db ? a.part + (size_t)a.nsplit * a.cout_pad * a.k_real : nullptr;
     dim3 grid((unsigned)((a.k_real + 63) / 64), (unsigned)((a.cout_pad + 63) / 64), (unsigned)a.nsplit);
     hipLaunchKernelGGL(k_conv_wgrad, grid, dim3(kConvBlock), 0, s, a);
     CHK(hipGetLastError());
@@ -734,9 +755,7 @@ int conv_wgrad(const uint16_t* x, int xp, int xo, int cin, const uint16_t* dy, i
                        cout, a.cout_pad, a.k_real, dw);
     CHK(hipGetLastError());
     if (db) {
-        hipLaunchKernelGGL(k_bgrad_part, dim3(a.nsplit), dim3(256), 0, s, dy, dp, dof, cout, a.npix, bpart);
-        CHK(hipGetLastError());
-        hipLaunchKernelGGL(k_bgrad_reduce, dim3(1), dim3(kBgradCh), 0, s, bpart, a.nsplit, cout, db);
+        hipLaunchKernelGGL(k_bgrad_reduce, dim3(cout), dim3(256), 0, s, a.bpart, a.nsplit, db);
         CHK(hipGetLastError());
     }
     return GLBM_OK;

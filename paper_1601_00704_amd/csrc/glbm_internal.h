@@ -53,6 +53,8 @@ struct InstDev {
     double cforce;       // 1 - 1 / (2 tau)
     double nu;
     float scale, inv_scale;  // FP16 deviation scale 2^s and 2^-s
+    float gf[3];             // g, omega and cforce rounded to float (FP32 kernels)
+    float omegaf, cforcef;
 };
 
 struct Tile {

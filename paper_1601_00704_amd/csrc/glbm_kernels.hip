@@ -109,6 +109,33 @@ __device__ __forceinline__ int xcd_tile(int bid, int G)
 
 template <typename T> __device__ __forceinline__ bool finite(T v) { return isfinite(v); }
 
+// 1 / x: in FP32 the hardware reciprocal refined by one Newton step (within
+// an ulp or two of the rounded quotient, without the full division sequence);
+// in FP64 the correctly rounded division.
+template <typename T> __device__ __forceinline__ T recip(T x)
+{
+    if constexpr (sizeof(T) == 4) {
+        const float r = __builtin_amdgcn_rcpf(x);
+        return r * __builtin_fmaf(-x, r, 2.0f);
+    } else {
+        return T(1) / x;
+    }
+}
+
+// Instance constants in the compute type (FP32 copies made on the host).
+template <typename T> __device__ __forceinline__ T inst_g(const InstDev& I, int a)
+{
+    if constexpr (sizeof(T) == 4) return I.gf[a]; else return I.g[a];
+}
+template <typename T> __device__ __forceinline__ T inst_omega(const InstDev& I)
+{
+    if constexpr (sizeof(T) == 4) return I.omegaf; else return I.omega;
+}
+template <typename T> __device__ __forceinline__ T inst_cforce(const InstDev& I)
+{
+    if constexpr (sizeof(T) == 4) return I.cforcef; else return I.cforce;
+}
+
 // Pull the q post-collision values that stream into node (x, y, z).
 // For a kRho store, d[i] receives the stored part (f_i - w_i rho_s) and r[i]
 // the density deviation rho_s - 1 of the source node s; otherwise d[i] is the
@@ -121,7 +148,10 @@ __device__ __forceinline__ void gather(typename St<STORE>::T (&d)[Q], typename S
 {
     using L = Lat<Q>;
     using S = St<STORE>;
-    using T = typename S::T;
+    using SV = typename S::S;
+    // Full 64-bit per-lane addresses: measured faster here than a uniform plane
+    // base with a 32-bit per-lane offset, although the latter needs fewer
+    // instructions.
     const int nx = I.nx, ny = I.ny, nz = I.nz, stride = I.stride;
     const int xm = x == 0 ? nx - 1 : x - 1, xp = x == nx - 1 ? 0 : x + 1;
     const int ym = y == 0 ? ny - 1 : y - 1, yp = y == ny - 1 ? 0 : y + 1;
@@ -151,7 +181,7 @@ __device__ __forceinline__ void gather(typename St<STORE>::T (&d)[Q], typename S
             }
         }
         // planes without an x shift are read by exactly one wavefront per cache line
-        const typename S::S raw = (ex == 0 && nt_aligned) ? __builtin_nontemporal_load(src + idx) : src[idx];
+        const SV raw = (ex == 0 && nt_aligned) ? __builtin_nontemporal_load(src + idx) : src[idx];
         d[i] = S::dec(raw, I.inv_scale);
         if constexpr (S::kRho) r[i] = rho_plane<STORE>(src, Q, stride)[node];
     }
@@ -207,7 +237,7 @@ template <int Q, typename T, bool FORCH> struct Node {
             if (L::ez(i)) j[2] += L::ez(i) > 0 ? diff : -diff;
         }
         rho = T(1) + drho;
-        const T irho = T(1) / rho;
+        const T irho = recip(rho);
         const T eps = tab[TAB_EPS];
         T v[3];
 #pragma unroll
@@ -233,33 +263,12 @@ template <int Q, typename T, bool FORCH> struct Node {
     }
 };
 
-// Relax towards Eq. (30) and add Eq. (31); deviations in, deviations out.
-template <int Q, typename T, bool FORCH>
-__device__ __forceinline__ void collide(T (&d)[Q], const Node<Q, T, FORCH>& s, const T* tab, T omega, T cforce)
+// A leading direction of an opposite pair (the one whose first non-zero
+// component is positive).
+template <int Q> __host__ __device__ constexpr bool lead(int i)
 {
     using L = Lat<Q>;
-    const T ieps = tab[TAB_INV_EPS];
-    const T uu = s.u[0] * s.u[0] + s.u[1] * s.u[1] + s.u[2] * s.u[2];
-    const T uF = s.u[0] * s.F[0] + s.u[1] * s.F[1] + s.u[2] * s.F[2];
-    const T A = T(-1.5) * ieps * uu;
-    const T B = T(-3) * ieps * uF;
-    const T omw = T(1) - omega;
-    // Equilibrium and forcing parts of the moving directions; the rest direction
-    // takes what closes the zeroth moments (sum_i feq_i = rho, sum_i F_i = 0), so
-    // rounded weights cannot create or destroy mass.
-    T eq0 = s.drho, f0 = T(0);
-#pragma unroll
-    for (int i = 1; i < Q; ++i) {
-        const T eu = T(L::ex(i)) * s.u[0] + T(L::ey(i)) * s.u[1] + T(L::ez(i)) * s.u[2];
-        const T eF = T(L::ex(i)) * s.F[0] + T(L::ey(i)) * s.F[1] + T(L::ez(i)) * s.F[2];
-        const T w = T(L::w(i));
-        const T deq = w * (s.drho + s.rho * (T(3) * eu + T(4.5) * ieps * eu * eu + A));
-        const T frc = w * s.rho * cforce * (T(3) * eF + T(9) * ieps * eu * eF + B);
-        eq0 -= deq;
-        f0 -= frc;
-        d[i] = omw * d[i] + omega * deq + frc;
-    }
-    d[0] = omw * d[0] + omega * eq0 + f0;
+    return L::ex(i) > 0 || (L::ex(i) == 0 && (L::ey(i) > 0 || (L::ey(i) == 0 && L::ez(i) > 0)));
 }
 
 // 1 - sum of the weights as rounded to T (exactly representable: a sum of a
@@ -272,13 +281,19 @@ template <int Q, typename T> __device__ __forceinline__ T weight_defect()
     return T(1.0 - sw);
 }
 
-// The same relaxation on local parts e_i = f_i - w_i rho(x) (kRho stores):
-// e*_i = (1 - omega) e_i + omega w_i rho teq_i + F_i; the rest direction
-// closes the zeroth moments as in collide() and also takes drho (1 - sum w),
-// so that the values leaving the node, w_i drho + e*_i with the rounded
-// weights, carry exactly its mass.
-template <int Q, typename T, bool FORCH>
-__device__ __forceinline__ void collide_local(T (&e)[Q], const Node<Q, T, FORCH>& s, const T* tab, T omega, T cforce)
+// Relax towards Eq. (30) and add Eq. (31).
+//   LOCAL = false: deviations d_i = f_i - w_i in and out.
+//   LOCAL = true (kRho stores): local parts e_i = f_i - w_i rho(x) in and out,
+//     e*_i = (1 - omega) e_i + omega w_i rho teq_i + F_i.
+// For a pair of opposite directions the equilibrium and the forcing term
+// split into a part even in e_i (shared) and an odd part (sign flipped), so
+// each pair is evaluated once.  The rest direction takes what closes the
+// zeroth moments (sum_i feq_i = rho, sum_i F_i = 0), so that rounded weights
+// cannot create or destroy mass; in the local form it also takes drho times
+// the defect 1 - sum w of the rounded weights, so that the values leaving the
+// node, w_i drho + e*_i, carry exactly its mass.
+template <int Q, typename T, bool FORCH, bool LOCAL>
+__device__ __forceinline__ void relax(T (&d)[Q], const Node<Q, T, FORCH>& s, const T* tab, T omega, T cforce)
 {
     using L = Lat<Q>;
     const T ieps = tab[TAB_INV_EPS];
@@ -286,20 +301,33 @@ __device__ __forceinline__ void collide_local(T (&e)[Q], const Node<Q, T, FORCH>
     const T uF = s.u[0] * s.F[0] + s.u[1] * s.F[1] + s.u[2] * s.F[2];
     const T A = T(-1.5) * ieps * uu;
     const T B = T(-3) * ieps * uF;
+    const T k1 = T(4.5) * ieps, k2 = T(9) * ieps;
+    const T rc = s.rho * cforce;
     const T omw = T(1) - omega;
-    T eq0 = T(0), f0 = T(0);
+    T eq0 = LOCAL ? T(0) : s.drho, f0 = T(0);
 #pragma unroll
     for (int i = 1; i < Q; ++i) {
+        if (!lead<Q>(i)) continue;
+        const int o = L::opp(i);
         const T eu = T(L::ex(i)) * s.u[0] + T(L::ey(i)) * s.u[1] + T(L::ez(i)) * s.u[2];
         const T eF = T(L::ex(i)) * s.F[0] + T(L::ey(i)) * s.F[1] + T(L::ez(i)) * s.F[2];
         const T w = T(L::w(i));
-        const T deq = w * s.rho * (T(3) * eu + T(4.5) * ieps * eu * eu + A);
-        const T frc = w * s.rho * cforce * (T(3) * eF + T(9) * ieps * eu * eF + B);
-        eq0 -= deq;
-        f0 -= frc;
-        e[i] = omw * e[i] + omega * deq + frc;
+        const T wr = w * s.rho, wf = w * rc;
+        const T ev = LOCAL ? wr * (k1 * eu * eu + A) : w * s.drho + wr * (k1 * eu * eu + A);
+        const T od = T(3) * wr * eu;
+        const T evf = wf * (k2 * eu * eF + B);
+        const T odf = T(3) * wf * eF;
+        const T P = omega * ev + evf;
+        const T D = omega * od + odf;
+        d[i] = omw * d[i] + P + D;
+        d[o] = omw * d[o] + P - D;
+        eq0 -= T(2) * ev;
+        f0 -= T(2) * evf;
     }
-    e[0] = omw * e[0] + omega * eq0 + f0 + weight_defect<Q, T>() * s.drho;
+    if (LOCAL)
+        d[0] = omw * d[0] + omega * eq0 + f0 + weight_defect<Q, T>() * s.drho;
+    else
+        d[0] = omw * d[0] + omega * eq0 + f0;
 }
 
 template <int Q, typename T, bool FORCH>
@@ -322,8 +350,8 @@ __device__ __forceinline__ void sweep_slots(const Args& a, const Tile& t, const 
 {
     using SS = St<STORE>;
     using T = typename SS::T;
-    const T g[3] = {T(I.g[0]), T(I.g[1]), T(I.g[2])};
-    const T omega = T(I.omega), cforce = T(I.cforce);
+    const T g[3] = {inst_g<T>(I, 0), inst_g<T>(I, 1), inst_g<T>(I, 2)};
+    const T omega = inst_omega<T>(I), cforce = inst_cforce<T>(I);
     const bool nt_store = (a.cache & 1) != 0, nt_load = (a.cache & 2) != 0;
     const int twm = (1 << a.tw_log2) - 1;
     const int z = t.z0;
@@ -351,11 +379,11 @@ __device__ __forceinline__ void sweep_slots(const Args& a, const Tile& t, const 
             // density and the parts relative to it
             const T dr = localize<Q, T>(d[u], r[u]);
             s.moments_with(d[u], dr, ct, g);
-            collide_local<Q, T, FORCH>(d[u], s, ct, omega, cforce);
+            relax<Q, T, FORCH, true>(d[u], s, ct, omega, cforce);
             rho_plane<STORE>(dst, Q, I.stride)[n[u]] = dr;
         } else {
             s.moments(d[u], ct, g);
-            collide<Q, T, FORCH>(d[u], s, ct, omega, cforce);
+            relax<Q, T, FORCH, false>(d[u], s, ct, omega, cforce);
         }
         if (nt_store) {
 #pragma unroll
@@ -386,8 +414,7 @@ __device__ __forceinline__ void sweep_tile(const Args& a, const Tile& t, const I
 // staged in LDS.  Measured on MI355X (4096^2, FP32): 256 x 1 tiles with bits
 // 0, 2 and 3 run at 5.9 TB/s; staging the table in LDS costs each workgroup
 // a fill and a barrier before its first population load is issued.
-template <int Q, int STORE, int BC, bool FORCH>
-__global__ __launch_bounds__(kBlock) void k_sweep(Args a)
+template <int Q, int STORE, int BC, bool FORCH> __device__ __forceinline__ void sweep_block(const Args& a)
 {
     using T = typename St<STORE>::T;
     constexpr int NT = FORCH ? kTabW : 4;
@@ -404,6 +431,26 @@ __global__ __launch_bounds__(kBlock) void k_sweep(Args a)
         load_table<Q, T, FORCH>(tab, a, t.inst);
         sweep_tile<Q, STORE, BC, FORCH>(a, t, I, tab, NT);
     }
+}
+
+template <int Q, int STORE, int BC, bool FORCH> __global__ __launch_bounds__(kBlock) void k_sweep(Args a)
+{
+    sweep_block<Q, STORE, BC, FORCH>(a);
+}
+
+// D3Q19 with a cap of W waves per SIMD.  With 19 read and 19 write streams per
+// wave, fewer waves in flight than the register count allows measured faster
+// for the FP32 and FP64 stores (4 waves: 1.4 % faster than 5, 2.7 % faster
+// than 8 on the 256^3 map); the FP16 stores, which issue more instructions
+// per byte, run best with 5 or more.
+template <int STORE, int BC, bool FORCH, int W>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1, W))) void k_sweep19(Args a)
+{
+    sweep_block<19, STORE, BC, FORCH>(a);
+}
+template <int STORE> constexpr int waves19()
+{
+    return (STORE == GLBM_STORE_F16DEV || STORE == GLBM_STORE_F16LOC) ? 5 : 4;
 }
 
 // ------------------------------------------------------------ observations --
@@ -442,7 +489,7 @@ __device__ __forceinline__ void observe_tile(const Args& a, const Tile& t, const
     const uint8_t* __restrict__ cls = a.cls + I.cls_off;
     T* __restrict__ snap = static_cast<T*>(a.snap) + I.snap_off;
     const int N = I.nx * I.ny * I.nz;
-    const T g[3] = {T(I.g[0]), T(I.g[1]), T(I.g[2])};
+    const T g[3] = {inst_g<T>(I, 0), inst_g<T>(I, 1), inst_g<T>(I, 2)};
     const int twm = (1 << a.tw_log2) - 1;
     const int z = t.z0;
     double acc[6] = {0, 0, 0, 0, 0, 0};
@@ -642,7 +689,7 @@ __global__ __launch_bounds__(kBlock) void k_get_fields(Args a, int inst, double*
     const S* __restrict__ src = static_cast<const S*>(a.buf[sel]) + I.pop_off;
     const uint8_t* __restrict__ cls = a.cls + I.cls_off;
     const int N = I.nx * I.ny * I.nz;
-    const T g[3] = {T(I.g[0]), T(I.g[1]), T(I.g[2])};
+    const T g[3] = {inst_g<T>(I, 0), inst_g<T>(I, 1), inst_g<T>(I, 2)};
     const int twm = (1 << a.tw_log2) - 1;
     const int z = t.z0;
     for (int sl = 0; sl < a.nslot; ++sl) {
@@ -686,7 +733,10 @@ __global__ __launch_bounds__(kBlock) void k_get_fields(Args a, int inst, double*
 template <int Q, int STORE, int BC, bool FORCH> struct SweepK {
     static hipError_t go(const Args& a, hipStream_t s)
     {
-        hipLaunchKernelGGL((k_sweep<Q, STORE, BC, FORCH>), dim3(a.ntiles), dim3(kBlock), 0, s, a);
+        if constexpr (Q == 19)
+            hipLaunchKernelGGL((k_sweep19<STORE, BC, FORCH, waves19<STORE>()>), dim3(a.ntiles), dim3(kBlock), 0, s, a);
+        else
+            hipLaunchKernelGGL((k_sweep<Q, STORE, BC, FORCH>), dim3(a.ntiles), dim3(kBlock), 0, s, a);
         return hipGetLastError();
     }
 };
