@@ -80,13 +80,17 @@ def _pops(s, inst=0):
 
 
 def test_batch_equals_single_bitwise(gpu):
-    """Each instance of an uneven batch evolves bitwise as it does alone."""
+    """Each instance of an uneven batch evolves bitwise as it does alone, at the same tile
+    shape (the default tile width follows the widest instance of a context, and the FP64
+    partial sums of the residual and the flux are grouped per tile)."""
     g = gpu
     shapes = [(40, 64), (33, 100), (64, 128)]
     cases = [random_case(sh, seed=50 + i) for i, sh in enumerate(shapes)]
     G = [(2e-5, 0, 0), (0, 1e-5, 0), (1e-5, 1e-5, 0)]
     descs = [g.make_desc(sh, store=g.GLBM_STORE_F32, g=G[i], check_every=100) for i, sh in enumerate(shapes)]
     sb = g.Solver(descs, [c[0] for c in cases])
+    sb.set_option(g.GLBM_OPT_TILE_WIDTH, 64)
+    sb.set_option(g.GLBM_OPT_TILE_ROWS, 4)
     for i, c in enumerate(cases):
         sb.set_local_perm(c[1][:255], c[2][:255], inst=i)
     sb.step(350)
@@ -95,7 +99,7 @@ def test_batch_equals_single_bitwise(gpu):
     pb = [_pops(sb, i) for i in range(3)]
     sb.close()
     for i, c in enumerate(cases):
-        ss = gpu_solver(g, 9, c[0], c[1], c[2], G=G[i], store="f32")
+        ss = gpu_solver(g, 9, c[0], c[1], c[2], G=G[i], store="f32", tile=(64, 4))
         ss.step(350)
         r1, st1 = ss.residual()
         assert np.array_equal(_pops(ss), pb[i])
@@ -303,3 +307,107 @@ def _inv_order(g):
 
 def _w(g):
     return g.glbm_velocity_set(9)[1]
+
+
+def _step_want(g, q, cls, eps, k, G, tau, walls, f0, node):
+    """The oracle's values of node after one step from the state f0 (all GPU planes, FP64):
+    each direction j is the collision output of the node it streams from, or, across a wall
+    face or from a wall node, the node's own output in the opposite direction.  Also returns
+    the density of the node that wrote each value."""
+    e, w = g.glbm_velocity_set(q)
+    perm = oracle_order(q, g)
+    opp = [next(jj for jj in range(q) if tuple(e[jj]) == tuple(-e[j])) for j in range(q)]
+    nz, ny, nx = (1,) + cls.shape if cls.ndim == 2 else cls.shape
+    flat = cls.reshape(-1)
+    kinv = np.where(np.isinf(k), 0.0, 1.0 / np.where(np.isinf(k), 1.0, k))
+    z, rem = divmod(int(node), ny * nx)
+    y, x = divmod(rem, nx)
+    want, rho_w = np.zeros(q), np.zeros(q)
+    cache = {}
+    for j in range(q):
+        c3 = [x - e[j, 0], y - e[j, 1], z - e[j, 2]]
+        blocked = False
+        for a, (n_a, lo, hi) in enumerate(((nx, 1, 2), (ny, 4, 8), (nz, 16, 32))):
+            if c3[a] < 0:
+                blocked |= bool(walls & lo)
+                c3[a] += n_a
+            elif c3[a] >= n_a:
+                blocked |= bool(walls & hi)
+                c3[a] -= n_a
+        sn = (c3[2] * ny + c3[1]) * nx + c3[0]
+        if not blocked and j != 0 and flat[sn] == 255:
+            blocked = True
+        src, jj = (int(node), opp[j]) if blocked else (sn, j)
+        if src not in cache:
+            c = int(flat[src])
+            f_or = np.empty(q)
+            f_or[perm] = f0[:, src]
+            cache[src] = oracle.collide_node(q, f_or, eps[c], kinv[c], 0.0, tau, G)
+        fo, rho, _, _ = cache[src]
+        want[j] = fo[perm[jj]]
+        rho_w[j] = rho
+    return want, rho_w, w
+
+
+def test_d3q19_full_size_one_step_sampled(gpu):
+    """The 256^3 D3Q19 map with bounce-back walls on the x/y faces (FP32, default launch
+    configuration): one sweep matches the oracle's collision and streaming on sampled nodes,
+    faces and edges included."""
+    g = gpu
+    inst = si.cfg3(256)
+    cls = inst.classes()
+    r_iom, r_om = inst.radii()
+    eps, k = g.glbm_class_table(g.gas_params(inst), r_iom, r_om)
+    G = (0, 0, 1e-4)
+    d = g.make_desc(cls.shape, lattice=g.GLBM_D3Q19, store=g.GLBM_STORE_F32, tau=inst.tau, g=G,
+                    wall_faces=inst.wall_faces, check_every=100)
+    s = g.Solver([d], [cls])
+    s.set_local_perm(eps[:255], k[:255])
+    s.step(40)
+    f0 = s.populations()
+    s.step(1)
+    f1 = s.populations()
+    s.close()
+    nz, ny, nx = cls.shape
+    rng = np.random.default_rng(11)
+    nodes = list(rng.choice(cls.size, size=40, replace=False))
+    for (zz, yy, xx) in ((5, 0, 7), (9, 255, 130), (200, 17, 0), (31, 64, 255), (0, 0, 0), (255, 255, 255),
+                         (100, 0, 255), (77, 255, 0)):
+        nodes.append((zz * ny + yy) * nx + xx)
+    for node in nodes:
+        want, _, w = _step_want(g, 19, cls, eps, k, G, inst.tau, inst.wall_faces, f0, node)
+        scale = np.abs(want - w).max()
+        assert np.abs(f1[:, node] - want).max() <= 1e-6 * scale + 1e-13, node
+
+
+def test_batch_f16loc_largest_member_one_step_sampled(gpu):
+    """A batch holding the largest member of the uneven batch (1024^2) beside smaller ones, in
+    F16LOC storage: one sweep of the 1024^2 instance matches the oracle on sampled nodes to the
+    FP16 rounding of the stored local parts (2^-11 of f_i - w_i rho of the writing node)."""
+    g = gpu
+    big = next(k for k in range(64) if si.cfg2_instance(k).shape[0] == 1024)
+    ks = [big] + [k for k in range(8) if k != big][:2]
+    insts = [si.cfg2_instance(k) for k in ks]
+    maps = [i.classes() for i in insts]
+    descs = [g.make_desc(m.shape, store=g.GLBM_STORE_F16LOC, tau=i.tau, g=(1e-4, 0, 0), check_every=100)
+             for i, m in zip(insts, maps)]
+    s = g.Solver(descs, maps)
+    tabs = []
+    for j, inst in enumerate(insts):
+        r_iom, r_om = inst.radii()
+        eps, k = g.glbm_class_table(g.gas_params(inst), r_iom, r_om)
+        s.set_local_perm(eps[:255], k[:255], inst=j)
+        tabs.append((eps, k))
+    s.step(40)
+    f0 = s.populations(0)
+    s.step(1)
+    f1 = s.populations(0)
+    s.close()
+    cls = maps[0]
+    eps, k = tabs[0]
+    rng = np.random.default_rng(5)
+    for node in rng.choice(cls.size, size=48, replace=False):
+        want, rho_w, w = _step_want(g, 9, cls, eps, k, (1e-4, 0, 0), insts[0].tau, 0, f0, node)
+        local = np.abs(want - w * rho_w).max()
+        scale = np.abs(want - w).max()
+        assert np.abs(f1[:, node] - want).max() <= 2.0 ** -10 * local + 1e-6 * scale + 1e-13, node
