@@ -77,6 +77,25 @@ def calibrate_copy(nbytes=1 << 30, reps=5):
     print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "reps": reps}))
 
 
+def copy_bandwidth(nbytes=1 << 30, reps=10):
+    """HBM bandwidth of a plain device-to-device copy on this GPU (GB/s, read + write)."""
+    import torch
+    a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b
+    torch.cuda.empty_cache()
+    return 2.0 * nbytes / (ms * 1e-3) / 1e9
+
+
 def _pmc_per_kernel(path):
     import csv
     import glob
@@ -483,7 +502,8 @@ def main():
                      "frac": round(achieved / PEAK_HBM_GBS, 4),
                      "traffic": traffic,
                      "kernel": "k_sweep<9,%s>" % args.store, "bytes_per_lu": bytes_per_lu,
-                     "mean_launch_ms": round(per_launch, 5), "launches": launches},
+                     "mean_launch_ms": round(per_launch, 5), "launches": launches,
+                     "measured_copy_gbs": round(copy_bandwidth(), 1)},
     }
     if not args.no_cpu:
         y0, x0 = 0, 0

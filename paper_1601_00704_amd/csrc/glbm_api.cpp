@@ -66,7 +66,7 @@ int validate(int32_t n_inst, const glbm_instance_desc* d)
         if (x.store < 0 || x.store > 4) return fail(GLBM_EINVAL, "instance %d: bad store %d", i, x.store);
         if (x.nx < 1 || x.ny < 1 || x.nz < 1) return fail(GLBM_EINVAL, "instance %d: empty grid", i);
         if (x.lattice == GLBM_D2Q9 && x.nz != 1) return fail(GLBM_EINVAL, "instance %d: D2Q9 needs nz = 1", i);
-        if ((int64_t)x.nx * x.ny * x.nz * (x.lattice + 3) >= (int64_t)1 << 31)
+        if (round_up((int64_t)x.nx * x.ny * x.nz, kBlk) * (x.lattice + 3) >= (int64_t)1 << 31)
             return fail(GLBM_EINVAL, "instance %d: grid too large for 32-bit plane indexing", i);
         if (!(x.tau > 0.5) || !std::isfinite(x.tau)) return fail(GLBM_EINVAL, "instance %d: tau must be > 1/2", i);
         for (int a = 0; a < 3; ++a)
@@ -97,7 +97,7 @@ Layout layout_of(int32_t n_inst, const glbm_instance_desc* d)
     Layout L;
     for (int i = 0; i < n_inst; ++i) {
         const int64_t n = (int64_t)d[i].nx * d[i].ny * d[i].nz;
-        const int64_t s = plane_stride(n);
+        const int64_t s = plane_stride(node_blocks(d[i].store) ? round_up(n, kBlk) : n);
         L.off.push_back(L.elems);
         L.stride.push_back(s);
         L.elems += round_up(s * planes_of(d[i]), 256);

@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "glbm.h"
+
 namespace glbm {
 
 constexpr int kBlock = 256;         // threads per workgroup (4 wavefronts)
@@ -38,12 +40,23 @@ enum PartSlot {
     P_NCHK = 7,  // checks done (instance record only)
 };
 
+// Population layout.  FP64 and FP32 stores keep the q values of kBlk
+// consecutive nodes together, as q runs of kBlk elements (node blocks): the
+// 2q streams of a sweep then stay within a few hundred KiB of each other,
+// which measured 2-7 % faster than q whole-lattice planes.  The FP16 stores,
+// bound by instructions rather than bytes, measured faster with planes
+// (element i * stride + node).
+constexpr int kBlkLog2 = 12;
+constexpr int kBlk = 1 << kBlkLog2;
+constexpr bool node_blocks(int store) { return store != GLBM_STORE_F16DEV && store != GLBM_STORE_F16LOC; }
+
 // Device-side instance descriptor.
 struct InstDev {
     int64_t pop_off;     // element offset of plane 0 of this instance in each buffer
     int64_t cls_off;     // byte offset of the class map
     int64_t snap_off;    // element offset of the u snapshot (3 planes of N)
-    int32_t stride;      // elements between planes
+    int32_t stride;      // elements per population plane (node blocks: padded to whole blocks); the
+                         // FP32 density plane of the local-density stores starts at q * stride
     int32_t nx, ny, nz;
     uint32_t walls;      // face bits
     int32_t par;         // parity offset: state buffer = (g + par) & 1 at global step g

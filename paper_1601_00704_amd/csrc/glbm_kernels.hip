@@ -1,8 +1,9 @@
 // HIP kernels of the GLBM sweep for gfx950 (MI355X).
 //
-// The state of an instance is q planes of population deviations d_i = f_i - w_i
-// (rho0 = 1) in one of three storage types, laid out as SoA planes
-// plane_i[node], node = (z * ny + y) * nx + x.  One time step of the
+// The state of an instance is q population deviations d_i = f_i - w_i per node
+// (rho0 = 1) in one of several storage types, in node blocks or planes
+// (glbm_internal.h); node = (z * ny + y) * nx + x indexes the class map, the
+// density plane and the snapshot, pidx() the populations.  One time step of the
 // generalized lattice Boltzmann equation (Eq. 29 of arXiv:1601.00704) is one
 // launch of k_sweep: every thread pulls the q post-collision values that stream
 // into its node (periodic wrap, or halfway bounce-back at wall faces and wall
@@ -122,6 +123,15 @@ template <typename T> __device__ __forceinline__ T recip(T x)
     }
 }
 
+// Element index of population i of node n (layout: glbm_internal.h).
+template <int Q, int STORE> __device__ __forceinline__ int pidx(int i, int n, int stride)
+{
+    if constexpr (node_blocks(STORE))
+        return (((n >> kBlkLog2) * Q + i) << kBlkLog2) + (n & (kBlk - 1));
+    else
+        return i * stride + n;
+}
+
 // Instance constants in the compute type (FP32 copies made on the host).
 template <typename T> __device__ __forceinline__ T inst_g(const InstDev& I, int a)
 {
@@ -163,7 +173,11 @@ __device__ __forceinline__ void gather(typename St<STORE>::T (&d)[Q], typename S
         const int sy = ey > 0 ? ym : (ey < 0 ? yp : y);
         const int sz = ez > 0 ? zm : (ez < 0 ? zp : z);
         const int sn = (sz * ny + sy) * nx + sx;
-        int idx = i * stride + sn;
+        int idx;
+        if constexpr (node_blocks(STORE))
+            idx = pidx<Q, STORE>(i, sn, stride);
+        else
+            idx = i * stride + sn;
         int node = sn;
         if (BC >= 1) {
             const uint32_t w = I.walls;
@@ -176,7 +190,10 @@ __device__ __forceinline__ void gather(typename St<STORE>::T (&d)[Q], typename S
             if (ez < 0) blocked |= (z == nz - 1) && (w & 32u);
             if (BC >= 2 && i != 0) blocked |= cls[sn] == kWallClass;
             if (blocked) {
-                idx = L::opp(i) * stride + n;
+                if constexpr (node_blocks(STORE))
+                    idx = pidx<Q, STORE>(L::opp(i), n, stride);
+                else
+                    idx = L::opp(i) * stride + n;
                 node = n;
             }
         }
@@ -385,13 +402,24 @@ __device__ __forceinline__ void sweep_slots(const Args& a, const Tile& t, const 
             s.moments(d[u], ct, g);
             relax<Q, T, FORCH, false>(d[u], s, ct, omega, cforce);
         }
-        if (nt_store) {
+        if constexpr (node_blocks(STORE)) {
+            if (nt_store) {
 #pragma unroll
-            for (int i = 0; i < Q; ++i)
-                __builtin_nontemporal_store(SS::enc(d[u][i], I.scale), dst + i * I.stride + n[u]);
+                for (int i = 0; i < Q; ++i)
+                    __builtin_nontemporal_store(SS::enc(d[u][i], I.scale), dst + pidx<Q, STORE>(i, n[u], 0));
+            } else {
+#pragma unroll
+                for (int i = 0; i < Q; ++i) dst[pidx<Q, STORE>(i, n[u], 0)] = SS::enc(d[u][i], I.scale);
+            }
         } else {
+            if (nt_store) {
 #pragma unroll
-            for (int i = 0; i < Q; ++i) dst[i * I.stride + n[u]] = SS::enc(d[u][i], I.scale);
+                for (int i = 0; i < Q; ++i)
+                    __builtin_nontemporal_store(SS::enc(d[u][i], I.scale), dst + i * I.stride + n[u]);
+            } else {
+#pragma unroll
+                for (int i = 0; i < Q; ++i) dst[i * I.stride + n[u]] = SS::enc(d[u][i], I.scale);
+            }
         }
     }
 }
@@ -666,7 +694,7 @@ __global__ __launch_bounds__(kBlock) void k_set_fields(Args a, int inst, const R
             if (sz >= I.nz) { blocked |= (I.walls & 32u) != 0; sz -= I.nz; }
             const int sn = (sz * I.ny + sy) * I.nx + sx;
             if (BC >= 2 && !blocked && i != 0) blocked = cls[sn] == kWallClass;
-            const int idx = blocked ? L::opp(i) * I.stride + n : i * I.stride + sn;
+            const int idx = blocked ? pidx<Q, STORE>(L::opp(i), n, I.stride) : pidx<Q, STORE>(i, sn, I.stride);
             // a kRho value is decoded with the density of the node whose slot it occupies
             const T dr = SS::kRho ? T(rho_in[blocked ? n : sn] - R(1)) : T(0);
             dst[idx] = SS::enc(dq - T(L::w(i)) * dr, I.scale);
