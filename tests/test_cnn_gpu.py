@@ -93,12 +93,26 @@ def test_conv_forward_full_tile_grid(gpu):
     _conv_case(gpu, 2, 256, 256, 32, 32, 32, 0, 32, 0, relu=True, f32=False, acc=False, seed=9)
 
 
-@pytest.mark.parametrize("cin,cout", [(32, 3), (96, 32), (64, 128)])
-def test_conv_data_gradient(gpu, cin, cout):
+# Wider rows (128 and 256 pixels, as in the network) for every layer shape with cin a
+# multiple of 32 (tap-major kernel), ragged output channel counts included.
+@pytest.mark.parametrize("cin,cout,W", [(32, 32, 256), (96, 32, 256), (32, 3, 256), (96, 32, 128),
+                                         (64, 128, 128), (192, 64, 128), (128, 128, 256), (64, 96, 128)])
+def test_conv_forward_wide_rows(gpu, cin, cout, W):
+    _conv_case(gpu, 2, 3, W, cin, cout, cin, 0, cout, 0, relu=False, f32=True, acc=False, seed=cin + 7 * cout + W)
+
+
+@pytest.mark.parametrize("relu,acc", [(True, False), (False, True)])
+def test_conv_forward_wide_row_slices(gpu, relu, acc):
+    # input channels [32, 96) of a 192-wide buffer, output channels [64, 96) of a 192-wide one
+    _conv_case(gpu, 1, 4, 256, 64, 32, 192, 32, 192, 64, relu=relu, f32=False, acc=acc, seed=17)
+
+
+@pytest.mark.parametrize("cin,cout,W", [(32, 3, 64), (96, 32, 64), (64, 128, 64), (96, 32, 128), (64, 128, 128)])
+def test_conv_data_gradient(gpu, cin, cout, W):
     import torch
     g = gpu
-    rng = np.random.default_rng(cin * cout)
-    B, H, W = 2, 4, 64
+    rng = np.random.default_rng(cin * cout + W)
+    B, H = 2, 4
     cp = -(-cout // 16) * 16
     w = _bf(rng.standard_normal((cout, cin, 3, 3)) / np.sqrt(9 * cin))
     gy = np.zeros((B, H, W, cp))
