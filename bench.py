@@ -46,7 +46,7 @@ def workload_key(args):
     """(profile key, lattice Q, nodes) of the workload the arguments select."""
     if args.workload == "batch":
         import shale_inputs as si
-        nodes = sum(int(np.prod(i.shape)) for i in si.cfg2_batch(args.batch))
+        nodes = sum(int(np.prod(i.shape)) for i in si.uneven_batch(args.batch))
         return "sweep_batch%d_d2q9_%s" % (args.batch, args.store), 9, nodes
     if args.workload == "d3q19":
         return "sweep_d3q19_%s_%d" % (args.store, args.side3), 19, args.side3 ** 3
@@ -201,7 +201,7 @@ def run_batch(args):
     Langmuir parameters, one HIP graph per n_c-step chunk over all instances."""
     import numpy as np
     import shale_inputs as si
-    insts = si.cfg2_batch(args.batch)
+    insts = si.uneven_batch(args.batch)
     t0 = time.perf_counter()
     maps = si.batch_classes(insts, processes=args.map_procs or None)
     t_geom = time.perf_counter() - t0
@@ -256,7 +256,7 @@ def run_d3q19(args):
     """256^3 D3Q19: 3-D QSGS (55% solid, TOC 0.20, 20 MPa), drive along z,
     halfway bounce-back on the x and y faces."""
     import shale_inputs as si
-    inst = si.cfg3(args.side3)
+    inst = si.shale3d(args.side3)
     t0 = time.perf_counter()
     cls = inst.classes()
     t_geom = time.perf_counter() - t0
@@ -433,7 +433,7 @@ def main():
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the GLBM hot path here is built and timed on a single "
-              "MI355X (multi-GPU sharding is a design note, not part of this build).", file=sys.stderr)
+              "MI355X; sharding over several GPUs is not implemented.", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
@@ -442,7 +442,7 @@ def main():
     import paper_1601_00704_amd.glbm as g
 
     torch.cuda.set_device(0)
-    inst = si.cfg1(args.side)
+    inst = si.shale4096(args.side)
     t0 = time.perf_counter()
     cls = inst.classes()
     t_geom = time.perf_counter() - t0

@@ -33,7 +33,7 @@ N_C = 100
 
 def _instances(seeds, side):
     import shale_inputs as si
-    return [si.cfg4_instance(s, side) for s in seeds]
+    return [si.warmstart_instance(s, side) for s in seeds]
 
 
 def _maps(insts):

@@ -183,17 +183,17 @@ class Instance:
         return tuple(g)
 
 
-def cfg0() -> Instance:
+def shale128() -> Instance:
     """128^2 D2Q9 case: 60% solid, TOC 0.15, methane at 400 K and 5 MPa."""
     return Instance(shape=(128, 128), seed=0)
 
 
-def cfg1(side: int = 4096) -> Instance:
+def shale4096(side: int = 4096) -> Instance:
     """4096^2 D2Q9 case: TOC 0.10 at 10 MPa, otherwise as the 128^2 case."""
     return Instance(shape=(side, side), seed=1, toc=0.10, pressure=10.0e6)
 
 
-def cfg1_crops(inst: Instance, cls: np.ndarray, size: int = 512):
+def shale4096_crops(inst: Instance, cls: np.ndarray, size: int = 512):
     """Four periodic crops of the large map at (0,0), (0,W/2), (W/2,0), (W/2,W/2)."""
     h = cls.shape[0] // 2
     out = []
@@ -205,7 +205,7 @@ def cfg1_crops(inst: Instance, cls: np.ndarray, size: int = 512):
 BATCH_SIDES = (256, 384, 512, 768, 1024)
 
 
-def cfg2_instance(k: int, side: Optional[int] = None) -> Instance:
+def batch_instance(k: int, side: Optional[int] = None) -> Instance:
     """Instance k of the uneven batch: seed 2000+k, parameters drawn per instance."""
     seed = 2000 + k
     rng = np.random.Generator(np.random.PCG64(seed))
@@ -220,15 +220,15 @@ def cfg2_instance(k: int, side: Optional[int] = None) -> Instance:
                     q_sat=None, langmuir_vl=vl)
 
 
-def cfg3(side: int = 256) -> Instance:
+def shale3d(side: int = 256) -> Instance:
     """256^3 D3Q19 case: 55% solid, TOC 0.20, 20 MPa, drive along z, walls on x/y faces."""
     return Instance(shape=(side, side, side), seed=3, solid_frac=0.55, toc=0.20,
                     pressure=20.0e6, drive_axis=2, wall_faces=0b001111)
 
 
-def cfg4_instance(seed: int, side: int = 512) -> Instance:
-    """A warm-start problem: cfg2's parameter distributions at a fixed side."""
-    inst = cfg2_instance(0)
+def warmstart_instance(seed: int, side: int = 512) -> Instance:
+    """A warm-start problem: the uneven batch's parameter distributions at a fixed side."""
+    inst = batch_instance(0)
     rng = np.random.Generator(np.random.PCG64(seed))
     rng.choice(BATCH_SIDES)
     inst.seed = seed
@@ -256,9 +256,9 @@ def batch_classes(instances: Sequence["Instance"], processes: Optional[int] = No
         return pool.map(_classes_of, list(instances), chunksize=1)
 
 
-def cfg2_batch(n: int = 256):
+def uneven_batch(n: int = 256):
     """The uneven batch: instances 0 .. n-1, largest first (longest-processing-time order)."""
-    insts = [cfg2_instance(k) for k in range(n)]
+    insts = [batch_instance(k) for k in range(n)]
     return sorted(insts, key=lambda i: -int(np.prod(i.shape)))
 
 

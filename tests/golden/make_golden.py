@@ -47,20 +47,20 @@ def solve_case(name, inst, cls, tol, max_steps, precision="ext"):
     print(name, "steps", sol.steps, "r", sol.residual, "k", sol.k, "%.1fs" % dt, flush=True)
 
 
-def case_cfg0():
-    inst = si.cfg0()
-    solve_case("cfg0_128_oracle", inst, inst.classes(), 1e-8, 400000)
+def case_shale128():
+    inst = si.shale128()
+    solve_case("shale128_oracle", inst, inst.classes(), 1e-8, 400000)
 
 
 def case_crop():
-    inst = si.cfg1(4096)
+    inst = si.shale4096(4096)
     cls = inst.classes()
     crop = np.ascontiguousarray(cls[:512, :512])
-    solve_case("cfg1_crop512_oracle", inst, crop, 1e-8, 2000000, precision="f64")
+    solve_case("shale4096_crop512_oracle", inst, crop, 1e-8, 2000000, precision="f64")
 
 
-CASES = {"cfg0": case_cfg0, "crop": case_crop}
+CASES = {"shale128": case_shale128, "crop": case_crop}
 
 if __name__ == "__main__":
-    for c in (sys.argv[1:] or ["cfg0"]):
+    for c in (sys.argv[1:] or ["shale128"]):
         CASES[c]()

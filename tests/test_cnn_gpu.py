@@ -235,8 +235,8 @@ def test_warm_start_end_to_end(gpu):
     import shale_inputs as si
     from paper_1601_00704_amd import warmstart as ws
     side, n_train, n_test = 256, 32, 4
-    tr = [si.cfg4_instance(100000 + k, side) for k in range(n_train)]
-    te = [si.cfg4_instance(200000 + k, side) for k in range(n_test)]
+    tr = [si.warmstart_instance(100000 + k, side) for k in range(n_train)]
+    te = [si.warmstart_instance(200000 + k, side) for k in range(n_test)]
     tr_maps, te_maps = si.batch_classes(tr, processes=1), si.batch_classes(te, processes=1)
     G = tr[0].g
     x = torch.zeros((n_train, side, side, 8), dtype=torch.int16, device="cuda")

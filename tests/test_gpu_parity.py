@@ -107,17 +107,17 @@ def test_d3q19_periodic(gpu):
 
 
 @pytest.fixture(scope="module")
-def cfg1_crops():
+def shale4096_crops():
     """512 x 512 crops of the 4096 x 4096 benchmark map, with its physical class table."""
     from oracle import kapp
-    inst = si.cfg1()
-    crops = si.cfg1_crops(inst, inst.classes(), 512)
+    inst = si.shale4096()
+    crops = si.shale4096_crops(inst, inst.classes(), 512)
     return crops, kapp.class_table(inst)
 
 
 @pytest.mark.parametrize("store,crop", [("f64", 0), ("f32", 1), ("f32loc", 2), ("f16loc", 3)])
-def test_cfg1_crop_fixed_steps(gpu, cfg1_crops, store, crop):
+def test_shale4096_crop_fixed_steps(gpu, shale4096_crops, store, crop):
     """The benchmark's own map and class table (K_app from DGM/GMS at 10 MPa, body force 1e-6):
     200 steps on a 512 x 512 crop, element by element."""
-    crops, (eps, k, fe) = cfg1_crops
+    crops, (eps, k, fe) = shale4096_crops
     _compare(gpu, 9, crops[crop], eps, k, fe, store, 200, G=(1e-6, 0, 0))

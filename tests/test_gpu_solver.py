@@ -1,7 +1,7 @@
 """Whole-solve behaviour of the GPU path through the C ABI.
 
 Converged permeability on the 128^2 shale case against the stored oracle
-result (tests/golden/cfg0_128_oracle.json, written by make_golden.py from the
+result (tests/golden/shale128_oracle.json, written by make_golden.py from the
 extended-precision oracle), batching, graph replay, checkpoints, symmetry
 invariants, error paths, warm start, and one-step parity at the full 4096^2
 benchmark size on sampled nodes.
@@ -29,10 +29,10 @@ def _golden(name):
         return json.load(fh)
 
 
-def _cfg0_solver(g, store):
-    inst = si.cfg0()
+def _shale128_solver(g, store):
+    inst = si.shale128()
     cls = inst.classes()
-    ref = _golden("cfg0_128_oracle")
+    ref = _golden("shale128_oracle")
     assert hashlib.sha256(cls.tobytes()).hexdigest()[:16] == ref["map_sha"], "QSGS map differs from the golden"
     r_iom, r_om = inst.radii()
     eps, k = g.glbm_class_table(g.gas_params(inst), r_iom, r_om)
@@ -43,9 +43,9 @@ def _cfg0_solver(g, store):
 
 
 @pytest.mark.parametrize("store,tol", [("f64", 1e-11), ("f32", 1e-5), ("f32loc", 1e-5), ("f16loc", 1e-3)])
-def test_cfg0_permeability_matches_oracle(gpu, store, tol):
+def test_shale128_permeability_matches_oracle(gpu, store, tol):
     """k after the oracle's converged step count (r <= 1e-8) matches the oracle."""
-    s, ref = _cfg0_solver(gpu, store)
+    s, ref = _shale128_solver(gpu, store)
     try:
         s.step(ref["steps"])
         k = s.permeability()[0, 0]
@@ -60,9 +60,9 @@ def test_cfg0_permeability_matches_oracle(gpu, store, tol):
         assert abs(r[0] - ref["residual"]) / ref["residual"] < 1e-6
 
 
-def test_cfg0_convergence_stop_matches_oracle(gpu):
+def test_shale128_convergence_stop_matches_oracle(gpu):
     """With tol = 1e-8 the FP64 GPU solve stops at the oracle's check step."""
-    s, ref = _cfg0_solver(gpu, "f64")
+    s, ref = _shale128_solver(gpu, "f64")
     try:
         rc = s.step(400000, tol=1e-8)
         r, st = s.residual()
@@ -263,7 +263,7 @@ def test_full_size_one_step_sampled(gpu):
     matches the oracle's collision and streaming on sampled nodes, and mass is
     conserved over the run."""
     g = gpu
-    inst = si.cfg1(4096)
+    inst = si.shale4096(4096)
     cls = inst.classes()
     r_iom, r_om = inst.radii()
     eps, k = g.glbm_class_table(g.gas_params(inst), r_iom, r_om)
@@ -354,7 +354,7 @@ def test_d3q19_full_size_one_step_sampled(gpu):
     configuration): one sweep matches the oracle's collision and streaming on sampled nodes,
     faces and edges included."""
     g = gpu
-    inst = si.cfg3(256)
+    inst = si.shale3d(256)
     cls = inst.classes()
     r_iom, r_om = inst.radii()
     eps, k = g.glbm_class_table(g.gas_params(inst), r_iom, r_om)
@@ -385,9 +385,9 @@ def test_batch_f16loc_largest_member_one_step_sampled(gpu):
     F16LOC storage: one sweep of the 1024^2 instance matches the oracle on sampled nodes to the
     FP16 rounding of the stored local parts (2^-11 of f_i - w_i rho of the writing node)."""
     g = gpu
-    big = next(k for k in range(64) if si.cfg2_instance(k).shape[0] == 1024)
+    big = next(k for k in range(64) if si.batch_instance(k).shape[0] == 1024)
     ks = [big] + [k for k in range(8) if k != big][:2]
-    insts = [si.cfg2_instance(k) for k in ks]
+    insts = [si.batch_instance(k) for k in ks]
     maps = [i.classes() for i in insts]
     descs = [g.make_desc(m.shape, store=g.GLBM_STORE_F16LOC, tau=i.tau, g=(1e-4, 0, 0), check_every=100)
              for i, m in zip(insts, maps)]

@@ -41,7 +41,7 @@ def test_om_surface_term_closed_form():
         assert abs(ks - want) / want < 1e-9
 
 
-def test_cfg0_values():
+def test_shale128_values():
     """The 128^2 case at its median radii: IOM K_0 = (0.1/2)(40 nm)^2 / 32 = 2.5e-18 m^2."""
     k0 = kapp.intrinsic_permeability(0.1, TORT, 40e-9)
     assert abs(k0 - 2.5e-18) < 1e-30
@@ -103,11 +103,11 @@ def test_om_langmuir_dependence():
 
 
 # ---------------------------------------------- product vs oracle (host) --
-@pytest.mark.parametrize("which", ["cfg0", "cfg1", "cfg2", "cfg3"])
+@pytest.mark.parametrize("which", ["shale128", "shale4096", "batch", "shale3d"])
 def test_native_class_table_matches_oracle(which):
     import paper_1601_00704_amd.glbm as g
-    inst = {"cfg0": si.cfg0(), "cfg1": si.cfg1(64), "cfg2": si.cfg2_instance(17, side=64),
-            "cfg3": si.cfg3(16)}[which]
+    inst = {"shale128": si.shale128(), "shale4096": si.shale4096(64), "batch": si.batch_instance(17, side=64),
+            "shale3d": si.shale3d(16)}[which]
     r_iom, r_om = inst.radii()
     eps, k = g.glbm_class_table(g.gas_params(inst), r_iom, r_om)
     e_o, k_o, _ = kapp.class_table(inst)
@@ -120,7 +120,7 @@ def test_native_class_table_matches_oracle(which):
 
 def test_native_class_table_rejects_bad_input():
     import paper_1601_00704_amd.glbm as g
-    inst = si.cfg0()
+    inst = si.shale128()
     p = g.gas_params(inst)
     p.pressure = -1.0
     with pytest.raises(g.GlbmError):
