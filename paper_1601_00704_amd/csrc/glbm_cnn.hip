@@ -265,9 +265,11 @@ __global__ void k_flip(const uint16_t* w, int cin, int cout, int k_pad_w, int co
 
 // ---------------------------------------------------------- weight gradient --
 // Workgroup: 64 output channels x 64 columns of K, reducing over a range of
-// pixels 32 at a time.  dy and the shifted x are staged transposed in LDS
-// ([channel][pixel]) so that each lane reads 8 consecutive pixels.
-constexpr int kWgPix = 32;
+// pixels 128 at a time.  dy and the shifted x are staged transposed in LDS
+// ([channel][pixel]) so that each lane reads 8 consecutive pixels: a thread
+// loads 8 channels of 4 pixels and writes each channel's 4 values with one
+// 8-byte store.  Each wavefront then issues 16 MFMAs per staged chunk.
+constexpr int kWgPix = 128;
 constexpr int kBgradCh = 128;        // channel slots per split of the bias partials
 constexpr int kWgMinSplit = 512;     // fewest pixels per split
 constexpr int kWgTargetBlocks = 2048;  // workgroups the split count aims for
@@ -310,45 +312,60 @@ __global__ __launch_bounds__(kConvBlock) void k_conv_wgrad(WgradArgs a)
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
 
-    // loader role: pixel lp = tid / 8, 8-wide chunk lc = tid % 8
-    const int lp = threadIdx.x >> 3, lc = threadIdx.x & 7;
+    // loader role: pixels 4 lp .. 4 lp + 3 of the chunk, 8-wide channel / K group lc.
+    // lp runs fastest, so that the 8-byte transposed LDS writes of a wavefront
+    // fill consecutive slots of two rows (no bank conflicts beyond the minimum).
+    const int lp = threadIdx.x & 31, lc = threadIdx.x >> 5;
+    const int co = c0 + 8 * lc;
+    const int k = k0 + 8 * lc;
+    int tap = 0, ci = 0;
+    if (k < a.k_real) {
+        tap = k / a.cin;
+        ci = k - tap * a.cin;
+    }
+    const int ty = tap / 3 - 1, tx = tap % 3 - 1;
     for (long long pb = pbeg; pb < pend; pb += kWgPix) {
-        __syncthreads();
-        {
-            const long long p = pb + lp;
-            uint4 dv = make_uint4(0, 0, 0, 0), xv = make_uint4(0, 0, 0, 0);
+        uint4 dv[4], xv[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const long long p = pb + 4 * lp + u;
+            dv[u] = make_uint4(0, 0, 0, 0);
+            xv[u] = make_uint4(0, 0, 0, 0);
             if (p < pend) {
-                const int b = int(p / HW);
-                const int rem = int(p - (long long)b * HW);
-                const int py = rem / a.W, px = rem - py * a.W;
-                const int co = c0 + 8 * lc;
                 if (co < a.cout) {
                     const uint16_t* src = a.dy + (size_t)p * a.dy_pitch + a.dy_off + co;
                     if (co + 8 <= a.cout) {
-                        dv = *reinterpret_cast<const uint4*>(src);
+                        dv[u] = *reinterpret_cast<const uint4*>(src);
                     } else {
                         uint16_t t[8] = {0, 0, 0, 0, 0, 0, 0, 0};
                         for (int i = 0; i < a.cout - co; ++i) t[i] = src[i];
-                        memcpy(&dv, t, 16);
+                        memcpy(&dv[u], t, 16);
                     }
                 }
-                const int k = k0 + 8 * lc;
                 if (k < a.k_real) {
-                    const int tap = k / a.cin, ci = k - tap * a.cin;
-                    int yy = py + tap / 3 - 1, xx = px + tap % 3 - 1;
+                    const int b = int(p / HW);
+                    const int rem = int(p - (long long)b * HW);
+                    const int py = rem / a.W, px = rem - py * a.W;
+                    int yy = py + ty, xx = px + tx;
                     yy += yy < 0 ? a.H : (yy >= a.H ? -a.H : 0);
                     xx += xx < 0 ? a.W : (xx >= a.W ? -a.W : 0);
-                    xv = *reinterpret_cast<const uint4*>(a.x + ((size_t)b * HW + yy * a.W + xx) * a.x_pitch + a.x_off +
-                                                         ci);
+                    xv[u] = *reinterpret_cast<const uint4*>(a.x + ((size_t)b * HW + yy * a.W + xx) * a.x_pitch +
+                                                            a.x_off + ci);
                 }
             }
-            const uint16_t* dh = reinterpret_cast<const uint16_t*>(&dv);
-            const uint16_t* xh = reinterpret_cast<const uint16_t*>(&xv);
+        }
+        __syncthreads();
+        // transposed: row = channel (or K column), 4 consecutive pixels per 8-byte write
 #pragma unroll
-            for (int i = 0; i < 8; ++i) {
-                dyt[(8 * lc + i) * kWtRow + lp] = dh[i];
-                xt[(8 * lc + i) * kWtRow + lp] = xh[i];
-            }
+        for (int i = 0; i < 8; ++i) {
+            const uint16_t* d0 = reinterpret_cast<const uint16_t*>(dv);
+            const uint16_t* x0 = reinterpret_cast<const uint16_t*>(xv);
+            const uint2 dq = make_uint2(uint32_t(d0[i]) | (uint32_t(d0[8 + i]) << 16),
+                                        uint32_t(d0[16 + i]) | (uint32_t(d0[24 + i]) << 16));
+            const uint2 xq = make_uint2(uint32_t(x0[i]) | (uint32_t(x0[8 + i]) << 16),
+                                        uint32_t(x0[16 + i]) | (uint32_t(x0[24 + i]) << 16));
+            *reinterpret_cast<uint2*>(&dyt[(8 * lc + i) * kWtRow + 4 * lp]) = dq;
+            *reinterpret_cast<uint2*>(&xt[(8 * lc + i) * kWtRow + 4 * lp]) = xq;
         }
         __syncthreads();
         if (bias && threadIdx.x < 64) {
@@ -357,13 +374,18 @@ __global__ __launch_bounds__(kConvBlock) void k_conv_wgrad(WgradArgs a)
             for (int q = 0; q < kWgPix; ++q) bsum += double(bf2f(dyt[threadIdx.x * kWtRow + q]));
         }
 #pragma unroll
-        for (int i = 0; i < 2; ++i) {
-            const uint4 av = *reinterpret_cast<const uint4*>(&dyt[(wc + 16 * i + m) * kWtRow + 8 * kq]);
+        for (int ks = 0; ks < kWgPix / 32; ++ks) {
 #pragma unroll
-            for (int j = 0; j < 2; ++j) {
-                const uint4 bv = *reinterpret_cast<const uint4*>(&xt[(wk + 16 * j + m) * kWtRow + 8 * kq]);
-                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, av),
-                                                                     __builtin_bit_cast(bf16x8, bv), acc[i][j], 0, 0, 0);
+            for (int i = 0; i < 2; ++i) {
+                const uint4 av = *reinterpret_cast<const uint4*>(&dyt[(wc + 16 * i + m) * kWtRow + 32 * ks + 8 * kq]);
+#pragma unroll
+                for (int j = 0; j < 2; ++j) {
+                    const uint4 bv =
+                        *reinterpret_cast<const uint4*>(&xt[(wk + 16 * j + m) * kWtRow + 32 * ks + 8 * kq]);
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, av),
+                                                                         __builtin_bit_cast(bf16x8, bv), acc[i][j], 0,
+                                                                         0, 0);
+                }
             }
         }
     }
@@ -377,9 +399,9 @@ __global__ __launch_bounds__(kConvBlock) void k_conv_wgrad(WgradArgs a)
         for (int j = 0; j < 2; ++j)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int co = c0 + wc + 16 * i + 4 * kq + r;
-                const int k = k0 + wk + 16 * j + m;
-                if (co < a.cout_pad && k < a.k_real) out[(size_t)co * a.k_real + k] = acc[i][j][r];
+                const int co2 = c0 + wc + 16 * i + 4 * kq + r;
+                const int k2 = k0 + wk + 16 * j + m;
+                if (co2 < a.cout_pad && k2 < a.k_real) out[(size_t)co2 * a.k_real + k2] = acc[i][j][r];
             }
 }
 

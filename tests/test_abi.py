@@ -97,3 +97,17 @@ def test_package_fails_loudly_without_library(tmp_path, monkeypatch):
     mod = importlib.util.module_from_spec(spec)
     with pytest.raises(ImportError):
         spec.loader.exec_module(mod)
+
+
+def test_largest_lattice_limit():
+    """Population indices are 32-bit: (q + 3) x the node count, rounded up to whole node
+    blocks, must stay below 2^31.  Sizes are computed only; nothing is allocated."""
+    import paper_1601_00704_amd.glbm as g
+    ny = 16384                                    # D2Q9: q + 3 = 12
+    assert 12 * ny * 10240 < 1 << 31 <= 12 * ny * 11264
+    assert g.glbm_required_bytes([_desc(g, shape=(ny, 10240))]) > 0
+    assert g.glbm_required_bytes([_desc(g, shape=(ny, 11264))]) == 0
+    assert "32-bit" in g.glbm_last_error()
+    # D3Q19 (q + 3 = 22): 448^3 fits, 480^3 does not
+    assert g.glbm_required_bytes([_desc(g, shape=(448, 448, 448), lattice=g.GLBM_D3Q19)]) > 0
+    assert g.glbm_required_bytes([_desc(g, shape=(480, 480, 480), lattice=g.GLBM_D3Q19)]) == 0
