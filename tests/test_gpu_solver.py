@@ -411,3 +411,27 @@ def test_batch_f16loc_largest_member_one_step_sampled(gpu):
         local = np.abs(want - w * rho_w).max()
         scale = np.abs(want - w).max()
         assert np.abs(f1[:, node] - want).max() <= 2.0 ** -10 * local + 1e-6 * scale + 1e-13, node
+
+
+@pytest.mark.parametrize("store", ["f64", "f32"])
+def test_degenerate_open_pore_domain(gpu, store):
+    """No matrix at all (eps = 1, K infinite everywhere, periodic): nothing resists the body
+    force, so there is no steady state.  With Guo forcing the momentum grows by rho G per
+    step from rest, so u(t) = G (t + 1/2) at every node, rho stays 1, and a solve with a
+    tolerance ends ENOTCONVERGED."""
+    g = gpu
+    cls = si.uniform_classes((16, 64), 0)
+    eps, k = np.ones(256), np.full(256, np.inf)
+    G = (1e-6, -2.5e-7, 0.0)
+    s = gpu_solver(g, 9, cls, eps, k, G=G, store=store)
+    try:
+        assert s.step(300, tol=1e-8) == g.GLBM_ENOTCONVERGED
+        rho, u = s.fields()
+        _, st = s.residual()
+    finally:
+        s.close()
+    t = float(st[0])
+    tol = 1e-12 if store == "f64" else 1e-5
+    for a in range(2):
+        assert np.allclose(u[a], G[a] * (t + 0.5), rtol=tol, atol=0), (a, u[a][:3], G[a] * (t + 0.5))
+    assert np.abs(rho - 1.0).max() < (1e-14 if store == "f64" else 1e-6)
