@@ -6,6 +6,9 @@ followed by the FP64 residual and Darcy-flux reductions of that state, all in
 the HIP library.  The workload is a 4096 x 4096 D2Q9 shale map (seeded QSGS,
 60% solid, TOC 0.10, methane at 400 K and 10 MPa) with FP32 populations.
 
+The tile shape and cache policy of the sweep are chosen by the library's
+autotuner (glbm_autotune) before the warm-up, or given with --tile.
+
 Reported (one JSON line):
   value        lattice updates per second over the timed steps (MLUPS)
   roofline     the sweep kernel's algorithmic HBM bytes per launch
@@ -167,6 +170,23 @@ DTYPE = {"f32": "f32", "f16dev": "f32 math / f16 storage", "f16loc": "f32 math /
          "f64": "f64"}
 
 
+def _choose_tile(s, g, args):
+    """Tile shape and cache policy: given with --tile, else picked by glbm_autotune
+    (unless --no-autotune); returns the config record or None (library defaults)."""
+    if args.tile:
+        s.set_option(g.GLBM_OPT_TILE_WIDTH, args.tile[0])
+        s.set_option(g.GLBM_OPT_TILE_ROWS, args.tile[1])
+        s.set_option(g.GLBM_OPT_CACHE, args.tile[2])
+        return {"width": args.tile[0], "rows": args.tile[1], "cache_policy": args.tile[2], "by": "--tile"}
+    if args.no_autotune:
+        return None
+    t0 = time.perf_counter()
+    ch = g.glbm_autotune(s.ctx, 20)
+    print("autotune: width %d rows %d cache %d (%.1fs)" % (ch[0], ch[1], ch[2], time.perf_counter() - t0),
+          file=sys.stderr, flush=True)
+    return {"width": int(ch[0]), "rows": int(ch[1]), "cache_policy": int(ch[2]), "by": "glbm_autotune"}
+
+
 def _timed_chunks(s, g, steps, warmup, graph):
     """Warm up, then time `steps` chunks of N_C sweeps + the FP64 check."""
     import torch
@@ -218,16 +238,7 @@ def run_batch(args):
     N = int(sum(m.size for m in maps))
     print("setup: %d instances, %d nodes, maps in %.1fs, store %s" % (len(maps), N, t_geom, args.store),
           file=sys.stderr, flush=True)
-    chosen = None
-    if args.tile:
-        s.set_option(g.GLBM_OPT_TILE_WIDTH, args.tile[0])
-        s.set_option(g.GLBM_OPT_TILE_ROWS, args.tile[1])
-        s.set_option(g.GLBM_OPT_CACHE, args.tile[2])
-    elif not args.no_autotune:
-        t0 = time.perf_counter()
-        chosen = g.glbm_autotune(s.ctx, 10)
-        print("autotune: width %d rows %d cache %d (%.1fs)" % (chosen[0], chosen[1], chosen[2],
-                                                            time.perf_counter() - t0), file=sys.stderr, flush=True)
+    tile = _choose_tile(s, g, args)
     wall = _timed_chunks(s, g, args.steps, args.warmup, graph=True)
     per_launch, launches = _sweep_mean_ms(s, g)
     r, st = s.residual()
@@ -239,10 +250,7 @@ def run_batch(args):
                        "P_L U(2,8) MPa, V_L U(0.002,0.008) m3/kg; %s populations; one HIP graph per "
                        "n_c=%d-sweep chunk + FP64 per-instance checks" % (len(maps), sides, args.store.upper(), N_C),
            "instances": len(maps), "nodes": N, "sweeps_per_step": N_C, "graph": True,
-           "tile": ({"width": args.tile[0], "rows": args.tile[1], "cache_policy": args.tile[2], "by": "--tile"}
-                    if args.tile else None if chosen is None else
-                    {"width": int(chosen[0]), "rows": int(chosen[1]), "cache_policy": int(chosen[2]),
-                     "by": "glbm_autotune"}),
+           "tile": tile,
            "median_residual": float(np.median(r)), "steps_total": int(st.max())}
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
             "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic_from_profile(workload_key(args)[0]),
@@ -272,6 +280,7 @@ def run_d3q19(args):
     s.set_local_perm(eps[:255], kl[:255])
     N = cls.size
     print("setup: %s map in %.1fs" % (cls.shape, t_geom), file=sys.stderr, flush=True)
+    tile = _choose_tile(s, g, args)
     wall = _timed_chunks(s, g, args.steps, args.warmup, graph=False)
     ms, n = g.glbm_sweep_time(s.ctx)
     per_launch = ms / max(n, 1)
@@ -304,7 +313,7 @@ def run_d3q19(args):
     cfg = {"workload": "D3Q19 GLBM %d^3, 3-D QSGS 55%% solid, TOC 0.20, CH4 400 K 20 MPa, drive z, walls on x/y "
                        "faces, %s populations" % (args.side3, args.store.upper()),
            "nodes": N, "sweeps_per_step": N_C, "steps_total": int(st[0]), "residual": float(r[0]),
-           "k_lattice_z": float(kk[2])}
+           "k_lattice_z": float(kk[2]), "tile": tile}
     if conv:
         cfg["time_to_converge"] = conv
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
@@ -402,9 +411,9 @@ def main():
     ap.add_argument("--cnn-batch", type=int, default=8)
     ap.add_argument("--cnn-side", type=int, default=512)
     ap.add_argument("--batch", type=int, default=256)
-    ap.add_argument("--no-autotune", action="store_true", help="batch: keep the default tile shape")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the library's default tile shape")
     ap.add_argument("--tile", type=int, nargs=3, metavar=("WIDTH", "ROWS", "CACHE"),
-                    help="batch: use this tile shape and cache policy instead of the autotuner's")
+                    help="use this tile shape and cache policy instead of the autotuner's")
     ap.add_argument("--map-procs", type=int, default=0,
                     help="worker processes for the batch's maps (0: one per core, at most 16)")
     ap.add_argument("--side3", type=int, default=256)
@@ -452,11 +461,12 @@ def main():
     d = g.make_desc(cls.shape, store=store, tau=inst.tau, g=inst.gvec(), check_every=N_C)
     s = g.Solver([d], [cls])
     s.set_local_perm(eps[:255], kl[:255])
-    s.set_option(g.GLBM_OPT_GRAPH, 0)
-    s.set_option(g.GLBM_OPT_TIMING, 1)
     N = cls.size
     print("setup: %dx%d map in %.1fs, store %s" % (args.side, args.side, t_geom, args.store),
           file=sys.stderr, flush=True)
+    tile = _choose_tile(s, g, args)
+    s.set_option(g.GLBM_OPT_GRAPH, 0)
+    s.set_option(g.GLBM_OPT_TIMING, 1)
 
     for w in range(args.warmup):
         s.step(N_C)
@@ -497,7 +507,7 @@ def main():
                                "populations, n_c=%d sweeps + FP64 residual/flux per step"
                                % (args.side, args.side, args.store.upper(), N_C),
                    "nodes": N, "sweeps_per_step": N_C, "steps_total": int(st[0]),
-                   "residual": float(r[0]), "k_lattice": float(kk[0])},
+                   "residual": float(r[0]), "k_lattice": float(kk[0]), "tile": tile},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": round(achieved / PEAK_HBM_GBS, 4),
                      "traffic": traffic,
