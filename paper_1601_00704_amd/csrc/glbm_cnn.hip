@@ -441,19 +441,51 @@ struct View {
 };
 
 // y (H/2 x W/2) = mean of 2x2 blocks of x (H x W); channels c < C
+// The pooling, upsampling and ReLU-mask kernels move 8 channels (16 bytes) per
+// thread; channel counts, pitches and offsets are multiples of 8 throughout the
+// network.
+__device__ __forceinline__ void unpack8(const uint4& v, float (&f)[8])
+{
+    const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        f[2 * i] = __uint_as_float(w[i] << 16);
+        f[2 * i + 1] = __uint_as_float(w[i] & 0xffff0000u);
+    }
+}
+__device__ __forceinline__ uint4 pack8(const float (&f)[8])
+{
+    uint32_t w[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) w[i] = uint32_t(f2bf(f[2 * i])) | (uint32_t(f2bf(f[2 * i + 1])) << 16);
+    return make_uint4(w[0], w[1], w[2], w[3]);
+}
+__device__ __forceinline__ uint4 ld8(const uint16_t* p) { return *reinterpret_cast<const uint4*>(p); }
+__device__ __forceinline__ void st8(uint16_t* p, const uint4& v) { *reinterpret_cast<uint4*>(p) = v; }
+
+// y (H/2 x W/2) = mean of 2x2 blocks of x (H x W); channels c < C
 __global__ void k_pool_fwd(const uint16_t* x, int xp, int xo, uint16_t* y, int yp, int yo, int C, int B, int H, int W)
 {
     const long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-    const int H2 = H / 2, W2 = W / 2;
-    const long long total = (long long)B * H2 * W2 * C;
+    const int H2 = H / 2, W2 = W / 2, C8 = C >> 3;
+    const long long total = (long long)B * H2 * W2 * C8;
     if (idx >= total) return;
-    const int c = int(idx % C);
-    const long long q = idx / C;
+    const int c = int(idx % C8) * 8;
+    const long long q = idx / C8;
     const int x2 = int(q % W2), y2 = int((q / W2) % H2), b = int(q / ((long long)W2 * H2));
     const size_t base = ((size_t)b * H + 2 * y2) * W + 2 * x2;
-    const float s = bf2f(x[base * xp + xo + c]) + bf2f(x[(base + 1) * xp + xo + c]) +
-                    bf2f(x[(base + W) * xp + xo + c]) + bf2f(x[(base + W + 1) * xp + xo + c]);
-    y[(size_t)q * yp + yo + c] = f2bf(0.25f * s);
+    float a[8], t[8];
+    unpack8(ld8(x + base * xp + xo + c), a);
+    unpack8(ld8(x + (base + 1) * xp + xo + c), t);
+#pragma unroll
+    for (int i = 0; i < 8; ++i) a[i] += t[i];
+    unpack8(ld8(x + (base + W) * xp + xo + c), t);
+#pragma unroll
+    for (int i = 0; i < 8; ++i) a[i] += t[i];
+    unpack8(ld8(x + (base + W + 1) * xp + xo + c), t);
+#pragma unroll
+    for (int i = 0; i < 8; ++i) a[i] = 0.25f * (a[i] + t[i]);
+    st8(y + (size_t)q * yp + yo + c, pack8(a));
 }
 
 // dx (H x W) (+)= dy (H/2 x W/2) / 4 broadcast
@@ -461,55 +493,84 @@ __global__ void k_pool_bwd(const uint16_t* dy, int yp, int yo, uint16_t* dx, int
                            int acc)
 {
     const long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-    const long long total = (long long)B * H * W * C;
+    const int C8 = C >> 3;
+    const long long total = (long long)B * H * W * C8;
     if (idx >= total) return;
-    const int c = int(idx % C);
-    const long long q = idx / C;
+    const int c = int(idx % C8) * 8;
+    const long long q = idx / C8;
     const int x = int(q % W), y = int((q / W) % H), b = int(q / ((long long)W * H));
     const size_t qs = ((size_t)b * (H / 2) + y / 2) * (W / 2) + x / 2;
-    float v = 0.25f * bf2f(dy[qs * yp + yo + c]);
+    float v[8];
+    unpack8(ld8(dy + qs * yp + yo + c), v);
     uint16_t* o = dx + (size_t)q * xp + xo + c;
-    if (acc) v += bf2f(*o);
-    *o = f2bf(v);
+    float t[8];
+    if (acc) unpack8(ld8(o), t);
+#pragma unroll
+    for (int i = 0; i < 8; ++i) v[i] = 0.25f * v[i] + (acc ? t[i] : 0.f);
+    st8(o, pack8(v));
 }
 
 // y (2H x 2W) = nearest upsample of x (H x W)
 __global__ void k_up_fwd(const uint16_t* x, int xp, int xo, uint16_t* y, int yp, int yo, int C, int B, int H, int W)
 {
     const long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-    const long long total = (long long)B * 4 * H * W * C;
+    const int C8 = C >> 3;
+    const long long total = (long long)B * 4 * H * W * C8;
     if (idx >= total) return;
-    const int c = int(idx % C);
-    const long long q = idx / C;
+    const int c = int(idx % C8) * 8;
+    const long long q = idx / C8;
     const int X = int(q % (2 * W)), Y = int((q / (2 * W)) % (2 * H)), b = int(q / (4LL * W * H));
     const size_t qs = ((size_t)b * H + Y / 2) * W + X / 2;
-    y[(size_t)q * yp + yo + c] = x[qs * xp + xo + c];
+    st8(y + (size_t)q * yp + yo + c, ld8(x + qs * xp + xo + c));
 }
 
 // dx (H x W) = sum of the 2x2 block of dy (2H x 2W)
 __global__ void k_up_bwd(const uint16_t* dy, int yp, int yo, uint16_t* dx, int xp, int xo, int C, int B, int H, int W)
 {
     const long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-    const long long total = (long long)B * H * W * C;
+    const int C8 = C >> 3;
+    const long long total = (long long)B * H * W * C8;
     if (idx >= total) return;
-    const int c = int(idx % C);
-    const long long q = idx / C;
+    const int c = int(idx % C8) * 8;
+    const long long q = idx / C8;
     const int x = int(q % W), y = int((q / W) % H), b = int(q / ((long long)W * H));
     const size_t base = ((size_t)b * 2 * H + 2 * y) * 2 * W + 2 * x;
     const size_t W2 = 2 * (size_t)W;
-    const float s = bf2f(dy[base * yp + yo + c]) + bf2f(dy[(base + 1) * yp + yo + c]) +
-                    bf2f(dy[(base + W2) * yp + yo + c]) + bf2f(dy[(base + W2 + 1) * yp + yo + c]);
-    dx[(size_t)q * xp + xo + c] = f2bf(s);
+    float a[8], t[8];
+    unpack8(ld8(dy + base * yp + yo + c), a);
+    unpack8(ld8(dy + (base + 1) * yp + yo + c), t);
+#pragma unroll
+    for (int i = 0; i < 8; ++i) a[i] += t[i];
+    unpack8(ld8(dy + (base + W2) * yp + yo + c), t);
+#pragma unroll
+    for (int i = 0; i < 8; ++i) a[i] += t[i];
+    unpack8(ld8(dy + (base + W2 + 1) * yp + yo + c), t);
+#pragma unroll
+    for (int i = 0; i < 8; ++i) a[i] += t[i];
+    st8(dx + (size_t)q * xp + xo + c, pack8(a));
 }
 
 // dy *= (y > 0), channel slice of each
 __global__ void k_relu_mask(uint16_t* dy, int dp, int dof, const uint16_t* y, int yp, int yo, int C, long long npix)
 {
     const long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-    if (idx >= npix * C) return;
-    const int c = int(idx % C);
-    const long long q = idx / C;
-    if (!(bf2f(y[(size_t)q * yp + yo + c]) > 0.f)) dy[(size_t)q * dp + dof + c] = 0;
+    const int C8 = C >> 3;
+    if (idx >= npix * C8) return;
+    const int c = int(idx % C8) * 8;
+    const long long q = idx / C8;
+    float yv[8], g[8];
+    unpack8(ld8(y + (size_t)q * yp + yo + c), yv);
+    uint16_t* o = dy + (size_t)q * dp + dof + c;
+    const uint4 gv = ld8(o);
+    unpack8(gv, g);
+    uint32_t w[4] = {gv.x, gv.y, gv.z, gv.w};
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        if (!(yv[2 * i] > 0.f)) w[i] &= 0xffff0000u;
+        if (!(yv[2 * i + 1] > 0.f)) w[i] &= 0x0000ffffu;
+    }
+    (void)g;
+    st8(o, make_uint4(w[0], w[1], w[2], w[3]));
 }
 
 // masked MSE over channels 0..2: loss partials per block and dL/dout as bf16 [npix][16]
@@ -877,19 +938,19 @@ int forward(glbm_cnn c, const uint16_t* x, int B)
     if (rc) return rc;
     CV(0, x, 8, 0, c->a0, 32, 0, H, W);
     CV(1, c->a0, 32, 0, c->c1, 96, 0, H, W);  // e1 -> c1[0:32]
-    hipLaunchKernelGGL(k_pool_fwd, dim3(nblocks((long long)B * H1 * W1 * 32)), dim3(256), 0, s, c->c1, 96, 0, c->p1, 32,
+    hipLaunchKernelGGL(k_pool_fwd, dim3(nblocks((long long)B * H1 * W1 * 32 / 8)), dim3(256), 0, s, c->c1, 96, 0, c->p1, 32,
                        0, 32, B, H, W);
     CV(2, c->p1, 32, 0, c->a2, 64, 0, H1, W1);
     CV(3, c->a2, 64, 0, c->c2, 192, 0, H1, W1);  // e2 -> c2[0:64]
-    hipLaunchKernelGGL(k_pool_fwd, dim3(nblocks((long long)B * H2 * W2 * 64)), dim3(256), 0, s, c->c2, 192, 0, c->p2, 64,
+    hipLaunchKernelGGL(k_pool_fwd, dim3(nblocks((long long)B * H2 * W2 * 64 / 8)), dim3(256), 0, s, c->c2, 192, 0, c->p2, 64,
                        0, 64, B, H1, W1);
     CV(4, c->p2, 64, 0, c->a4, 128, 0, H2, W2);
     CV(5, c->a4, 128, 0, c->e3, 128, 0, H2, W2);
-    hipLaunchKernelGGL(k_up_fwd, dim3(nblocks((long long)B * 4 * H2 * W2 * 128)), dim3(256), 0, s, c->e3, 128, 0, c->c2,
+    hipLaunchKernelGGL(k_up_fwd, dim3(nblocks((long long)B * 4 * H2 * W2 * 128 / 8)), dim3(256), 0, s, c->e3, 128, 0, c->c2,
                        192, 64, 128, B, H2, W2);
     CV(6, c->c2, 192, 0, c->a6, 64, 0, H1, W1);
     CV(7, c->a6, 64, 0, c->d2, 64, 0, H1, W1);
-    hipLaunchKernelGGL(k_up_fwd, dim3(nblocks((long long)B * 4 * H1 * W1 * 64)), dim3(256), 0, s, c->d2, 64, 0, c->c1, 96,
+    hipLaunchKernelGGL(k_up_fwd, dim3(nblocks((long long)B * 4 * H1 * W1 * 64 / 8)), dim3(256), 0, s, c->d2, 64, 0, c->c1, 96,
                        32, 64, B, H1, W1);
     CV(8, c->c1, 96, 0, c->a8, 32, 0, H, W);
 #undef CV
@@ -915,7 +976,8 @@ int bwd_weight(glbm_cnn c, int li, const uint16_t* x, int xp, int xo, const uint
 
 int relu_mask(glbm_cnn c, uint16_t* dy, int dp, int dof, const uint16_t* y, int yp, int yo, int C, long long npix)
 {
-    hipLaunchKernelGGL(k_relu_mask, dim3(nblocks(npix * C)), dim3(256), 0, c->s, dy, dp, dof, y, yp, yo, C, npix);
+    if ((C | dp | dof | yp | yo) & 7) return cfail(GLBM_EINVAL, "relu mask: channels, pitches and offsets must be multiples of 8");
+    hipLaunchKernelGGL(k_relu_mask, dim3(nblocks(npix * C / 8)), dim3(256), 0, c->s, dy, dp, dof, y, yp, yo, C, npix);
     CHK(hipGetLastError());
     return GLBM_OK;
 }
@@ -948,7 +1010,7 @@ int backward(glbm_cnn c, const uint16_t* x, const float* target, const uint8_t* 
     if ((rc = bwd_weight(c, 8, c->c1, 96, 0, c->g_a8, 32, B, H, W))) return rc;
     if ((rc = bwd_data(c, 8, c->g_a8, 32, c->g_c1, 96, 0, false, B, H, W))) return rc;
     // up(d2) -> c1[32:96]
-    hipLaunchKernelGGL(k_up_bwd, dim3(nblocks(n1 * 64)), dim3(256), 0, s, c->g_c1, 96, 32, c->g_d2, 64, 0, 64, B, H1, W1);
+    hipLaunchKernelGGL(k_up_bwd, dim3(nblocks(n1 * 64 / 8)), dim3(256), 0, s, c->g_c1, 96, 32, c->g_d2, 64, 0, 64, B, H1, W1);
     CHK(hipGetLastError());
     // layer 7: a6 -> d2
     if ((rc = relu_mask(c, c->g_d2, 64, 0, c->d2, 64, 0, 64, n1))) return rc;
@@ -959,7 +1021,7 @@ int backward(glbm_cnn c, const uint16_t* x, const float* target, const uint8_t* 
     if ((rc = bwd_weight(c, 6, c->c2, 192, 0, c->g_a6, 64, B, H1, W1))) return rc;
     if ((rc = bwd_data(c, 6, c->g_a6, 64, c->g_c2, 192, 0, false, B, H1, W1))) return rc;
     // up(e3) -> c2[64:192]
-    hipLaunchKernelGGL(k_up_bwd, dim3(nblocks(n2 * 128)), dim3(256), 0, s, c->g_c2, 192, 64, c->g_e3, 128, 0, 128, B, H2,
+    hipLaunchKernelGGL(k_up_bwd, dim3(nblocks(n2 * 128 / 8)), dim3(256), 0, s, c->g_c2, 192, 64, c->g_e3, 128, 0, 128, B, H2,
                        W2);
     CHK(hipGetLastError());
     // layer 5: a4 -> e3
@@ -971,7 +1033,7 @@ int backward(glbm_cnn c, const uint16_t* x, const float* target, const uint8_t* 
     if ((rc = bwd_weight(c, 4, c->p2, 64, 0, c->g_a4, 128, B, H2, W2))) return rc;
     if ((rc = bwd_data(c, 4, c->g_a4, 128, c->g_p2, 64, 0, false, B, H2, W2))) return rc;
     // pool(e2): add into c2[0:64] gradient
-    hipLaunchKernelGGL(k_pool_bwd, dim3(nblocks(n1 * 64)), dim3(256), 0, s, c->g_p2, 64, 0, c->g_c2, 192, 0, 64, B, H1, W1,
+    hipLaunchKernelGGL(k_pool_bwd, dim3(nblocks(n1 * 64 / 8)), dim3(256), 0, s, c->g_p2, 64, 0, c->g_c2, 192, 0, 64, B, H1, W1,
                        1);
     CHK(hipGetLastError());
     // layer 3: a2 -> e2 (c2[0:64])
@@ -982,7 +1044,7 @@ int backward(glbm_cnn c, const uint16_t* x, const float* target, const uint8_t* 
     if ((rc = relu_mask(c, c->g_a2, 64, 0, c->a2, 64, 0, 64, n1))) return rc;
     if ((rc = bwd_weight(c, 2, c->p1, 32, 0, c->g_a2, 64, B, H1, W1))) return rc;
     if ((rc = bwd_data(c, 2, c->g_a2, 64, c->g_p1, 32, 0, false, B, H1, W1))) return rc;
-    hipLaunchKernelGGL(k_pool_bwd, dim3(nblocks(n0 * 32)), dim3(256), 0, s, c->g_p1, 32, 0, c->g_c1, 96, 0, 32, B, H, W, 1);
+    hipLaunchKernelGGL(k_pool_bwd, dim3(nblocks(n0 * 32 / 8)), dim3(256), 0, s, c->g_p1, 32, 0, c->g_c1, 96, 0, 32, B, H, W, 1);
     CHK(hipGetLastError());
     // layer 1: a0 -> e1 (c1[0:32])
     if ((rc = relu_mask(c, c->g_c1, 96, 0, c->c1, 96, 0, 32, n0))) return rc;
