@@ -439,9 +439,9 @@ __device__ __forceinline__ void sweep_tile(const Args& a, const Tile& t, const I
 // One time step of one tile.  Policy bits of a.cache: 0 nontemporal stores,
 // 1 nontemporal loads of x-aligned planes, 2 plain workgroup order (no XCD
 // grouping), 3 per-class constants read through the L1 cache instead of being
-// staged in LDS.  Measured on MI355X (4096^2, FP32): 256 x 1 tiles with bits
-// 0, 2 and 3 run at 5.9 TB/s; staging the table in LDS costs each workgroup
-// a fill and a barrier before its first population load is issued.
+// staged in LDS.  The best setting depends on the layout and the map, and
+// glbm_autotune picks it; on the 4096^2 FP32 map with node blocks it is
+// 512 x 1 tiles with bits 0 and 2 (about 5.9 TB/s of HBM traffic).
 template <int Q, int STORE, int BC, bool FORCH> __device__ __forceinline__ void sweep_block(const Args& a)
 {
     using T = typename St<STORE>::T;
