@@ -90,8 +90,12 @@ typedef struct {
 
 /*
  * Bytes of device memory that the populations of these instances need (both
- * ping-pong buffers, with the library's plane padding).  Returns 0 if the
- * descriptors are invalid.
+ * ping-pong buffers, with the library's padding).  The arrangement inside is
+ * the library's own (node blocks of 4096 nodes for the FP64 and FP32 stores,
+ * planes for the FP16 stores) and may change; read populations with
+ * glbm_get_populations.  Returns 0 if the descriptors are invalid, including
+ * when (q + 3) times the node count, rounded up to whole blocks, reaches 2^31
+ * (32-bit element indices).
  */
 size_t glbm_required_bytes(int32_t n_inst, const glbm_instance_desc* desc);
 
