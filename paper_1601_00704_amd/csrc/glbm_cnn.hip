@@ -156,7 +156,10 @@ __global__ __launch_bounds__(kConvBlock) void k_conv_fwd_tap(ConvArgs a)
 {
     constexpr int kCin = 32 * CI;
     constexpr int kRow = kCin + 8;  // padded LDS row (bf16)
-    __shared__ __attribute__((aligned(16))) uint16_t wt[2][kChTile * kRow];
+    // LDS rows for the weights of one tap: the 64-channel tile, or 32 rows when
+    // the layer has at most 32 output channels (MB = 4)
+    constexpr int kRows = MB == 4 ? 32 : kChTile;
+    __shared__ __attribute__((aligned(16))) uint16_t wt[2][kRows * kRow];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int m = lane & 15, kq = lane >> 4;
     const long long pw = (long long)blockIdx.x * (64 * MB) + wave * (16 * MB);
@@ -186,8 +189,8 @@ __global__ __launch_bounds__(kConvBlock) void k_conv_fwd_tap(ConvArgs a)
 
     for (int tap = 0; tap < 9; ++tap) {
         uint16_t* w = wt[tap & 1];
-        // weights of this tap: rows n0 .. n0 + 63, columns tap * cin .. + cin
-        for (int e = threadIdx.x; e < kChTile * (kCin / 8); e += kConvBlock) {
+        // weights of this tap: the 16 nt rows in use from n0, columns tap * cin .. + cin
+        for (int e = threadIdx.x; e < 16 * nt * (kCin / 8); e += kConvBlock) {
             const int r = e / (kCin / 8), c8 = (e % (kCin / 8)) * 8;
             uint4 v = make_uint4(0, 0, 0, 0);
             if (n0 + r < a.cout_pad)
