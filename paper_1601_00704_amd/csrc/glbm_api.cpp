@@ -263,6 +263,26 @@ int leave(glbm_ctx c)
     return GLBM_OK;
 }
 
+// Joins the work stream back into the caller's stream on every exit path of an
+// entry point that forked it, error returns included; done() joins explicitly
+// and reports the join's own error.
+struct Joined {
+    glbm_ctx c;
+    bool on = true;
+    explicit Joined(glbm_ctx ctx) : c(ctx) {}
+    Joined(const Joined&) = delete;
+    Joined& operator=(const Joined&) = delete;
+    ~Joined()
+    {
+        if (on) (void)leave(c);
+    }
+    int done()
+    {
+        on = false;
+        return leave(c);
+    }
+};
+
 int resolve_timing(glbm_ctx c)
 {
     if (!c->ev_used) return GLBM_OK;
@@ -548,6 +568,7 @@ int glbm_set_local_perm(glbm_ctx c, int32_t inst, int32_t n_classes, const doubl
 
     int rc = enter(c);
     if (rc) return rc;
+    Joined joined(c);
     std::vector<double> row((size_t)kClasses * kTabW, 0.0);
     for (int i = i0; i < i1; ++i) {
         const double nu = c->inst_h[i].nu;
@@ -588,7 +609,7 @@ int glbm_set_local_perm(glbm_ctx c, int32_t inst, int32_t n_classes, const doubl
     }
     c->snap_valid = false;
     free_graph(c);
-    return leave(c);
+    return joined.done();
 }
 
 int glbm_step_n(glbm_ctx c, int64_t n, double tol)
@@ -600,6 +621,7 @@ int glbm_step_n(glbm_ctx c, int64_t n, double tol)
     if (rc) return rc;
     rc = enter(c);
     if (rc) return rc;
+    Joined joined(c);
 
     // (re)activate: everything when tol <= 0, else every instance not already below tol
     for (int i = 0; i < c->n_inst; ++i) {
@@ -678,7 +700,7 @@ int glbm_step_n(glbm_ctx c, int64_t n, double tol)
     set_parities(c);
     rc = upload_state(c);
     if (rc) return rc;
-    rc = leave(c);
+    rc = joined.done();
     if (rc) return rc;
     if (nonfinite) return fail(GLBM_ENONFINITE, "non-finite populations detected");
     if (tol > 0.0 && any_active()) return fail(GLBM_ENOTCONVERGED, "step budget reached before r <= %g", tol);
@@ -706,6 +728,7 @@ int glbm_permeability(glbm_ctx c, double* k)
     if (rc) return rc;
     rc = enter(c);
     if (rc) return rc;
+    Joined joined(c);
     Args a = c->args(c->gstep);
     a.res = c->flux_d;
     HIPCHK(launch_observe(c->cfg, a, 4, c->work));
@@ -721,7 +744,7 @@ int glbm_permeability(glbm_ctx c, double* k)
             k[3 * i + d] = g != 0.0 ? nu * mean / g : NAN;
         }
     }
-    return leave(c);
+    return joined.done();
 }
 
 static int set_fields_impl(glbm_ctx c, int32_t inst, const void* rho_d, const void* u_d, int is_double)
@@ -746,6 +769,7 @@ int glbm_set_fields(glbm_ctx c, int32_t inst, const double* rho, const double* u
     if (rc) return rc;
     rc = enter(c);
     if (rc) return rc;
+    Joined joined(c);
     const InstDev& I = c->inst_h[inst];
     const size_t n = (size_t)I.nx * I.ny * I.nz;
     double* d = nullptr;
@@ -761,7 +785,7 @@ int glbm_set_fields(glbm_ctx c, int32_t inst, const double* rho, const double* u
     (void)hipFree(d);
     if (rc) return rc;
     HIPCHK(es);
-    return leave(c);
+    return joined.done();
 }
 
 int glbm_set_fields_device(glbm_ctx c, int32_t inst, const float* rho_dev, const float* u_dev)
@@ -774,9 +798,10 @@ int glbm_set_fields_device(glbm_ctx c, int32_t inst, const float* rho_dev, const
     if (rc) return rc;
     rc = enter(c);
     if (rc) return rc;
+    Joined joined(c);
     rc = set_fields_impl(c, inst, rho_dev, u_dev, 0);
     if (rc) return rc;
-    return leave(c);
+    return joined.done();
 }
 
 static int get_impl(glbm_ctx c, int32_t inst, double* rho, double* u, double* pops)
@@ -787,6 +812,7 @@ static int get_impl(glbm_ctx c, int32_t inst, double* rho, double* u, double* po
     if (rc) return rc;
     rc = enter(c);
     if (rc) return rc;
+    Joined joined(c);
     const InstDev& I = c->inst_h[inst];
     const size_t n = (size_t)I.nx * I.ny * I.nz;
     const size_t q = (size_t)c->cfg.q;
@@ -802,7 +828,7 @@ static int get_impl(glbm_ctx c, int32_t inst, double* rho, double* u, double* po
     (void)hipFree(d);
     if (e != hipSuccess) return fail(GLBM_EDEVICE, "get fields: %s", hipGetErrorString(e));
     HIPCHK(es);
-    return leave(c);
+    return joined.done();
 }
 
 int glbm_get_fields(glbm_ctx c, int32_t inst, double* rho, double* u)
@@ -840,6 +866,7 @@ int glbm_save_state(glbm_ctx c, void* host, size_t bytes)
     if (bytes < glbm_state_bytes(c)) return fail(GLBM_ENOMEM, "buffer too small");
     int rc = enter(c);
     if (rc) return rc;
+    Joined joined(c);
     char* p = static_cast<char*>(host);
     CkptHeader h{kMagic, c->pop_bytes, (uint64_t)c->snap_elems * c->tsz, (uint64_t)c->n_inst, c->gstep,
                  c->snap_valid ? 1 : 0, 0};
@@ -855,7 +882,7 @@ int glbm_save_state(glbm_ctx c, void* host, size_t bytes)
     memcpy(p, c->steps.data(), c->n_inst * sizeof(int64_t));
     p += c->n_inst * sizeof(int64_t);
     memcpy(p, c->snap_step.data(), c->n_inst * sizeof(int64_t));
-    return leave(c);
+    return joined.done();
 }
 
 int glbm_load_state(glbm_ctx c, const void* host, size_t bytes)
@@ -871,6 +898,7 @@ int glbm_load_state(glbm_ctx c, const void* host, size_t bytes)
         return fail(GLBM_EINVAL, "checkpoint does not match this context");
     int rc = enter(c);
     if (rc) return rc;
+    Joined joined(c);
     p += sizeof h;
     HIPCHK(hipMemcpyAsync(c->pop_base, p, c->pop_bytes, hipMemcpyHostToDevice, c->work));
     p += c->pop_bytes;
@@ -890,7 +918,7 @@ int glbm_load_state(glbm_ctx c, const void* host, size_t bytes)
     rc = upload_state(c);
     if (rc) return rc;
     free_graph(c);
-    return leave(c);
+    return joined.done();
 }
 
 int glbm_set_option(glbm_ctx c, int32_t option, int64_t value)
@@ -1051,6 +1079,7 @@ int glbm_cnn_features(glbm_ctx c, int32_t inst, double log10_pressure_mpa, uint1
     }
     rc = enter(c);
     if (rc) return rc;
+    Joined joined(c);
     float* d = nullptr;
     HIPCHK(hipMalloc(&d, tab.size() * sizeof(float)));
     const InstDev& I = c->inst_h[inst];
@@ -1061,7 +1090,7 @@ int glbm_cnn_features(glbm_ctx c, int32_t inst, double log10_pressure_mpa, uint1
     (void)hipFree(d);
     if (e != hipSuccess) return fail(GLBM_EDEVICE, "features: %s", hipGetErrorString(e));
     HIPCHK(es);
-    return leave(c);
+    return joined.done();
 }
 
 int glbm_cnn_targets(glbm_ctx c, int32_t inst, double rho_scale, double u_scale, float* target, uint8_t* mask)
@@ -1074,6 +1103,7 @@ int glbm_cnn_targets(glbm_ctx c, int32_t inst, double rho_scale, double u_scale,
     if (rc) return rc;
     rc = enter(c);
     if (rc) return rc;
+    Joined joined(c);
     const InstDev& I = c->inst_h[inst];
     const long long n = (long long)I.nx * I.ny * I.nz;
     double* d = nullptr;
@@ -1085,7 +1115,7 @@ int glbm_cnn_targets(glbm_ctx c, int32_t inst, double rho_scale, double u_scale,
     (void)hipFree(d);
     if (e != hipSuccess) return fail(GLBM_EDEVICE, "targets: %s", hipGetErrorString(e));
     HIPCHK(es);
-    return leave(c);
+    return joined.done();
 }
 
 int glbm_cnn_apply(glbm_ctx c, int32_t inst, const float* y, double rho_scale, double u_scale)
@@ -1097,6 +1127,7 @@ int glbm_cnn_apply(glbm_ctx c, int32_t inst, const float* y, double rho_scale, d
     if (rc) return rc;
     rc = enter(c);
     if (rc) return rc;
+    Joined joined(c);
     const InstDev& I = c->inst_h[inst];
     const long long n = (long long)I.nx * I.ny * I.nz;
     float* d = nullptr;
@@ -1107,7 +1138,7 @@ int glbm_cnn_apply(glbm_ctx c, int32_t inst, const float* y, double rho_scale, d
     (void)hipFree(d);
     if (rc) return rc;
     HIPCHK(es);
-    return leave(c);
+    return joined.done();
 }
 
 int glbm_velocity_set(int32_t lattice, int32_t* e, double* w)
