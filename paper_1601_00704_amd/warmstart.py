@@ -140,6 +140,8 @@ def evaluate(cnn, insts, maps, tol, max_steps, ctx_size, G, H, W, store, trace_e
     traces = {}
     xb = torch.empty((1, H, W, 8), dtype=torch.int16, device="cuda")
     yb = torch.empty((1, H, W, 4), dtype=torch.float32, device="cuda")
+    tb = torch.empty((1, H, W, 4), dtype=torch.float32, device="cuda")
+    mb = torch.empty((1, H, W), dtype=torch.uint8, device="cuda")
     for c0 in range(0, len(insts), ctx_size):
         sub, sm = insts[c0:c0 + ctx_size], maps[c0:c0 + ctx_size]
         te = trace_every if c0 == 0 else 0
@@ -148,16 +150,23 @@ def evaluate(cnn, insts, maps, tol, max_steps, ctx_size, G, H, W, store, trace_e
         if te:
             traces["cold"] = cold.trace
         kc = cold.s.permeability()[:, 0]
+        truth = []
+        for j in range(len(sub)):
+            g.glbm_cnn_targets(cold.s.ctx, j, s_rho, s_u, tb.data_ptr(), mb.data_ptr())
+            truth.append((tb.cpu().numpy().reshape(H, W, 4).copy(), mb.cpu().numpy().reshape(H, W).copy()))
         cold.close()
         warm = Batch(sub, sm, store)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
+        preds = []
         for j, inst in enumerate(sub):
             g.glbm_cnn_features(warm.s.ctx, j, math.log10(inst.pressure / 1e6), xb.data_ptr())
             g.glbm_cnn_forward(cnn, xb.data_ptr(), yb.data_ptr(), 1)
             g.glbm_cnn_apply(warm.s.ctx, j, yb.data_ptr(), s_rho, s_u)
+            preds.append(yb.clone())
         torch.cuda.synchronize()
         ti = time.perf_counter() - t0
+        errs = [prediction_errors(p.cpu().numpy().reshape(H, W, 4), *truth[j]) for j, p in enumerate(preds)]
         ww, rcw, rw, stw = warm.solve(tol, max_steps, te)
         if te:
             traces["warm"] = warm.trace
@@ -170,10 +179,26 @@ def evaluate(cnn, insts, maps, tol, max_steps, ctx_size, G, H, W, store, trace_e
             out.append({"seed": inst.seed, "cold_steps": int(stc[j]), "warm_steps": int(stw[j]),
                         "k_cold": float(kc[j]), "k_warm": float(kw[j]),
                         "k_rel_diff": float(abs(kw[j] - kc[j]) / abs(kc[j])),
-                        "cold_residual": float(rc_[j]), "warm_residual": float(rw[j])})
+                        "cold_residual": float(rc_[j]), "warm_residual": float(rw[j]), **errs[j]})
         print("evaluated %d/%d: cold %.1fs, warm %.1fs + inference %.2fs" % (c0 + len(sub), len(insts), wc, ww, ti),
               flush=True)
     return out, cold_wall, warm_wall, infer_wall, traces
+
+
+def prediction_errors(y, target, mask, block=16):
+    """Relative L2 errors of a prediction against the converged fields (normalised units,
+    fluid nodes): density, velocity, and the density averaged over block x block tiles
+    (the large-scale part that sets how long the solve still takes)."""
+    m = mask.astype(bool)
+    d0, t0 = (y[..., 0] - target[..., 0]) * m, target[..., 0] * m
+    du, tu = (y[..., 1:3] - target[..., 1:3]) * m[..., None], target[..., 1:3] * m[..., None]
+    H, W = m.shape
+
+    def coarse(a):
+        return a.reshape(H // block, block, W // block, block).mean(axis=(1, 3))
+    return {"rho_rel_err": float(np.linalg.norm(d0) / max(np.linalg.norm(t0), 1e-300)),
+            "u_rel_err": float(np.linalg.norm(du) / max(np.linalg.norm(tu), 1e-300)),
+            "rho_coarse_rel_err": float(np.linalg.norm(coarse(d0)) / max(np.linalg.norm(coarse(t0)), 1e-300))}
 
 
 def main(argv=None):
@@ -232,6 +257,9 @@ def main(argv=None):
         "steps_ratio_median": float(np.median(cs / np.maximum(ws, 1))),
         "steps_cold_median": float(np.median(cs)), "steps_warm_median": float(np.median(ws)),
         "k_rel_diff_max": float(kd.max()), "k_rel_diff_median": float(np.median(kd)),
+        "rho_rel_err_median": float(np.median([r["rho_rel_err"] for r in res])),
+        "u_rel_err_median": float(np.median([r["u_rel_err"] for r in res])),
+        "rho_coarse_rel_err_median": float(np.median([r["rho_coarse_rel_err"] for r in res])),
         "eval_store": args.eval_store or args.store, "traces": traces,
         "per_instance": res,
     }
