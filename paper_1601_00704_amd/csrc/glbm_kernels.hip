@@ -23,6 +23,8 @@
 
 #include <hip/hip_fp16.h>
 
+#include <type_traits>
+
 namespace glbm {
 namespace {
 
@@ -32,6 +34,7 @@ namespace {
 // opposite pairs.  Weights: D2Q9 4/9, 1/9, 1/36; D3Q19 1/3, 1/18, 1/36.
 template <int Q> struct Lat;
 template <> struct Lat<9> {
+    static constexpr int D = 2;
     static constexpr int ex(int i) { constexpr int a[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1}; return a[i]; }
     static constexpr int ey(int i) { constexpr int a[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1}; return a[i]; }
     static constexpr int ez(int) { return 0; }
@@ -39,6 +42,7 @@ template <> struct Lat<9> {
     static constexpr double w(int i) { return i == 0 ? 4.0 / 9.0 : (i < 5 ? 1.0 / 9.0 : 1.0 / 36.0); }
 };
 template <> struct Lat<19> {
+    static constexpr int D = 3;
     static constexpr int ex(int i) {
         constexpr int a[19] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
         return a[i];
@@ -123,6 +127,18 @@ template <typename T> __device__ __forceinline__ T recip(T x)
     }
 }
 
+// Element i of a uniform base, addressed by a 32-bit unsigned byte offset
+// (base + zero-extended offset: one vector instruction per access instead of
+// a sign extension and a 64-bit add).  Valid while i * sizeof(V) < 2^32,
+// which the host's size check guarantees for a population buffer.  The FP16
+// stores (planes) are bound by vector instructions and use it; the FP32 and
+// FP64 stores keep 64-bit per-lane addresses, which measured faster there.
+template <typename V> __device__ __forceinline__ V* elem(V* base, uint32_t i)
+{
+    using B = typename std::conditional<std::is_const<V>::value, const char, char>::type;
+    return reinterpret_cast<V*>(reinterpret_cast<B*>(base) + i * uint32_t(sizeof(V)));
+}
+
 // Element index of population i of node n (layout: glbm_internal.h).
 template <int Q, int STORE> __device__ __forceinline__ int pidx(int i, int n, int stride)
 {
@@ -198,9 +214,14 @@ __device__ __forceinline__ void gather(typename St<STORE>::T (&d)[Q], typename S
             }
         }
         // planes without an x shift are read by exactly one wavefront per cache line
-        const SV raw = (ex == 0 && nt_aligned) ? __builtin_nontemporal_load(src + idx) : src[idx];
+        const SV* at;
+        if constexpr (node_blocks(STORE))
+            at = src + idx;
+        else
+            at = elem(src, uint32_t(idx));
+        const SV raw = (ex == 0 && nt_aligned) ? __builtin_nontemporal_load(at) : *at;
         d[i] = S::dec(raw, I.inv_scale);
-        if constexpr (S::kRho) r[i] = rho_plane<STORE>(src, Q, stride)[node];
+        if constexpr (S::kRho) r[i] = *elem(rho_plane<STORE>(src, Q, stride), uint32_t(node));
     }
 }
 
@@ -211,9 +232,9 @@ template <int Q, typename T>
 __device__ __forceinline__ T localize(T (&d)[Q], const T (&r)[Q])
 {
     using L = Lat<Q>;
-    T a = 0, b = 0;
+    T a = T(L::w(0)) * r[0], b = d[0];
 #pragma unroll
-    for (int i = 0; i < Q; ++i) {
+    for (int i = 1; i < Q; ++i) {
         a += T(L::w(i)) * r[i];
         b += d[i];
     }
@@ -223,63 +244,6 @@ __device__ __forceinline__ T localize(T (&d)[Q], const T (&r)[Q])
     return drho;
 }
 
-// Moments and force of one node: Eq. (32)-(35) and (27)-(28) on deviations.
-template <int Q, typename T, bool FORCH> struct Node {
-    T drho, rho, u[3], F[3];
-    __device__ __forceinline__ void moments(const T (&d)[Q], const T* tab, const T g[3])
-    {
-        T dr = 0;
-#pragma unroll
-        for (int i = 0; i < Q; ++i) dr += d[i];
-        moments_with(d, dr, tab, g);
-    }
-    // d: deviations (or local parts e_i, whose momentum is the same), dr: rho - 1
-    __device__ __forceinline__ void moments_with(const T (&d)[Q], T dr, const T* tab, const T g[3])
-    {
-        using L = Lat<Q>;
-        // Opposite populations share their density part w_i drho; summing the
-        // momentum as differences of opposite pairs cancels it exactly (each
-        // difference of two close values is exact in floating point) before
-        // anything is rounded.
-        T j[3] = {0, 0, 0};
-        drho = dr;
-#pragma unroll
-        for (int i = 1; i < Q; ++i) {
-            const int o = L::opp(i);
-            const bool lead = L::ex(i) > 0 || (L::ex(i) == 0 && (L::ey(i) > 0 || (L::ey(i) == 0 && L::ez(i) > 0)));
-            if (!lead) continue;
-            const T diff = d[i] - d[o];
-            if (L::ex(i)) j[0] += L::ex(i) > 0 ? diff : -diff;
-            if (L::ey(i)) j[1] += L::ey(i) > 0 ? diff : -diff;
-            if (L::ez(i)) j[2] += L::ez(i) > 0 ? diff : -diff;
-        }
-        rho = T(1) + drho;
-        const T irho = recip(rho);
-        const T eps = tab[TAB_EPS];
-        T v[3];
-#pragma unroll
-        for (int a = 0; a < 3; ++a) v[a] = j[a] * irho + T(0.5) * eps * g[a];
-        if (FORCH) {
-            const T c0 = tab[TAB_C0], c1 = tab[TAB_C1];
-            const T vm = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
-            const T den = T(1) / (c0 + sqrt(c0 * c0 + c1 * vm));
-#pragma unroll
-            for (int a = 0; a < 3; ++a) u[a] = v[a] * den;
-            const T um = sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
-            const T drag = tab[TAB_DRAG] + tab[TAB_FORCH] * um;
-#pragma unroll
-            for (int a = 0; a < 3; ++a) F[a] = eps * g[a] - drag * u[a];
-        } else {
-            const T h = tab[TAB_INV_2C0], drag = tab[TAB_DRAG];
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                u[a] = v[a] * h;
-                F[a] = eps * g[a] - drag * u[a];
-            }
-        }
-    }
-};
-
 // A leading direction of an opposite pair (the one whose first non-zero
 // component is positive).
 template <int Q> __host__ __device__ constexpr bool lead(int i)
@@ -287,6 +251,99 @@ template <int Q> __host__ __device__ constexpr bool lead(int i)
     using L = Lat<Q>;
     return L::ex(i) > 0 || (L::ex(i) == 0 && (L::ey(i) > 0 || (L::ey(i) == 0 && L::ez(i) > 0)));
 }
+
+// a . b over the first D components.
+template <int D, typename T> __device__ __forceinline__ T dot(const T (&a)[3], const T (&b)[3])
+{
+    T s = a[0] * b[0];
+#pragma unroll
+    for (int k = 1; k < D; ++k) s += a[k] * b[k];
+    return s;
+}
+
+// e_i . v over the non-zero components of e_i (each is +1 or -1).
+template <int Q, typename T> __device__ __forceinline__ T edot(int i, const T (&v)[3])
+{
+    using L = Lat<Q>;
+    const int e[3] = {L::ex(i), L::ey(i), L::ez(i)};
+    T s = 0;
+    bool seen = false;
+#pragma unroll
+    for (int a = 0; a < L::D; ++a) {
+        if (!e[a]) continue;
+        const T t = e[a] > 0 ? v[a] : -v[a];
+        s = seen ? s + t : t;
+        seen = true;
+    }
+    return s;
+}
+
+// Moments and force of one node: Eq. (32)-(35) and (27)-(28) on deviations.
+template <int Q, typename T, bool FORCH> struct Node {
+    T drho, rho, u[3], F[3];
+    __device__ __forceinline__ void moments(const T (&d)[Q], const T* tab, const T g[3])
+    {
+        T dr = d[0];
+#pragma unroll
+        for (int i = 1; i < Q; ++i) dr += d[i];
+        moments_with(d, dr, tab, g);
+    }
+    // d: deviations (or local parts e_i, whose momentum is the same), dr: rho - 1
+    __device__ __forceinline__ void moments_with(const T (&d)[Q], T dr, const T* tab, const T g[3])
+    {
+        using L = Lat<Q>;
+        constexpr int D = L::D;
+        // Opposite populations share their density part w_i drho; summing the
+        // momentum as differences of opposite pairs cancels it exactly (each
+        // difference of two close values is exact in floating point) before
+        // anything is rounded.  Each sum starts from its first term, and a
+        // 2-D lattice never touches the z components (IEEE arithmetic cannot
+        // drop a 0 * x or a 0 + x on its own).
+        T j[3] = {0, 0, 0};
+        bool seen[3] = {false, false, false};
+        drho = dr;
+#pragma unroll
+        for (int i = 1; i < Q; ++i) {
+            const int o = L::opp(i);
+            if (!lead<Q>(i)) continue;
+            const T diff = d[i] - d[o];
+            const int e[3] = {L::ex(i), L::ey(i), L::ez(i)};
+#pragma unroll
+            for (int a = 0; a < D; ++a) {
+                if (!e[a]) continue;
+                const T t = e[a] > 0 ? diff : -diff;
+                j[a] = seen[a] ? j[a] + t : t;
+                seen[a] = true;
+            }
+        }
+        rho = T(1) + drho;
+        const T irho = recip(rho);
+        const T eps = tab[TAB_EPS];
+        T v[3];
+#pragma unroll
+        for (int a = 0; a < D; ++a) v[a] = j[a] * irho + T(0.5) * eps * g[a];
+        if (FORCH) {
+            const T c0 = tab[TAB_C0], c1 = tab[TAB_C1];
+            const T vm = sqrt(dot<D>(v, v));
+            const T den = T(1) / (c0 + sqrt(c0 * c0 + c1 * vm));
+#pragma unroll
+            for (int a = 0; a < D; ++a) u[a] = v[a] * den;
+            const T um = sqrt(dot<D>(u, u));
+            const T drag = tab[TAB_DRAG] + tab[TAB_FORCH] * um;
+#pragma unroll
+            for (int a = 0; a < D; ++a) F[a] = eps * g[a] - drag * u[a];
+        } else {
+            const T h = tab[TAB_INV_2C0], drag = tab[TAB_DRAG];
+#pragma unroll
+            for (int a = 0; a < D; ++a) {
+                u[a] = v[a] * h;
+                F[a] = eps * g[a] - drag * u[a];
+            }
+        }
+#pragma unroll
+        for (int a = D; a < 3; ++a) u[a] = F[a] = T(0);
+    }
+};
 
 // 1 - sum of the weights as rounded to T (exactly representable: a sum of a
 // few floats computed in double).
@@ -314,20 +371,22 @@ __device__ __forceinline__ void relax(T (&d)[Q], const Node<Q, T, FORCH>& s, con
 {
     using L = Lat<Q>;
     const T ieps = tab[TAB_INV_EPS];
-    const T uu = s.u[0] * s.u[0] + s.u[1] * s.u[1] + s.u[2] * s.u[2];
-    const T uF = s.u[0] * s.F[0] + s.u[1] * s.F[1] + s.u[2] * s.F[2];
+    constexpr int DIM = L::D;
+    const T uu = dot<DIM>(s.u, s.u);
+    const T uF = dot<DIM>(s.u, s.F);
     const T A = T(-1.5) * ieps * uu;
     const T B = T(-3) * ieps * uF;
     const T k1 = T(4.5) * ieps, k2 = T(9) * ieps;
     const T rc = s.rho * cforce;
     const T omw = T(1) - omega;
-    T eq0 = LOCAL ? T(0) : s.drho, f0 = T(0);
+    T eq0 = s.drho, f0 = T(0);
+    bool first = true;
 #pragma unroll
     for (int i = 1; i < Q; ++i) {
         if (!lead<Q>(i)) continue;
         const int o = L::opp(i);
-        const T eu = T(L::ex(i)) * s.u[0] + T(L::ey(i)) * s.u[1] + T(L::ez(i)) * s.u[2];
-        const T eF = T(L::ex(i)) * s.F[0] + T(L::ey(i)) * s.F[1] + T(L::ez(i)) * s.F[2];
+        const T eu = edot<Q>(i, s.u);
+        const T eF = edot<Q>(i, s.F);
         const T w = T(L::w(i));
         const T wr = w * s.rho, wf = w * rc;
         const T ev = LOCAL ? wr * (k1 * eu * eu + A) : w * s.drho + wr * (k1 * eu * eu + A);
@@ -338,8 +397,9 @@ __device__ __forceinline__ void relax(T (&d)[Q], const Node<Q, T, FORCH>& s, con
         const T D = omega * od + odf;
         d[i] = omw * d[i] + P + D;
         d[o] = omw * d[o] + P - D;
-        eq0 -= T(2) * ev;
-        f0 -= T(2) * evf;
+        eq0 = (LOCAL && first) ? T(-2) * ev : eq0 - T(2) * ev;
+        f0 = first ? T(-2) * evf : f0 - T(2) * evf;
+        first = false;
     }
     if (LOCAL)
         d[0] = omw * d[0] + omega * eq0 + f0 + weight_defect<Q, T>() * s.drho;
@@ -358,8 +418,11 @@ __device__ __forceinline__ void load_table(T* lds, const Args& a, int inst)
 
 // ---------------------------------------------------------------- the sweep --
 // U consecutive slots of a thread (U = 1 in use; the loads of all U slots are
-// issued before the first node is collided).
-template <int U, int Q, int STORE, int BC, bool FORCH>
+// issued before the first node is collided).  NTS: nontemporal population
+// stores.  It is a template parameter so that the two store forms stay
+// separate code: as a run-time branch over otherwise identical stores, the
+// optimizer merges them and drops the nontemporal hint.
+template <int U, int Q, int STORE, int BC, bool FORCH, bool NTS>
 __device__ __forceinline__ void sweep_slots(const Args& a, const Tile& t, const InstDev& I, int sl0,
                                             const typename St<STORE>::T* __restrict__ tb, int tw,
                                             const typename St<STORE>::S* __restrict__ src,
@@ -369,7 +432,7 @@ __device__ __forceinline__ void sweep_slots(const Args& a, const Tile& t, const 
     using T = typename SS::T;
     const T g[3] = {inst_g<T>(I, 0), inst_g<T>(I, 1), inst_g<T>(I, 2)};
     const T omega = inst_omega<T>(I), cforce = inst_cforce<T>(I);
-    const bool nt_store = (a.cache & 1) != 0, nt_load = (a.cache & 2) != 0;
+    const bool nt_load = (a.cache & 2) != 0;
     const int twm = (1 << a.tw_log2) - 1;
     const int z = t.z0;
     int n[U], c[U];
@@ -397,13 +460,16 @@ __device__ __forceinline__ void sweep_slots(const Args& a, const Tile& t, const 
             const T dr = localize<Q, T>(d[u], r[u]);
             s.moments_with(d[u], dr, ct, g);
             relax<Q, T, FORCH, true>(d[u], s, ct, omega, cforce);
-            rho_plane<STORE>(dst, Q, I.stride)[n[u]] = dr;
+            if constexpr (node_blocks(STORE))
+                rho_plane<STORE>(dst, Q, I.stride)[n[u]] = dr;
+            else
+                *elem(rho_plane<STORE>(dst, Q, I.stride), uint32_t(n[u])) = dr;
         } else {
             s.moments(d[u], ct, g);
             relax<Q, T, FORCH, false>(d[u], s, ct, omega, cforce);
         }
         if constexpr (node_blocks(STORE)) {
-            if (nt_store) {
+            if constexpr (NTS) {
 #pragma unroll
                 for (int i = 0; i < Q; ++i)
                     __builtin_nontemporal_store(SS::enc(d[u][i], I.scale), dst + pidx<Q, STORE>(i, n[u], 0));
@@ -412,13 +478,14 @@ __device__ __forceinline__ void sweep_slots(const Args& a, const Tile& t, const 
                 for (int i = 0; i < Q; ++i) dst[pidx<Q, STORE>(i, n[u], 0)] = SS::enc(d[u][i], I.scale);
             }
         } else {
-            if (nt_store) {
+            // plane base uniform, one 32-bit byte offset shared by the q stores
+            if constexpr (NTS) {
 #pragma unroll
                 for (int i = 0; i < Q; ++i)
-                    __builtin_nontemporal_store(SS::enc(d[u][i], I.scale), dst + i * I.stride + n[u]);
+                    __builtin_nontemporal_store(SS::enc(d[u][i], I.scale), elem(dst + (size_t)i * I.stride, uint32_t(n[u])));
             } else {
 #pragma unroll
-                for (int i = 0; i < Q; ++i) dst[i * I.stride + n[u]] = SS::enc(d[u][i], I.scale);
+                for (int i = 0; i < Q; ++i) *elem(dst + (size_t)i * I.stride, uint32_t(n[u])) = SS::enc(d[u][i], I.scale);
             }
         }
     }
@@ -433,7 +500,11 @@ __device__ __forceinline__ void sweep_tile(const Args& a, const Tile& t, const I
     const S* __restrict__ src = static_cast<const S*>(a.buf[sel]) + I.pop_off;
     S* __restrict__ dst = static_cast<S*>(a.buf[sel ^ 1]) + I.pop_off;
     const uint8_t* __restrict__ cls = a.cls + I.cls_off;
-    for (int sl = 0; sl < a.nslot; ++sl) sweep_slots<1, Q, STORE, BC, FORCH>(a, t, I, sl, tb, tw, src, dst, cls);
+    if (a.cache & 1) {
+        for (int sl = 0; sl < a.nslot; ++sl) sweep_slots<1, Q, STORE, BC, FORCH, true>(a, t, I, sl, tb, tw, src, dst, cls);
+    } else {
+        for (int sl = 0; sl < a.nslot; ++sl) sweep_slots<1, Q, STORE, BC, FORCH, false>(a, t, I, sl, tb, tw, src, dst, cls);
+    }
 }
 
 // One time step of one tile.  Policy bits of a.cache: 0 nontemporal stores,
