@@ -217,9 +217,12 @@ int glbm_sweep_time(glbm_ctx ctx, double* ms_total, int64_t* launches);
 
 /*
  * Autotuner: time every (tile width, tile rows, cache policy) candidate for
- * `steps` sweeps and keep the fastest.  The state advances by those sweeps
- * (an even number per candidate); the residual snapshot is reset.  If chosen
- * is not NULL it receives {width, rows, cache}.
+ * `steps` sweeps and keep the fastest.  Widths 64 .. 1024 (up to twice the
+ * widest instance), rows 1 .. 16, cache policies 1, 3, 4, 5, 9, 12, 13, 15.
+ * The state advances by those sweeps (an even number per candidate); the
+ * residual snapshot is reset.  If chosen is not NULL it receives {width,
+ * rows, cache}.  Errors: GLBM_EINVAL for a null context or odd or < 2 steps;
+ * a failing launch is returned as is, with the caller's stream joined.
  */
 int glbm_autotune(glbm_ctx ctx, int32_t steps, int32_t* chosen);
 

@@ -995,22 +995,27 @@ int glbm_autotune(glbm_ctx c, int32_t steps, int32_t* chosen)
         if (twl > 6 && (1 << twl) > 2 * max_nx) break;
         for (int th : {1, 2, 4, 8, 16}) {
             if (!tile_ok(twl, th)) continue;
-            for (int cache : {1, 3, 5, 9, 13, 15}) {
+            // policies with and without nontemporal stores (bit 0)
+            for (int cache : {1, 3, 4, 5, 9, 12, 13, 15}) {
                 c->cache = cache;
                 rc = glbm_set_option(c, GLBM_OPT_TILE_WIDTH, 1 << twl);
                 if (!rc) rc = glbm_set_option(c, GLBM_OPT_TILE_ROWS, th);
                 if (!rc) rc = glbm_set_option(c, GLBM_OPT_TIMING, 1);
-                if (!rc) rc = enter(c);
-                for (int k = 0; k < steps && rc == GLBM_OK; ++k) rc = sweep_once(c, (int)((c->gstep + k) & 1));
+                if (rc) return rc;
+                rc = enter(c);
+                if (rc) return rc;
+                int k = 0;
+                for (; k < steps && rc == GLBM_OK; ++k) rc = sweep_once(c, (int)((c->gstep + k) & 1));
                 double ms = 0.0;
                 int64_t nl = 0;
                 if (!rc) rc = glbm_sweep_time(c, &ms, &nl);
                 // the sweeps advanced every active instance; keep the counters exact
                 for (int i = 0; i < c->n_inst; ++i)
-                    if (c->active_h[i]) c->steps[i] += steps;
-                c->gstep += steps;
+                    if (c->active_h[i]) c->steps[i] += k;
+                c->gstep += k;
                 c->snap_valid = false;
-                if (!rc) rc = leave(c);
+                const int lrc = leave(c);
+                if (!rc) rc = lrc;
                 if (rc) return rc;
                 if (ms < best) {
                     best = ms;

@@ -511,8 +511,9 @@ __device__ __forceinline__ void sweep_tile(const Args& a, const Tile& t, const I
 // 1 nontemporal loads of x-aligned planes, 2 plain workgroup order (no XCD
 // grouping), 3 per-class constants read through the L1 cache instead of being
 // staged in LDS.  The best setting depends on the layout and the map, and
-// glbm_autotune picks it; on the 4096^2 FP32 map with node blocks it is
-// 512 x 1 tiles with bits 0 and 2 (about 5.9 TB/s of HBM traffic).
+// glbm_autotune picks it; on the 4096^2 FP32 map with node blocks, 256 x 1
+// and 512 x 1 tiles with nontemporal stores time within 1 % of each other
+// (about 6.1 TB/s of algorithmic bytes).
 template <int Q, int STORE, int BC, bool FORCH> __device__ __forceinline__ void sweep_block(const Args& a)
 {
     using T = typename St<STORE>::T;

@@ -108,6 +108,31 @@ def test_batch_equals_single_bitwise(gpu):
         ss.close()
 
 
+@pytest.mark.parametrize("q,store", [(9, "f64"), (9, "f32"), (9, "f16loc"), (19, "f32"), (19, "f16loc")])
+def test_cache_policies_bitwise(gpu, q, store):
+    """A cache policy changes only cache hints (nontemporal stores and loads), the
+    workgroup order and where the class constants are read (LDS or L1), so every
+    policy yields the same bits: the nontemporal and plain store loops are separate
+    code and must compute the same thing."""
+    g = gpu
+    shape = (45, 70) if q == 9 else (10, 14, 22)
+    cls, eps, k, _ = random_case(shape, seed=71)
+    G = (2e-5, 1e-5, 0) if q == 9 else (1e-5, 0, 2e-5)
+    ref = None
+    for cache in (4, 5, 7, 12, 13, 15):
+        print("case q=%d store=%s cache=%d" % (q, store, cache), flush=True)
+        s = gpu_solver(g, q, cls, eps, k, G=G, store=store, tile=(64, 4), cache=cache)
+        s.step(150)
+        p = _pops(s)
+        r, st = s.residual()
+        s.close()
+        if ref is None:
+            ref = (p, r[0], st[0])
+        else:
+            assert np.array_equal(p, ref[0]), cache
+            assert r[0] == ref[1] and st[0] == ref[2], cache
+
+
 def test_batch_per_instance_convergence(gpu):
     """Instances stop individually at their own first check with r <= tol."""
     g = gpu
