@@ -438,6 +438,38 @@ def test_batch_f16loc_largest_member_one_step_sampled(gpu):
         assert np.abs(f1[:, node] - want).max() <= 2.0 ** -10 * local + 1e-6 * scale + 1e-13, node
 
 
+def test_f16loc_largest_lattice_one_step_sampled(gpu):
+    """The largest square D2Q9 lattice the library accepts, 13377^2 nodes ((q + 3) x nodes
+    just under 2^31 elements; ragged tiles in x), in F16LOC storage.  Its plane accesses use 32-bit byte offsets,
+    which reach about 3.9e9 here.  One sweep matches the oracle on sampled nodes, the first
+    and last rows and columns and the last node included."""
+    g = gpu
+    side = 13377
+    n = side * side
+    assert (n + 4095) // 4096 * 4096 * 12 < 2 ** 31 <= ((side + 1) ** 2 + 4095) // 4096 * 4096 * 12
+    with pytest.raises(g.GlbmError):
+        g.Solver([g.make_desc((side + 1, side + 1), store=g.GLBM_STORE_F16LOC)], [np.zeros((1, 1), np.uint8)])
+    print("case D2Q9 F16LOC %d^2" % side, flush=True)
+    cls, eps, k, _ = random_case((side, side), seed=91)
+    G = (1e-4, 0, 0)
+    d = g.make_desc(cls.shape, store=g.GLBM_STORE_F16LOC, tau=1.0, g=G, check_every=100)
+    s = g.Solver([d], [cls])
+    s.set_local_perm(eps[:255], k[:255])
+    s.step(20)
+    f0 = s.populations()
+    s.step(1)
+    f1 = s.populations()
+    s.close()
+    rng = np.random.default_rng(17)
+    nodes = [int(v) for v in rng.integers(0, n, size=32)]
+    nodes += [0, side - 1, (side - 1) * side, n - 1, (side - 1) * side + side // 2, (side // 2) * side + side - 1]
+    for node in nodes:
+        want, rho_w, w = _step_want(g, 9, cls, eps, k, G, 1.0, 0, f0, node)
+        local = np.abs(want - w * rho_w).max()
+        scale = np.abs(want - w).max()
+        assert np.abs(f1[:, node] - want).max() <= 2.0 ** -10 * local + 1e-6 * scale + 1e-13, node
+
+
 @pytest.mark.parametrize("store", ["f64", "f32"])
 def test_degenerate_open_pore_domain(gpu, store):
     """No matrix at all (eps = 1, K infinite everywhere, periodic): nothing resists the body
