@@ -658,50 +658,50 @@ __global__ __launch_bounds__(kBlock) void k_observe(Args a, int mode, int all)
     }
 }
 
-// One 1024-thread workgroup per instance sums its tile partials: thread t adds
-// tiles t, t + 1024, ... (eight loads in flight), then a fixed-order tree over
-// the threads.  The order depends only on the tile count, so results are
-// deterministic and equal between a batch and a single-instance run.
+// One 1024-thread workgroup per instance sums its tile partials.  They are
+// read as one flat array of doubles, so that a wavefront's loads are
+// contiguous: thread t adds component t % 8 of tiles t / 8, t / 8 + 128, ...
+// (eight loads in flight), then a fixed-order tree over the threads that hold
+// the same component.  The order depends only on the tile count, so results
+// are deterministic and equal between a batch and a single-instance run.
 constexpr int kFinBlock = 1024;
+constexpr int kFinTiles = kFinBlock / kPartW;   // tiles per pass
 __global__ __launch_bounds__(kFinBlock) void k_finalize(Args a, double tol, int with_r, int count_check, int all)
 {
+    static_assert(kFinBlock % kPartW == 0, "a thread keeps one component");
     __shared__ double red[kFinBlock];
     const int inst = blockIdx.x;
     if (!all && !a.active[inst]) return;
     const InstDev& I = a.inst[inst];
-    double acc[6] = {0, 0, 0, 0, 0, 0};
-    const double* base = a.part + (size_t)I.tile0 * kPartW;
-    int t = threadIdx.x;
-    for (; t + 7 * kFinBlock < I.ntiles; t += 8 * kFinBlock) {
-        double v[8][6];
+    const int k = threadIdx.x % kPartW, t0 = threadIdx.x / kPartW;
+    double acc = 0.0;
+    if (k < 6 && t0 < I.ntiles) {
+        // element (t0 + kFinTiles * j) * kPartW + k of the instance's partials
+        const double* p = a.part + (size_t)I.tile0 * kPartW + threadIdx.x;
+        const int nj = (I.ntiles - 1 - t0) / kFinTiles + 1;
+        int j = 0;
+        for (; j + 8 <= nj; j += 8) {
+            double v[8];
 #pragma unroll
-        for (int u = 0; u < 8; ++u)
+            for (int u = 0; u < 8; ++u) v[u] = p[(size_t)(j + u) * kFinBlock];
 #pragma unroll
-            for (int k = 0; k < 6; ++k) v[u][k] = base[(size_t)(t + u * kFinBlock) * kPartW + k];
-#pragma unroll
-        for (int u = 0; u < 8; ++u)
-#pragma unroll
-            for (int k = 0; k < 6; ++k) acc[k] += v[u][k];
-    }
-    for (; t < I.ntiles; t += kFinBlock)
-#pragma unroll
-        for (int k = 0; k < 6; ++k) acc[k] += base[(size_t)t * kPartW + k];
-    double out[6];
-#pragma unroll
-    for (int k = 0; k < 6; ++k) {
-        red[threadIdx.x] = acc[k];
-        __syncthreads();
-        for (int s = kFinBlock / 2; s > 0; s >>= 1) {
-            if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
-            __syncthreads();
+            for (int u = 0; u < 8; ++u) acc += v[u];
         }
-        out[k] = red[0];
+        for (; j < nj; ++j) acc += p[(size_t)j * kFinBlock];
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = kFinBlock / 2; s >= kPartW; s >>= 1) {
+        if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
         __syncthreads();
     }
     if (threadIdx.x == 0) {
+        double out[6];
+#pragma unroll
+        for (int c = 0; c < 6; ++c) out[c] = red[c];
         double* res = a.res + (size_t)inst * kPartW;
 #pragma unroll
-        for (int k = 0; k < 6; ++k) res[k] = out[k];
+        for (int c = 0; c < 6; ++c) res[c] = out[c];
         if (with_r) {
             const double r = sqrt(out[P_SD]) / (double(a.dsteps[inst]) * sqrt(out[P_SU]));
             res[P_R] = (out[P_SU] > 0.0) ? r : INFINITY;
