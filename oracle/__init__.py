@@ -125,7 +125,7 @@ class Problem:
     tau: float = 1.0
     G: Sequence[float] = (1e-6, 0.0, 0.0)
     walls: int = 0
-    store_mode: int = 0             # 0 plain; 1 / 2 emulate FP32 / FP16-deviation storage
+    store_mode: int = 0             # 0 plain; 1-5 emulate reduced-precision storage (glbm_ref.c store_round)
     scale_log2: int = 0
     precision: str = "f64"          # "f64", or "ext" for the x87 extended-precision build
 

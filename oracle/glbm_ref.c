@@ -36,9 +36,9 @@
  *   - walls use halfway bounce-back; a node of class 255 is a solid wall node;
  *     open faces are periodic.
  *
- * Optional storage emulation (store_mode 1 / 2) rounds every stored value
- * through float32 or float16 as (f - w_i) * 2^s, to study what reduced
- * precision storage can reach.  Mode 0 is the plain oracle.
+ * Optional storage emulation (store_mode 1-5, see store_round) rounds every
+ * stored value as a reduced-precision store would, to study what it can
+ * reach.  Mode 0 is the plain oracle.
  */
 #include <math.h>
 #include <omp.h>
@@ -137,7 +137,8 @@ static double round_half(double x)
 /* mode 1: (f - w) through float; mode 2: (f - w) 2^s through float16;
  * mode 3: (f - w rho_x) 2^s through float16 with rho_x - 1 through float,
  * rho_x the density of the node the value leaves; mode 4: the same through
- * float32. */
+ * float32; mode 5: as mode 3 with rho_x - 1 stored as (rho_x - 1) 2^10
+ * through float16. */
 static real store_round(real f, real w, int mode, int scale_log2, real rho_x)
 {
     if (mode == 1) return (real)(float)(f - w) + w;
@@ -149,6 +150,11 @@ static real store_round(real f, real w, int mode, int scale_log2, real rho_x)
         double s = ldexp(1.0, scale_log2);
         real r32 = 1 + (real)(float)(rho_x - 1);
         return (real)(round_half((double)((f - w * r32) * s)) / s) + w * r32;
+    }
+    if (mode == 5) {
+        double s = ldexp(1.0, scale_log2);
+        real r16 = 1 + (real)(round_half((double)((rho_x - 1) * 1024.0)) / 1024.0);
+        return (real)(round_half((double)((f - w * r16) * s)) / s) + w * r16;
     }
     if (mode == 4) {
         real r32 = 1 + (real)(float)(rho_x - 1);

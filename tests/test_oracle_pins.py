@@ -188,6 +188,33 @@ def test_mass_conservation(q, shape, walls):
     assert abs(m1 - m0) / m0 < 1e-15
 
 
+@pytest.mark.parametrize("mode,scale,tol", [(3, 24, 4e-3), (4, 0, 3e-5), (5, 24, 4e-3)])
+def test_storage_emulation_modes(mode, scale, tol):
+    """The reduced-precision storage emulations (local-density forms: FP16 parts with an
+    FP32 density, FP32 parts, FP16 parts with an FP16 density scaled by 2^10) stay within
+    their storage tolerance of the plain FP64 oracle and keep the total mass up to the
+    rounding of the stored parts.  A dropped w_i rho term or a wrong scale is off by many
+    orders of magnitude."""
+    rng = np.random.default_rng(12)
+    shape = (24, 34)
+    cls = rng.integers(0, 6, size=shape).astype(np.uint8)
+    eps = np.concatenate([[1.0], rng.uniform(0.1, 0.9, 255)])
+    k = np.concatenate([[math.inf], 10 ** rng.uniform(-3, -1, 255)])
+    G = (2e-5, 1e-5, 0)
+    runs = {}
+    for m, sc in ((0, 0), (mode, scale)):
+        p = oracle.Problem(q=9, cls=cls, eps=eps, k=k, f_eps=0.0, tau=1.0, G=G, store_mode=m, scale_log2=sc)
+        f = p.rest()
+        p.run(f, 300)
+        runs[m] = f.reshape(9, -1)
+    _, w = oracle.lattice(9)[:2]
+    dev = np.abs(runs[0] - np.asarray(w)[:, None]).max()
+    err = np.abs(runs[mode] - runs[0]).max()
+    assert dev > 1e-6
+    assert 0 < err <= tol * dev
+    assert abs(runs[mode].sum() - runs[0].sum()) <= 1e-3 * tol * dev * runs[0].size
+
+
 # ------------------------------------------------------ steady closed forms --
 @pytest.mark.parametrize("eps,K", [(0.4, 0.01), (0.1, 1e-3), (1.0, 0.5)])
 def test_uniform_medium_darcy(eps, K):
