@@ -138,7 +138,8 @@ static double round_half(double x)
  * mode 3: (f - w rho_x) 2^s through float16 with rho_x - 1 through float,
  * rho_x the density of the node the value leaves; mode 4: the same through
  * float32; mode 5: as mode 3 with rho_x - 1 stored as (rho_x - 1) 2^10
- * through float16. */
+ * through float16 (a variant of the FP16 local-density form, kept for the
+ * precision study). */
 static real store_round(real f, real w, int mode, int scale_log2, real rho_x)
 {
     if (mode == 1) return (real)(float)(f - w) + w;

@@ -46,8 +46,7 @@ size_t store_bytes(int store)
 // (two half-width planes) for F16LOC
 int planes_of(const glbm_instance_desc& d)
 {
-    // the density plane: one FP16 plane (F16LOC) or one FP32 plane (F32LOC)
-    return d.lattice + (d.store == GLBM_STORE_F16LOC || d.store == GLBM_STORE_F32LOC ? 1 : 0);
+    return d.lattice + (d.store == GLBM_STORE_F16LOC ? 2 : (d.store == GLBM_STORE_F32LOC ? 1 : 0));
 }
 size_t compute_bytes(int store) { return store == GLBM_STORE_F64 ? 8 : 4; }
 int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }

@@ -62,33 +62,22 @@ template <> struct Lat<19> {
 // ----------------------------------------------------------------- storage --
 template <int STORE> struct St;
 // kRho: the stored value is relative to w_i rho(x) of the node that wrote it,
-// whose rho - 1 sits in a density plane after the q population planes: FP32
-// for F32LOC, IEEE half scaled by 2^kRhoLog2 for F16LOC.  RP is the plane's
-// element type, rdec / renc its decoding and encoding; kRhoRound marks a plane
-// that rounds, so that the writer re-expresses its parts relative to the
-// stored (rounded) density and the reader reconstructs f exactly.
-constexpr int kRhoLog2 = 10;
-struct RhoF32 {
-    using RP = float;
-    static constexpr bool kRhoRound = false;
-    __device__ static float rdec(RP v) { return v; }
-    __device__ static RP renc(float d) { return d; }
-};
-template <> struct St<GLBM_STORE_F64> : RhoF32 {
+// whose rho - 1 sits in a float plane after the q population planes.
+template <> struct St<GLBM_STORE_F64> {
     static constexpr bool kRho = false;
     using S = double;
     using T = double;
     __device__ static T dec(S s, float) { return s; }
     __device__ static S enc(T d, float) { return d; }
 };
-template <> struct St<GLBM_STORE_F32> : RhoF32 {
+template <> struct St<GLBM_STORE_F32> {
     static constexpr bool kRho = false;
     using S = float;
     using T = float;
     __device__ static T dec(S s, float) { return s; }
     __device__ static S enc(T d, float) { return d; }
 };
-template <> struct St<GLBM_STORE_F16DEV> : RhoF32 {
+template <> struct St<GLBM_STORE_F16DEV> {
     static constexpr bool kRho = false;
     using S = uint16_t;
     using T = float;
@@ -97,25 +86,21 @@ template <> struct St<GLBM_STORE_F16DEV> : RhoF32 {
 };
 template <> struct St<GLBM_STORE_F16LOC> : St<GLBM_STORE_F16DEV> {
     static constexpr bool kRho = true;
-    using RP = uint16_t;
-    static constexpr bool kRhoRound = true;
-    __device__ static float rdec(RP h) { return __half2float(__ushort_as_half(h)) * (1.0f / float(1 << kRhoLog2)); }
-    __device__ static RP renc(float d) { return __half_as_ushort(__float2half_rn(d * float(1 << kRhoLog2))); }
 };
 template <> struct St<GLBM_STORE_F32LOC> : St<GLBM_STORE_F32> {
     static constexpr bool kRho = true;
 };
 
-// The density plane of a kRho buffer (after the q planes).
+// The float plane of rho - 1 of a kRho buffer (after the q planes).
 template <int STORE>
-__device__ __forceinline__ const typename St<STORE>::RP* rho_plane(const typename St<STORE>::S* base, int q, int stride)
+__device__ __forceinline__ const float* rho_plane(const typename St<STORE>::S* base, int q, int stride)
 {
-    return reinterpret_cast<const typename St<STORE>::RP*>(base + (size_t)q * stride);
+    return reinterpret_cast<const float*>(base + (size_t)q * stride);
 }
 template <int STORE>
-__device__ __forceinline__ typename St<STORE>::RP* rho_plane(typename St<STORE>::S* base, int q, int stride)
+__device__ __forceinline__ float* rho_plane(typename St<STORE>::S* base, int q, int stride)
 {
-    return reinterpret_cast<typename St<STORE>::RP*>(base + (size_t)q * stride);
+    return reinterpret_cast<float*>(base + (size_t)q * stride);
 }
 
 // Workgroups are dispatched round-robin over the 8 XCDs.  Map them so that
@@ -236,7 +221,7 @@ __device__ __forceinline__ void gather(typename St<STORE>::T (&d)[Q], typename S
             at = elem(src, uint32_t(idx));
         const SV raw = (ex == 0 && nt_aligned) ? __builtin_nontemporal_load(at) : *at;
         d[i] = S::dec(raw, I.inv_scale);
-        if constexpr (S::kRho) r[i] = S::rdec(*elem(rho_plane<STORE>(src, Q, stride), uint32_t(node)));
+        if constexpr (S::kRho) r[i] = *elem(rho_plane<STORE>(src, Q, stride), uint32_t(node));
     }
 }
 
@@ -475,18 +460,10 @@ __device__ __forceinline__ void sweep_slots(const Args& a, const Tile& t, const 
             const T dr = localize<Q, T>(d[u], r[u]);
             s.moments_with(d[u], dr, ct, g);
             relax<Q, T, FORCH, true>(d[u], s, ct, omega, cforce);
-            const typename SS::RP rh = SS::renc(dr);
-            if constexpr (SS::kRhoRound) {
-                // parts relative to the density as stored: w_i drho + e_i keeps
-                // its value, and the reader adds back exactly what was taken
-                const T shift = dr - SS::rdec(rh);
-#pragma unroll
-                for (int i = 0; i < Q; ++i) d[u][i] += T(Lat<Q>::w(i)) * shift;
-            }
             if constexpr (node_blocks(STORE))
-                rho_plane<STORE>(dst, Q, I.stride)[n[u]] = rh;
+                rho_plane<STORE>(dst, Q, I.stride)[n[u]] = dr;
             else
-                *elem(rho_plane<STORE>(dst, Q, I.stride), uint32_t(n[u])) = rh;
+                *elem(rho_plane<STORE>(dst, Q, I.stride), uint32_t(n[u])) = dr;
         } else {
             s.moments(d[u], ct, g);
             relax<Q, T, FORCH, false>(d[u], s, ct, omega, cforce);
@@ -768,7 +745,7 @@ __global__ __launch_bounds__(kBlock) void k_set_fields(Args a, int inst, const R
         if (c == kWallClass) continue;
         const T rho = T(rho_in[n]);
         const T u[3] = {T(u_in[n]), T(u_in[N + n]), T(u_in[2 * N + n])};
-        if (SS::kRho) rho_plane<STORE>(dst, Q, I.stride)[n] = SS::renc(T(rho_in[n] - R(1)));
+        if (SS::kRho) rho_plane<STORE>(dst, Q, I.stride)[n] = T(rho_in[n] - R(1));
         const T ieps = tabg[c * kTabW + TAB_INV_EPS];
         const T uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
 #pragma unroll
@@ -790,9 +767,8 @@ __global__ __launch_bounds__(kBlock) void k_set_fields(Args a, int inst, const R
             const int sn = (sz * I.ny + sy) * I.nx + sx;
             if (BC >= 2 && !blocked && i != 0) blocked = cls[sn] == kWallClass;
             const int idx = blocked ? pidx<Q, STORE>(L::opp(i), n, I.stride) : pidx<Q, STORE>(i, sn, I.stride);
-            // a kRho value is decoded with the density of the node whose slot it
-            // occupies, as that node stores it
-            const T dr = SS::kRho ? T(SS::rdec(SS::renc(T(rho_in[blocked ? n : sn] - R(1))))) : T(0);
+            // a kRho value is decoded with the density of the node whose slot it occupies
+            const T dr = SS::kRho ? T(rho_in[blocked ? n : sn] - R(1)) : T(0);
             dst[idx] = SS::enc(dq - T(L::w(i)) * dr, I.scale);
         }
     }

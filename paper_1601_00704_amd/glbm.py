@@ -33,10 +33,8 @@ STORE_BYTES = {GLBM_STORE_F64: 8, GLBM_STORE_F32: 4, GLBM_STORE_F16DEV: 2, GLBM_
 
 def bytes_per_update(q: int, store: int) -> int:
     """Algorithmic HBM bytes of one lattice update: read and write q populations
-    and the class byte; F16LOC / F32LOC add the node's density (FP16 / FP32),
-    written once and read once."""
-    extra = {GLBM_STORE_F16LOC: 4, GLBM_STORE_F32LOC: 8}.get(store, 0)
-    return 2 * q * STORE_BYTES[store] + 1 + extra
+    and the class byte (F16LOC / F32LOC add the float density: 4 B written, 4 B read)."""
+    return 2 * q * STORE_BYTES[store] + 1 + (8 if store in (GLBM_STORE_F16LOC, GLBM_STORE_F32LOC) else 0)
 
 EXPORTS = ("glbm_required_bytes", "glbm_init_geometry", "glbm_set_local_perm", "glbm_step_n",
            "glbm_residual", "glbm_permeability", "glbm_set_fields", "glbm_set_fields_device",

@@ -30,7 +30,7 @@ def _compare(g, q, cls, eps, k, fe, store, steps, G, walls=0, tau=1.0, tile=None
                                                                              tile, cache), flush=True)
     if store == "f16loc" and scale == 20:
         scale = 24
-    emul = {"f64": (0, 0), "f32": (0, 0), "f16dev": (2, scale), "f16loc": (5, scale), "f32loc": (4, 0)}[store]
+    emul = {"f64": (0, 0), "f32": (0, 0), "f16dev": (2, scale), "f16loc": (3, scale), "f32loc": (4, 0)}[store]
     prob = oracle_problem(q, cls, eps, k, fe, tau=tau, G=G, walls=walls, store_mode=emul[0],
                           scale_log2=emul[1])
     f = prob.rest()
