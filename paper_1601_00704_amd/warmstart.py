@@ -147,6 +147,7 @@ def evaluate(cnn, insts, maps, tol, max_steps, ctx_size, G, H, W, store, trace_e
         te = trace_every if c0 == 0 else 0
         cold = Batch(sub, sm, store)
         wc, rcc, rc_, stc = cold.solve(tol, max_steps, te)
+        print("cold-solved %d/%d (%.1fs, max steps %d)" % (c0 + len(sub), len(insts), wc, int(stc.max())), flush=True)
         if te:
             traces["cold"] = cold.trace
         kc = cold.s.permeability()[:, 0]
