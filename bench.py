@@ -404,7 +404,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--side", type=int, default=4096)
     ap.add_argument("--store", default="f32", choices=("f32", "f16dev", "f16loc", "f32loc", "f64"))
-    ap.add_argument("--cpu-steps", type=int, default=1000)
+    ap.add_argument("--cpu-steps", type=int, default=4000, help="oracle steps of the CPU baseline (about 10 s)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--workload", default="shale4096", choices=("shale4096", "batch", "d3q19", "cnn"),
                     help="shale4096: the benchmark line; batch / d3q19 / cnn: supplementary workloads")

@@ -239,6 +239,15 @@ def test_not_converged_and_state_errors(gpu):
     assert e.value.code == g.GLBM_EINVAL
     with pytest.raises(g.GlbmError):
         s.set_local_perm(np.full(255, 1.5), np.full(255, 0.1))  # eps > 1
+    for eps_bad, k_bad, fe_bad in ((0.0, 0.1, None), (0.5, 0.0, None), (0.5, -1e-3, None), (0.5, float("nan"), None),
+                                   (0.5, 0.1, -1.0), (0.5, 0.1, float("inf"))):
+        with pytest.raises(g.GlbmError) as e:
+            s.set_local_perm(np.full(255, eps_bad), np.full(255, k_bad),
+                             None if fe_bad is None else np.full(255, fe_bad))
+        assert e.value.code == g.GLBM_EINVAL, (eps_bad, k_bad, fe_bad)
+    # a valid table is accepted again afterwards
+    s.set_local_perm(eps[:255], k[:255])
+    assert s.step(100) == g.GLBM_OK
     s.close()
 
 
