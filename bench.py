@@ -129,7 +129,7 @@ def pmc_summary(fetch_dir, write_dir, cfetch_dir, cwrite_dir, args):
     import paper_1601_00704_amd.glbm as g
     key, q, n = workload_key(args)
     bpl = g.bytes_per_update(q, g.STORE_NAMES[args.store])
-    rec = {"kernel": "k_sweep<%d,%s>, %s, %d nodes" % (q, args.store, args.workload, n),
+    rec = {"kernel": "%s, %s, %d nodes" % (sweep_kernel(q, args.store), args.workload, n),
            "kernel_source_hash": kernel_source_hash(),
            "fetch_kib_per_launch": sf, "write_kib_per_launch": sw, "launches": [nf, nw],
            "copy_fetch_kib": cf, "copy_write_kib": cw, "fetch_scale": f_scale, "write_scale": w_scale,
@@ -141,6 +141,13 @@ def pmc_summary(fetch_dir, write_dir, cfetch_dir, cwrite_dir, args):
     with open(path, "w") as fh:
         json.dump(rec, fh, indent=1)
     print(json.dumps(rec))
+
+
+def sweep_kernel(q, store):
+    """Name of the sweep kernel that runs for a lattice and store."""
+    if q == 19:
+        return "k_sweep19<%s>" % store
+    return ("k_sweep9<%s>" if store in ("f64", "f32", "f32loc") else "k_sweep<9,%s>") % store
 
 
 def cpu_baseline(cls_crop, table, steps):
@@ -254,7 +261,7 @@ def run_batch(args):
            "median_residual": float(np.median(r)), "steps_total": int(st.max())}
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
             "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic_from_profile(workload_key(args)[0]),
-            "kernel": "k_sweep<9,%s> over the flat tile list" % args.store, "bytes_per_lu": bpl,
+            "kernel": "%s over the flat tile list" % sweep_kernel(9, args.store), "bytes_per_lu": bpl,
             "mean_launch_ms": round(per_launch, 5), "launches": launches}
     return _json_line(N * N_C * args.steps / wall / 1e6, args.steps, args.warmup, wall / args.steps * 1e3,
                       DTYPE[args.store], cfg, roof)
@@ -318,7 +325,7 @@ def run_d3q19(args):
         cfg["time_to_converge"] = conv
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
             "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic_from_profile(workload_key(args)[0]),
-            "kernel": "k_sweep<19,%s>" % args.store, "bytes_per_lu": bpl,
+            "kernel": sweep_kernel(19, args.store), "bytes_per_lu": bpl,
             "mean_launch_ms": round(per_launch, 5), "launches": n}
     return _json_line(N * N_C * args.steps / wall / 1e6, args.steps, args.warmup, wall / args.steps * 1e3,
                       DTYPE[args.store], cfg, roof)
@@ -511,7 +518,7 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": round(achieved / PEAK_HBM_GBS, 4),
                      "traffic": traffic,
-                     "kernel": "k_sweep<9,%s>" % args.store, "bytes_per_lu": bytes_per_lu,
+                     "kernel": sweep_kernel(9, args.store), "bytes_per_lu": bytes_per_lu,
                      "mean_launch_ms": round(per_launch, 5), "launches": launches,
                      "measured_copy_gbs": round(copy_bandwidth(), 1)},
     }

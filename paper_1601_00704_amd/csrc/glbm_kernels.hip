@@ -511,9 +511,9 @@ __device__ __forceinline__ void sweep_tile(const Args& a, const Tile& t, const I
 // 1 nontemporal loads of x-aligned planes, 2 plain workgroup order (no XCD
 // grouping), 3 per-class constants read through the L1 cache instead of being
 // staged in LDS.  The best setting depends on the layout and the map, and
-// glbm_autotune picks it; on the 4096^2 FP32 map with node blocks, 256 x 1
-// and 512 x 1 tiles with nontemporal stores time within 1 % of each other
-// (about 6.1 TB/s of algorithmic bytes).
+// glbm_autotune picks it; on the 4096^2 FP32 map (k_sweep9, 6 waves per
+// SIMD) it is 256 x 1 tiles with all four bits set (about 6.3 TB/s of
+// algorithmic bytes).
 template <int Q, int STORE, int BC, bool FORCH> __device__ __forceinline__ void sweep_block(const Args& a)
 {
     using T = typename St<STORE>::T;
@@ -552,6 +552,18 @@ template <int STORE> constexpr int waves19()
 {
     return (STORE == GLBM_STORE_F16DEV || STORE == GLBM_STORE_F16LOC) ? 5 : 4;
 }
+
+// D2Q9 with the node-block stores (FP64, FP32, FP32LOC), capped at 6 waves per
+// SIMD.  On the 4096^2 map, FP32 with the class constants read through L1
+// measured 0.1951 ms against 0.2023 uncapped (best uncapped tile: 0.2018);
+// FP32LOC -2.7 %, the FP32 batch -1.7 %, FP64 unchanged; caps of 4, 5 and 7
+// were slower than 6.  The FP16 stores run 6 % slower capped and use k_sweep.
+template <int STORE, int BC, bool FORCH, int W>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1, W))) void k_sweep9(Args a)
+{
+    sweep_block<9, STORE, BC, FORCH>(a);
+}
+constexpr int kWaves9 = 6;
 
 // ------------------------------------------------------------ observations --
 __device__ __forceinline__ double wave_sum(double v)
@@ -835,6 +847,8 @@ template <int Q, int STORE, int BC, bool FORCH> struct SweepK {
     {
         if constexpr (Q == 19)
             hipLaunchKernelGGL((k_sweep19<STORE, BC, FORCH, waves19<STORE>()>), dim3(a.ntiles), dim3(kBlock), 0, s, a);
+        else if constexpr (node_blocks(STORE))
+            hipLaunchKernelGGL((k_sweep9<STORE, BC, FORCH, kWaves9>), dim3(a.ntiles), dim3(kBlock), 0, s, a);
         else
             hipLaunchKernelGGL((k_sweep<Q, STORE, BC, FORCH>), dim3(a.ntiles), dim3(kBlock), 0, s, a);
         return hipGetLastError();
