@@ -37,6 +37,12 @@ PEAK_HBM_GBS = 8000.0
 N_C = 100
 
 
+def opt_in(store):
+    """The literal FP16 deviation store runs only as an explicit study form."""
+    import paper_1601_00704_amd.glbm as g
+    return g.GLBM_FLAG_F16DEV_OPT_IN if store == g.GLBM_STORE_F16DEV else 0
+
+
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
     for f in ("glbm_kernels.hip", "glbm_internal.h"):
@@ -236,7 +242,8 @@ def run_batch(args):
     import paper_1601_00704_amd.glbm as g
     torch.cuda.set_device(0)
     store = g.STORE_NAMES[args.store]
-    descs = [g.make_desc(m.shape, store=store, tau=i.tau, g=i.gvec(), check_every=N_C) for i, m in zip(insts, maps)]
+    descs = [g.make_desc(m.shape, store=store, tau=i.tau, g=i.gvec(), check_every=N_C,
+                    flags=opt_in(store)) for i, m in zip(insts, maps)]
     s = g.Solver(descs, maps)
     for k, inst in enumerate(insts):
         r_iom, r_om = inst.radii()
@@ -282,7 +289,8 @@ def run_d3q19(args):
     r_iom, r_om = inst.radii()
     eps, kl = g.glbm_class_table(g.gas_params(inst), r_iom, r_om)
     d = g.make_desc(cls.shape, lattice=g.GLBM_D3Q19, store=store, tau=inst.tau, g=inst.gvec(),
-                    wall_faces=inst.wall_faces, check_every=N_C)
+                    wall_faces=inst.wall_faces, check_every=N_C,
+                    flags=opt_in(store))
     s = g.Solver([d], [cls])
     s.set_local_perm(eps[:255], kl[:255])
     N = cls.size
@@ -465,7 +473,8 @@ def main():
     r_iom, r_om = inst.radii()
     eps, kl = g.glbm_class_table(g.gas_params(inst), r_iom, r_om)
     store = g.STORE_NAMES[args.store]
-    d = g.make_desc(cls.shape, store=store, tau=inst.tau, g=inst.gvec(), check_every=N_C)
+    d = g.make_desc(cls.shape, store=store, tau=inst.tau, g=inst.gvec(), check_every=N_C,
+                    flags=opt_in(store))
     s = g.Solver([d], [cls])
     s.set_local_perm(eps[:255], kl[:255])
     N = cls.size

@@ -43,10 +43,16 @@ enum { GLBM_D2Q9 = 9, GLBM_D3Q19 = 19 };
 /* Population storage.  Arithmetic is FP64 for F64 and FP32 otherwise; the
  * residual and flux reductions are always accumulated in FP64.
  *   F64     f_i - w_i stored as double                       (145 B per D2Q9 update)
- *   F32     f_i - w_i stored as float                        (73 B)
+ *   F32     f_i - w_i stored as float                        (73 B).  The fastest
+ *           store within 1e-5 of FP64 on k, but its rounding scales with the
+ *           density deviation, so on shale maps the residual levels off at
+ *           about 2-3e-8 and a solve with tol = 1e-8 ends GLBM_ENOTCONVERGED;
+ *           use F32LOC for solves to r <= 1e-8.
  *   F16DEV  (f_i - w_i) 2^s stored as IEEE half, rounded to nearest even (37 B).
  *           The velocity part of f is then resolved only relative to the
- *           density deviation: on the 128^2 shale map k is off by ~5%.
+ *           density deviation: on the 128^2 shale map k is off by several
+ *           percent, far outside 1e-3.  Accepted only with
+ *           GLBM_FLAG_F16DEV_OPT_IN (a study form); use F16LOC.
  *   F16LOC  (f_i - w_i rho(x)) 2^s as IEEE half, with rho(x) - 1 of the node
  *           x that wrote the value kept in an extra float plane (45 B).
  *           Removing the node's own density leaves the velocity and
@@ -86,7 +92,12 @@ typedef struct {
     double g[3];             /* external body force G of Eq. (27), lattice units */
     int32_t dev_scale_log2;  /* s of the F16DEV scale 2^s in [0, 30], or GLBM_SCALE_AUTO */
     int32_t check_every;     /* n_c > 0, even: residual and flux are evaluated every n_c steps */
+    uint32_t flags;          /* GLBM_FLAG_* bits; 0 for the defaults */
 } glbm_instance_desc;
+
+/* Descriptor flags.  GLBM_FLAG_F16DEV_OPT_IN: accept GLBM_STORE_F16DEV, whose
+ * k is outside the FP16 accuracy target on shale maps (see the store list). */
+enum { GLBM_FLAG_F16DEV_OPT_IN = 1 };
 
 /*
  * Bytes of device memory that the populations of these instances need (both
@@ -114,7 +125,8 @@ size_t glbm_required_bytes(int32_t n_inst, const glbm_instance_desc* desc);
  * leaves the initial state open.
  * Errors: GLBM_EINVAL (n_inst < 1, empty grid, tau <= 1/2, mixed lattice /
  * store / check_every, nz != 1 for D2Q9, odd check_every, scale outside
- * [0, 30], a wall face without its opposite face); GLBM_ENOMEM; GLBM_EDEVICE.
+ * [0, 30], a wall face without its opposite face, unknown flag bits,
+ * GLBM_STORE_F16DEV without GLBM_FLAG_F16DEV_OPT_IN); GLBM_ENOMEM; GLBM_EDEVICE.
  */
 int glbm_init_geometry(glbm_ctx* out, int32_t n_inst, const glbm_instance_desc* desc,
                        const uint8_t* const* cls_host, void* pop_dev, size_t pop_bytes,
@@ -167,8 +179,10 @@ int glbm_permeability(glbm_ctx ctx, double* k_lattice);
  */
 int glbm_set_fields(glbm_ctx ctx, int32_t inst, const double* rho, const double* u);
 
-/* Same as glbm_set_fields from device arrays of floats (rho[N], u[3N]). */
-int glbm_set_fields_device(glbm_ctx ctx, int32_t inst, const float* rho_dev, const float* u_dev);
+/* Same as glbm_set_fields from device arrays of floats: drho_dev[N] holds
+ * rho - 1 (a float of rho itself would round a small density deviation
+ * against 1), u_dev[3N] the velocity planes. */
+int glbm_set_fields_device(glbm_ctx ctx, int32_t inst, const float* drho_dev, const float* u_dev);
 
 /*
  * Density (N doubles) and velocity (3N doubles, Eq. 34) of the current state

@@ -115,7 +115,23 @@ int glbm_cnn_forward(glbm_cnn cnn, const uint16_t* x, float* y, int32_t batch);
 int glbm_cnn_backward(glbm_cnn cnn, const uint16_t* x, const float* target, const uint8_t* mask, int32_t batch,
                       double* loss);
 
-/* glbm_cnn_backward followed by one Adam step (beta1 0.9, beta2 0.999, eps 1e-8). */
+/*
+ * Replace the FP32 gradients by host values (same layout as the parameters),
+ * e.g. to apply an optimizer step to gradients computed elsewhere.
+ */
+int glbm_cnn_set_grads(glbm_cnn cnn, const float* host);
+
+/*
+ * One Adam step (Kingma & Ba, 2015) on the current gradients: with t the
+ * number of Adam steps taken so far by this network, including this one,
+ *   m = 0.9 m + 0.1 g,  v = 0.999 v + 0.001 g^2,
+ *   p -= lr (m / (1 - 0.9^t)) / (sqrt(v / (1 - 0.999^t)) + 1e-8)
+ * elementwise in FP32 on the master weights, which are then re-rounded to
+ * the bf16 weights the convolutions use.  Errors: GLBM_EINVAL for lr <= 0.
+ */
+int glbm_cnn_adam_step(glbm_cnn cnn, float lr);
+
+/* glbm_cnn_backward followed by glbm_cnn_adam_step. */
 int glbm_cnn_train_step(glbm_cnn cnn, const uint16_t* x, const float* target, const uint8_t* mask, int32_t batch,
                         float lr, double* loss);
 
@@ -142,6 +158,21 @@ int glbm_cnn_targets(glbm_ctx ctx, int32_t inst, double rho_scale, double u_scal
  * y FP32 [ny][nx][4] (device): rho = 1 + rho_scale y0, u = u_scale (y1, y2, 0).
  */
 int glbm_cnn_apply(glbm_ctx ctx, int32_t inst, const float* y, double rho_scale, double u_scale);
+
+/*
+ * glbm_cnn_apply that allocates no device memory, for callers that cannot
+ * call hipMalloc (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid it).  The rho - 1 and velocity fields are staged in
+ * a static per-GPU scratch array of GLBM_NOALLOC_MAX_NODES nodes (16 MiB,
+ * held until the process ends) instead of a buffer allocated per call; the
+ * result is the same as glbm_cnn_apply's.  Calls on one GPU share that
+ * array, so calls that overlap on one GPU (several host threads, or
+ * contexts on different streams of one device) race: serialise them.
+ * Errors: as glbm_cnn_apply; GLBM_EINVAL for an instance of more than
+ * GLBM_NOALLOC_MAX_NODES nodes.
+ */
+#define GLBM_NOALLOC_MAX_NODES (1 << 20)
+int glbm_cnn_apply_noalloc(glbm_ctx ctx, int32_t inst, const float* y, double rho_scale, double u_scale);
 
 #ifdef __cplusplus
 }

@@ -67,8 +67,11 @@ def lib(kind: str = "f64"):
         L.ref_init_fields.argtypes = [i32, i32, i32, i32, vp, vp, vp, vp, vp]
         L.ref_solve.argtypes = [i32, i32, i32, i32, u32, f64, vp, vp, vp, vp, vp, vp, i64, i32, f64,
                                 i32, i32, vp, vp, vp, i64]
+        L.ref_round_half.argtypes = [i64, vp, vp]
+        L.ref_store_round.argtypes = [f64, f64, i32, i32, f64]
+        L.ref_store_round.restype = f64
         for fn in ("ref_lattice", "ref_collide_node", "ref_feq_force", "ref_step",
-                   "ref_fields", "ref_init_rest", "ref_init_fields"):
+                   "ref_fields", "ref_init_rest", "ref_init_fields", "ref_round_half"):
             getattr(L, fn).restype = ctypes.c_int
         L.ref_solve.restype = ctypes.c_int64
         _lib[kind] = L
@@ -80,6 +83,20 @@ def num_threads() -> int:
     L = lib()
     L.ref_num_threads.restype = ctypes.c_int
     return int(L.ref_num_threads())
+
+
+def round_half(x):
+    """The oracle's nearest-float16 rounding (ties to even) of every element, as float64."""
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    out = np.empty_like(x)
+    assert lib().ref_round_half(x.size, _p(x), _p(out)) == 0
+    return out
+
+
+def store_round(f, w, mode, scale_log2=0, rho_x=1.0):
+    """The value a reduced-precision store of emulation mode `mode` keeps of population f
+    (w its weight, rho_x the density of the node that writes it)."""
+    return float(lib().ref_store_round(float(f), float(w), int(mode), int(scale_log2), float(rho_x)))
 
 
 def lattice(q: int):

@@ -167,3 +167,18 @@ def loss_and_grads(params, x, target, mask, bf16=False):
     back(0, g_a0, A["x"], A["a0"])
     flat = np.concatenate([np.concatenate([gw.reshape(-1), gb]) for gw, gb in grads])
     return loss, flat, out
+
+
+def adam_step(p, m, v, g, t, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+    """One Adam update (Kingma & Ba, 2015, Algorithm 1) at step t >= 1, in FP64.
+
+    m <- beta1 m + (1 - beta1) g;  v <- beta2 v + (1 - beta2) g^2;
+    p <- p - lr (m / (1 - beta1^t)) / (sqrt(v / (1 - beta2^t)) + eps).
+    Returns the new (p, m, v); the inputs are not modified.
+    """
+    p, m, v, g = (np.asarray(a, dtype=np.float64) for a in (p, m, v, g))
+    m = beta1 * m + (1.0 - beta1) * g
+    v = beta2 * v + (1.0 - beta2) * g * g
+    mhat = m / (1.0 - beta1 ** t)
+    vhat = v / (1.0 - beta2 ** t)
+    return p - lr * mhat / (np.sqrt(vhat) + eps), m, v

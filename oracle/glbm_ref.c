@@ -119,6 +119,8 @@ int ref_lattice(int q, int32_t* e, double* w, int32_t* opp)
     return 0;
 }
 
+static real store_round(real f, real w, int mode, int scale_log2, real rho_x);
+
 /* Nearest float16 value of x (ties to even), +-inf past 65504. */
 static double round_half(double x)
 {
@@ -132,6 +134,19 @@ static double round_half(double x)
     double r = nearbyint(a / quantum) * quantum; /* default rounding mode: ties to even */
     if (r > 65504.0) r = INFINITY;
     return x < 0 ? -r : r;
+}
+
+/* round_half of every element of x (n values) into out, for the tests. */
+int ref_round_half(int64_t n, const double* x, double* out)
+{
+    for (int64_t k = 0; k < n; ++k) out[k] = round_half(x[k]);
+    return 0;
+}
+
+/* Storage rounding of one value (store_round below), for the tests. */
+double ref_store_round(double f, double w, int mode, int scale_log2, double rho_x)
+{
+    return (double)store_round((real)f, (real)w, mode, scale_log2, (real)rho_x);
 }
 
 /* mode 1: (f - w) through float; mode 2: (f - w) 2^s through float16;

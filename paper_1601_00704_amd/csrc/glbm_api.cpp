@@ -10,6 +10,7 @@
 #include <cstdio>
 #include <cstring>
 #include <limits>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -80,6 +81,13 @@ int validate(int32_t n_inst, const glbm_instance_desc* d)
         if ((x.store == GLBM_STORE_F16DEV || x.store == GLBM_STORE_F16LOC) && x.dev_scale_log2 != GLBM_SCALE_AUTO &&
             (x.dev_scale_log2 < 0 || x.dev_scale_log2 > 30))
             return fail(GLBM_EINVAL, "instance %d: dev_scale_log2 must be in [0, 30]", i);
+        if (x.flags & ~(uint32_t)GLBM_FLAG_F16DEV_OPT_IN) return fail(GLBM_EINVAL, "instance %d: unknown flag bits", i);
+        if (x.store == GLBM_STORE_F16DEV && !(x.flags & GLBM_FLAG_F16DEV_OPT_IN))
+            return fail(GLBM_EINVAL,
+                        "instance %d: GLBM_STORE_F16DEV resolves the velocity part of f only relative to the density "
+                        "deviation (k several percent off on shale maps); use GLBM_STORE_F16LOC, or set "
+                        "GLBM_FLAG_F16DEV_OPT_IN to run it as a study form",
+                        i);
         if (x.lattice != d[0].lattice || x.store != d[0].store || x.check_every != d[0].check_every)
             return fail(GLBM_EINVAL, "instance %d: lattice, store and check_every must match instance 0", i);
     }
@@ -118,8 +126,43 @@ int auto_scale(const glbm_instance_desc& d)
 
 void glbm::set_error(const char* msg) { g_err = msg; }
 
+// ------------------------------------------------ allocation-free scratch --
+// Staging of glbm_cnn_apply_noalloc (rho - 1 and three velocity planes of one
+// instance, floats).  Each GPU holds its own copy until the process ends.  In
+// host code the name `scratch` is only a stand-in for the symbol: kernels get
+// the device address that hipGetSymbolAddress returns for the current device,
+// fetched once per device when a context is created there.
+static __device__ __align__(256) float scratch[4 * (size_t)GLBM_NOALLOC_MAX_NODES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on device dev (current at the call); GLBM_OK or GLBM_EDEVICE.
+int fetch_scratch(int dev)
+{
+    if (dev < 0 || dev >= kMaxDevices) return fail(GLBM_EDEVICE, "device %d outside the scratch table", dev);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_ptr[dev]) return GLBM_OK;
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+        return fail(GLBM_EDEVICE, "hipGetSymbolAddress(scratch) on device %d: %s", dev, hipGetErrorString(e));
+    g_scratch_ptr[dev] = p;
+    return GLBM_OK;
+}
+
+float* scratch_of(int dev)
+{
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    return (dev >= 0 && dev < kMaxDevices) ? static_cast<float*>(g_scratch_ptr[dev]) : nullptr;
+}
+}  // namespace
+
 struct glbm_ctx_s {
     int n_inst = 0;
+    int device = 0;   // HIP device current at glbm_init_geometry
     Config cfg{};
     int n_c = 100;
     size_t esz = 0, tsz = 0;
@@ -443,6 +486,8 @@ int glbm_init_geometry(glbm_ctx* out, int32_t n_inst, const glbm_instance_desc* 
                                                "%s failed: %s", #expr, hipGetErrorString(e_)));    \
     } while (0)
 
+    TRYHIP(hipGetDevice(&c->device));
+    TRY(fetch_scratch(c->device));
     TRYHIP(hipStreamCreateWithFlags(&c->work, hipStreamDefault));
     TRYHIP(hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
     TRYHIP(hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming));
@@ -788,18 +833,18 @@ int glbm_set_fields(glbm_ctx c, int32_t inst, const double* rho, const double* u
     return joined.done();
 }
 
-int glbm_set_fields_device(glbm_ctx c, int32_t inst, const float* rho_dev, const float* u_dev)
+int glbm_set_fields_device(glbm_ctx c, int32_t inst, const float* drho_dev, const float* u_dev)
 {
     g_err.clear();
     if (!c) return fail(GLBM_EINVAL, "null context");
     if (inst < 0 || inst >= c->n_inst) return fail(GLBM_EINVAL, "instance %d out of range", inst);
-    if (!rho_dev || !u_dev) return fail(GLBM_EINVAL, "rho and u are required");
+    if (!drho_dev || !u_dev) return fail(GLBM_EINVAL, "drho and u are required");
     int rc = check_tables(c);
     if (rc) return rc;
     rc = enter(c);
     if (rc) return rc;
     Joined joined(c);
-    rc = set_fields_impl(c, inst, rho_dev, u_dev, 0);
+    rc = set_fields_impl(c, inst, drho_dev, u_dev, 0);
     if (rc) return rc;
     return joined.done();
 }
@@ -1143,6 +1188,31 @@ int glbm_cnn_apply(glbm_ctx c, int32_t inst, const float* y, double rho_scale, d
     (void)hipFree(d);
     if (rc) return rc;
     HIPCHK(es);
+    return joined.done();
+}
+
+int glbm_cnn_apply_noalloc(glbm_ctx c, int32_t inst, const float* y, double rho_scale, double u_scale)
+{
+    g_err.clear();
+    if (!c || !y) return fail(GLBM_EINVAL, "null argument");
+    if (inst < 0 || inst >= c->n_inst) return fail(GLBM_EINVAL, "instance %d out of range", inst);
+    const InstDev& I = c->inst_h[inst];
+    const long long n = (long long)I.nx * I.ny * I.nz;
+    if (n > GLBM_NOALLOC_MAX_NODES)
+        return fail(GLBM_EINVAL, "instance %d has %lld nodes, more than the %d of the allocation-free scratch", inst, n,
+                    (int)GLBM_NOALLOC_MAX_NODES);
+    int rc = check_tables(c);
+    if (rc) return rc;
+    float* d = scratch_of(c->device);
+    if (!d) return fail(GLBM_ESTATE, "no scratch address for device %d", c->device);
+    rc = enter(c);
+    if (rc) return rc;
+    Joined joined(c);
+    // every element of the 4n staged floats is written before it is read: nothing to clear
+    const hipError_t e = launch_cnn_apply(y, n, rho_scale, u_scale, d, d + n, c->work);
+    if (e != hipSuccess) return fail(GLBM_EDEVICE, "apply: %s", hipGetErrorString(e));
+    rc = set_fields_impl(c, inst, d, d + n, 0);
+    if (rc) return rc;
     return joined.done();
 }
 

@@ -675,11 +675,13 @@ __global__ void k_targets(const double* rho, const double* u, const uint8_t* cls
     mask[i] = fluid ? 1 : 0;
 }
 
-__global__ void k_apply(const float* y, long long n, double rs, double us, float* rho, float* u)
+// Prediction -> fields for the equilibrium start: rho - 1 (not rho, which
+// would round a deviation of 1e-6 to a few digits) and the velocity planes.
+__global__ void k_apply(const float* y, long long n, double rs, double us, float* drho, float* u)
 {
     const long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
     if (i >= n) return;
-    rho[i] = float(1.0 + rs * y[4 * i + 0]);
+    drho[i] = float(rs * y[4 * i + 0]);
     u[i] = float(us * y[4 * i + 1]);
     u[n + i] = float(us * y[4 * i + 2]);
     u[2 * n + i] = 0.f;
@@ -861,9 +863,9 @@ hipError_t launch_cnn_targets(const double* rho, const double* u, const uint8_t*
     hipLaunchKernelGGL(k_targets, dim3(nblocks(n)), dim3(256), 0, s, rho, u, cls, n, rs, us, target, mask);
     return hipGetLastError();
 }
-hipError_t launch_cnn_apply(const float* y, long long n, double rs, double us, float* rho, float* u, hipStream_t s)
+hipError_t launch_cnn_apply(const float* y, long long n, double rs, double us, float* drho, float* u, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_apply, dim3(nblocks(n)), dim3(256), 0, s, y, n, rs, us, rho, u);
+    hipLaunchKernelGGL(k_apply, dim3(nblocks(n)), dim3(256), 0, s, y, n, rs, us, drho, u);
     return hipGetLastError();
 }
 }  // namespace glbm
@@ -1219,22 +1221,53 @@ int glbm_cnn_get_grads(glbm_cnn c, float* host)
     return GLBM_OK;
 }
 
-int glbm_cnn_set_params(glbm_cnn c, const float* host)
+static void to_device_order(const glbm_cnn c, const float* host, std::vector<float>& dev)
 {
-    if (!c || !host) return cfail(GLBM_EINVAL, "null argument");
-    std::vector<float> d((size_t)c->nparam);
+    dev.assign((size_t)c->nparam, 0.f);
     for (const auto& l : c->L) {
         for (int co = 0; co < l.cout; ++co)
             for (int ci = 0; ci < l.cin; ++ci)
                 for (int t = 0; t < 9; ++t)
-                    d[l.wofs + ((size_t)co * 9 + t) * l.cin + ci] = host[l.wofs + ((size_t)co * l.cin + ci) * 9 + t];
-        for (int co = 0; co < l.cout; ++co) d[l.bofs + co] = host[l.bofs + co];
+                    dev[l.wofs + ((size_t)co * 9 + t) * l.cin + ci] = host[l.wofs + ((size_t)co * l.cin + ci) * 9 + t];
+        for (int co = 0; co < l.cout; ++co) dev[l.bofs + co] = host[l.bofs + co];
     }
+}
+
+int glbm_cnn_set_params(glbm_cnn c, const float* host)
+{
+    if (!c || !host) return cfail(GLBM_EINVAL, "null argument");
+    std::vector<float> d;
+    to_device_order(c, host, d);
     CHK(hipMemcpyAsync(c->p, d.data(), d.size() * 4, hipMemcpyHostToDevice, c->s));
     int rc = pack_all(c);
     if (rc) return rc;
     CHK(hipStreamSynchronize(c->s));
     return GLBM_OK;
+}
+
+int glbm_cnn_set_grads(glbm_cnn c, const float* host)
+{
+    if (!c || !host) return cfail(GLBM_EINVAL, "null argument");
+    std::vector<float> d;
+    to_device_order(c, host, d);
+    CHK(hipMemcpyAsync(c->g, d.data(), d.size() * 4, hipMemcpyHostToDevice, c->s));
+    CHK(hipStreamSynchronize(c->s));
+    return GLBM_OK;
+}
+
+int glbm_cnn_adam_step(glbm_cnn c, float lr)
+{
+    if (!c) return cfail(GLBM_EINVAL, "null argument");
+    if (!(lr > 0.f) || !std::isfinite(lr)) return cfail(GLBM_EINVAL, "learning rate must be finite and > 0");
+    c->step += 1;
+    const float b1 = 0.9f, b2 = 0.999f;
+    // bias corrections 1 - beta^t evaluated in double, then rounded once
+    const float c1 = (float)(1.0 - std::pow(0.9, (double)c->step));
+    const float c2 = (float)(1.0 - std::pow(0.999, (double)c->step));
+    hipLaunchKernelGGL(k_adam, dim3(nblocks(c->nparam)), dim3(256), 0, c->s, c->p, c->g, c->m1, c->m2, c->nparam, lr, b1,
+                       b2, c1, c2, 1e-8f);
+    CHK(hipGetLastError());
+    return pack_all(c);
 }
 
 int glbm_cnn_forward(glbm_cnn c, const uint16_t* x, float* y, int32_t batch)
@@ -1260,13 +1293,7 @@ int glbm_cnn_train_step(glbm_cnn c, const uint16_t* x, const float* target, cons
 {
     int rc = glbm_cnn_backward(c, x, target, mask, batch, loss);
     if (rc) return rc;
-    c->step += 1;
-    const float b1 = 0.9f, b2 = 0.999f;
-    const float c1 = 1.f - std::pow(b1, (float)c->step), c2 = 1.f - std::pow(b2, (float)c->step);
-    hipLaunchKernelGGL(k_adam, dim3(nblocks(c->nparam)), dim3(256), 0, c->s, c->p, c->g, c->m1, c->m2, c->nparam, lr, b1,
-                       b2, c1, c2, 1e-8f);
-    CHK(hipGetLastError());
-    return pack_all(c);
+    return glbm_cnn_adam_step(c, lr);
 }
 
 }  // extern "C"

@@ -109,7 +109,8 @@ hipError_t launch_observe(const Config& c, const Args& a, int mode, hipStream_t 
 hipError_t launch_finalize(const Args& a, int n_inst, double tol, int with_r, int count_check,
                            hipStream_t s);
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
-// Write the equilibrium of (rho, u) of instance `inst` (device arrays; T = double or float)
+// Write the equilibrium of (rho, u) of instance `inst` (device arrays): src_is_double = 1 reads
+// rho as double, 0 reads rho - 1 as float; u is 3 planes of N of the same type
 hipError_t launch_set_fields(const Config& c, const Args& a, int inst, int ntiles, const void* rho,
                              const void* u, int src_is_double, hipStream_t s);
 // Density, velocity (double, N and 3N) and optionally populations (double, q*N) of instance `inst`
@@ -120,7 +121,7 @@ hipError_t launch_get_fields(const Config& c, const Args& a, int inst, int ntile
 hipError_t launch_cnn_features(const uint8_t* cls, long long n, const float* table, uint16_t* x, hipStream_t s);
 hipError_t launch_cnn_targets(const double* rho, const double* u, const uint8_t* cls, long long n, double rs,
                               double us, float* target, uint8_t* mask, hipStream_t s);
-hipError_t launch_cnn_apply(const float* y, long long n, double rs, double us, float* rho, float* u, hipStream_t s);
+hipError_t launch_cnn_apply(const float* y, long long n, double rs, double us, float* drho, float* u, hipStream_t s);
 
 // Error message of the calling thread (glbm_api.cpp).
 void set_error(const char* msg);

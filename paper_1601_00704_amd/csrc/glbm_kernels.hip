@@ -731,9 +731,12 @@ __global__ void k_zero(uint32_t* p, size_t n)
 }
 
 // Equilibrium of (rho, u) written so that the next pull reads it back as f(x).
+// A double source holds rho; a float source holds rho - 1, so that a small
+// density deviation is not rounded against 1 before it reaches the kernel.
 template <int Q, int STORE, int BC, typename R>
 __global__ __launch_bounds__(kBlock) void k_set_fields(Args a, int inst, const R* rho_in, const R* u_in)
 {
+    constexpr bool kDrho = sizeof(R) == 4;
     using SS = St<STORE>;
     using S = typename SS::S;
     using T = typename SS::T;
@@ -755,16 +758,17 @@ __global__ __launch_bounds__(kBlock) void k_set_fields(Args a, int inst, const R
         const int n = (z * I.ny + y) * I.nx + x;
         const int c = cls[n];
         if (c == kWallClass) continue;
-        const T rho = T(rho_in[n]);
+        const auto drho_at = [&](int m) { return kDrho ? T(rho_in[m]) : T(rho_in[m] - R(1)); };
+        const T drn = drho_at(n);
+        const T rho = T(1) + drn;
         const T u[3] = {T(u_in[n]), T(u_in[N + n]), T(u_in[2 * N + n])};
-        if (SS::kRho) rho_plane<STORE>(dst, Q, I.stride)[n] = T(rho_in[n] - R(1));
+        if (SS::kRho) rho_plane<STORE>(dst, Q, I.stride)[n] = drn;
         const T ieps = tabg[c * kTabW + TAB_INV_EPS];
         const T uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
             const T eu = T(L::ex(i)) * u[0] + T(L::ey(i)) * u[1] + T(L::ez(i)) * u[2];
-            const T dq = T(L::w(i)) * ((rho - T(1)) +
-                                        rho * (T(3) * eu + T(4.5) * ieps * eu * eu - T(1.5) * ieps * uu));
+            const T dq = T(L::w(i)) * (drn + rho * (T(3) * eu + T(4.5) * ieps * eu * eu - T(1.5) * ieps * uu));
             // destination slot: the pull of direction i at n reads plane i at n - e_i
             // when that move is open, else plane opp(i) at n itself.
             const int ex = L::ex(i), ey = L::ey(i), ez = L::ez(i);
@@ -780,7 +784,7 @@ __global__ __launch_bounds__(kBlock) void k_set_fields(Args a, int inst, const R
             if (BC >= 2 && !blocked && i != 0) blocked = cls[sn] == kWallClass;
             const int idx = blocked ? pidx<Q, STORE>(L::opp(i), n, I.stride) : pidx<Q, STORE>(i, sn, I.stride);
             // a kRho value is decoded with the density of the node whose slot it occupies
-            const T dr = SS::kRho ? T(rho_in[blocked ? n : sn] - R(1)) : T(0);
+            const T dr = SS::kRho ? drho_at(blocked ? n : sn) : T(0);
             dst[idx] = SS::enc(dq - T(L::w(i)) * dr, I.scale);
         }
     }

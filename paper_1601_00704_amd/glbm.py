@@ -25,6 +25,7 @@ GLBM_OK, GLBM_EINVAL, GLBM_ENOMEM, GLBM_EDEVICE, GLBM_ESTATE, GLBM_ENONFINITE, G
 GLBM_WALL_CLASS = 255
 GLBM_SCALE_AUTO = -2147483648
 GLBM_OPT_GRAPH, GLBM_OPT_TIMING, GLBM_OPT_TILE_ROWS, GLBM_OPT_TILE_WIDTH, GLBM_OPT_CACHE = 1, 2, 3, 4, 5
+GLBM_FLAG_F16DEV_OPT_IN = 1
 STORE_NAMES = {"f64": GLBM_STORE_F64, "f32": GLBM_STORE_F32, "f16dev": GLBM_STORE_F16DEV,
                "f16loc": GLBM_STORE_F16LOC, "f32loc": GLBM_STORE_F32LOC}
 STORE_BYTES = {GLBM_STORE_F64: 8, GLBM_STORE_F32: 4, GLBM_STORE_F16DEV: 2, GLBM_STORE_F16LOC: 2,
@@ -45,7 +46,7 @@ EXPORTS = ("glbm_required_bytes", "glbm_init_geometry", "glbm_set_local_perm", "
            "glbm_conv3x3_backward_weight", "glbm_cnn_create", "glbm_cnn_destroy", "glbm_cnn_num_params",
            "glbm_cnn_get_params", "glbm_cnn_set_params", "glbm_cnn_get_grads", "glbm_cnn_forward",
            "glbm_cnn_backward", "glbm_cnn_train_step", "glbm_cnn_features", "glbm_cnn_targets",
-           "glbm_cnn_apply")
+           "glbm_cnn_apply", "glbm_cnn_set_grads", "glbm_cnn_adam_step", "glbm_cnn_apply_noalloc")
 
 
 class GlbmError(RuntimeError):
@@ -58,7 +59,8 @@ class glbm_instance_desc(ctypes.Structure):
     _fields_ = [("lattice", ctypes.c_int32), ("store", ctypes.c_int32), ("nx", ctypes.c_int32),
                 ("ny", ctypes.c_int32), ("nz", ctypes.c_int32), ("wall_faces", ctypes.c_uint32),
                 ("tau", ctypes.c_double), ("g", ctypes.c_double * 3),
-                ("dev_scale_log2", ctypes.c_int32), ("check_every", ctypes.c_int32)]
+                ("dev_scale_log2", ctypes.c_int32), ("check_every", ctypes.c_int32),
+                ("flags", ctypes.c_uint32)]
 
 
 class glbm_gas_params(ctypes.Structure):
@@ -112,6 +114,9 @@ def _load():
         "glbm_cnn_features": (i32, [vp, i32, f64, vp]),
         "glbm_cnn_targets": (i32, [vp, i32, f64, f64, vp, vp]),
         "glbm_cnn_apply": (i32, [vp, i32, vp, f64, f64]),
+        "glbm_cnn_set_grads": (i32, [vp, vp]),
+        "glbm_cnn_apply_noalloc": (i32, [vp, i32, vp, f64, f64]),
+        "glbm_cnn_adam_step": (i32, [vp, ctypes.c_float]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -138,7 +143,7 @@ def _ptr(a: np.ndarray):
 
 
 def make_desc(shape, lattice=GLBM_D2Q9, store=GLBM_STORE_F32, tau=1.0, g=(1e-6, 0.0, 0.0),
-              wall_faces=0, dev_scale_log2=GLBM_SCALE_AUTO, check_every=100) -> glbm_instance_desc:
+              wall_faces=0, dev_scale_log2=GLBM_SCALE_AUTO, check_every=100, flags=0) -> glbm_instance_desc:
     """Descriptor of one instance; shape is (ny, nx) or (nz, ny, nx)."""
     if len(shape) == 2:
         nz, ny, nx = 1, shape[0], shape[1]
@@ -149,7 +154,7 @@ def make_desc(shape, lattice=GLBM_D2Q9, store=GLBM_STORE_F32, tau=1.0, g=(1e-6, 
     d.wall_faces, d.tau = wall_faces, tau
     for a in range(3):
         d.g[a] = float(g[a])
-    d.dev_scale_log2, d.check_every = dev_scale_log2, check_every
+    d.dev_scale_log2, d.check_every, d.flags = dev_scale_log2, check_every, flags
     return d
 
 
@@ -203,8 +208,8 @@ def glbm_set_fields(ctx, inst: int, rho, u):
     _check(_lib.glbm_set_fields(ctx, inst, _ptr(rho), _ptr(u)))
 
 
-def glbm_set_fields_device(ctx, inst: int, rho_dev: int, u_dev: int):
-    _check(_lib.glbm_set_fields_device(ctx, inst, rho_dev, u_dev))
+def glbm_set_fields_device(ctx, inst: int, drho_dev: int, u_dev: int):
+    _check(_lib.glbm_set_fields_device(ctx, inst, drho_dev, u_dev))
 
 
 def glbm_get_fields(ctx, inst: int, n: int):
@@ -353,6 +358,15 @@ def glbm_cnn_get_grads(cnn) -> np.ndarray:
     return a
 
 
+def glbm_cnn_set_grads(cnn, grads):
+    a = np.ascontiguousarray(grads, dtype=np.float32)
+    _check(_lib.glbm_cnn_set_grads(cnn, _ptr(a)))
+
+
+def glbm_cnn_adam_step(cnn, lr):
+    _check(_lib.glbm_cnn_adam_step(cnn, float(lr)))
+
+
 def glbm_cnn_forward(cnn, x, y, batch):
     _check(_lib.glbm_cnn_forward(cnn, x, y, batch))
 
@@ -379,6 +393,13 @@ def glbm_cnn_targets(ctx, inst, rho_scale, u_scale, target, mask):
 
 def glbm_cnn_apply(ctx, inst, y, rho_scale, u_scale):
     _check(_lib.glbm_cnn_apply(ctx, inst, y, float(rho_scale), float(u_scale)))
+
+
+def glbm_cnn_apply_noalloc(ctx, inst, y, rho_scale, u_scale):
+    _check(_lib.glbm_cnn_apply_noalloc(ctx, inst, y, float(rho_scale), float(u_scale)))
+
+
+GLBM_NOALLOC_MAX_NODES = 1 << 20
 
 
 def to_bf16_bits(a: np.ndarray) -> np.ndarray:

@@ -53,13 +53,22 @@ def case_shale128():
 
 
 def case_crop():
+    """The (0, 0) 512 x 512 crop of the 4096^2 benchmark map, run as a periodic instance."""
     inst = si.shale4096(4096)
     cls = inst.classes()
-    crop = np.ascontiguousarray(cls[:512, :512])
+    crop = si.shale4096_crops(inst, cls, 512)[0]
     solve_case("shale4096_crop512_oracle", inst, crop, 1e-8, 2000000, precision="f64")
 
 
-CASES = {"shale128": case_shale128, "crop": case_crop}
+def case_crop3d():
+    """The 64^3 corner crop of the 256^3 D3Q19 map (walls on the x/y faces, drive along z)."""
+    inst = si.shale3d(256)
+    cls = inst.classes()
+    crop = np.ascontiguousarray(cls[:64, :64, :64])
+    solve_case("shale3d_crop64_oracle", inst, crop, 1e-7, 400000, precision="f64")
+
+
+CASES = {"shale128": case_shale128, "crop": case_crop, "crop3d": case_crop3d}
 
 if __name__ == "__main__":
     for c in (sys.argv[1:] or ["shale128"]):

@@ -20,7 +20,8 @@ def gpu_solver(g, q, cls, eps, k, f_eps=None, tau=1.0, G=(1e-6, 0, 0), walls=0, 
     shape = cls.shape
     d = g.make_desc(shape, lattice=q, store=g.STORE_NAMES[store], tau=tau, g=G, wall_faces=walls,
                     check_every=check_every,
-                    dev_scale_log2=g.GLBM_SCALE_AUTO if scale_log2 is None else scale_log2)
+                    dev_scale_log2=g.GLBM_SCALE_AUTO if scale_log2 is None else scale_log2,
+                    flags=g.GLBM_FLAG_F16DEV_OPT_IN if store == "f16dev" else 0)
     s = g.Solver([d], [cls])
     n_cls = 255
     eps = np.broadcast_to(np.asarray(eps, np.float64), (256,))[:n_cls]

@@ -51,8 +51,9 @@ def test_required_bytes_and_validation():
     nb = g.glbm_required_bytes([ok])
     assert nb >= 2 * 9 * 32 * 64 * 4 and nb % 256 == 0
     nb64 = g.glbm_required_bytes([_desc(g, store=g.GLBM_STORE_F64)])
-    nb16 = g.glbm_required_bytes([_desc(g, store=g.GLBM_STORE_F16DEV)])
-    assert nb64 > nb > nb16
+    nb16 = g.glbm_required_bytes([_desc(g, store=g.GLBM_STORE_F16DEV, flags=g.GLBM_FLAG_F16DEV_OPT_IN)])
+    nb16l = g.glbm_required_bytes([_desc(g, store=g.GLBM_STORE_F16LOC)])
+    assert nb64 > nb > nb16l > nb16
     bad = [
         _desc(g, tau=0.5),
         _desc(g, check_every=7),
@@ -61,12 +62,16 @@ def test_required_bytes_and_validation():
         _desc(g, lattice=7),
         _desc(g, store=5),
         _desc(g, shape=(0, 8)),
-        _desc(g, store=g.GLBM_STORE_F16DEV, dev_scale_log2=40),
+        _desc(g, store=g.GLBM_STORE_F16DEV, dev_scale_log2=40, flags=g.GLBM_FLAG_F16DEV_OPT_IN),
         _desc(g, g=(float("nan"), 0, 0)),
+        _desc(g, flags=2),                      # unknown flag bit
     ]
     for d in bad:
         assert g.glbm_required_bytes([d]) == 0
         assert g.glbm_last_error() != ""
+    # the literal FP16 deviation store needs its explicit opt-in, and the message says why
+    assert g.glbm_required_bytes([_desc(g, store=g.GLBM_STORE_F16DEV)]) == 0
+    assert "F16LOC" in g.glbm_last_error() and "OPT_IN" in g.glbm_last_error()
     # mixed lattices / stores in one context are rejected
     assert g.glbm_required_bytes([ok, _desc(g, store=g.GLBM_STORE_F64)]) == 0
     assert g.glbm_required_bytes([ok, _desc(g, shape=(16, 16))]) > nb

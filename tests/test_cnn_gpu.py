@@ -199,15 +199,59 @@ def test_network_forward_and_gradients(gpu):
     le = abs(loss - lref) / lref
     ge = np.linalg.norm(grads - gref) / np.linalg.norm(gref)
     print("network: forward rel L2 %.2e  loss rel %.2e  grad rel L2 %.2e" % (fe, le, ge))
-    assert fe < 5e-3 and le < 5e-3 and ge < 2e-2
-    # per layer
+    # BF16 bar: <= 2e-3 on the global relative L2 ...
+    assert fe <= 2e-3 and le <= 2e-3 and ge <= 2e-3
+    # ... and <= 1e-2 per element, relative to the element's own magnitude floored at the
+    # RMS of its tensor (outputs per channel, gradients per layer's weights and biases):
+    # an element far below its tensor's scale is compared at that scale.
+    for c in range(3):
+        o_, r_ = out[..., c], oref[..., c]
+        den = np.maximum(np.abs(r_), np.sqrt(np.mean(r_ * r_)))
+        worst = (np.abs(o_ - r_) / den).max()
+        print("  output channel %d: worst element rel %.2e" % (c, worst))
+        assert worst <= 1e-2
     o = 0
     for i, (ci, co, _) in enumerate(C.SPEC):
-        n = co * ci * 9 + co
-        e = np.linalg.norm(grads[o:o + n] - gref[o:o + n]) / np.linalg.norm(gref[o:o + n])
-        print("  layer %d grad rel L2 %.2e" % (i, e))
-        assert e < 3e-2
-        o += n
+        for part, n in (("w", co * ci * 9), ("b", co)):
+            gg, rr = grads[o:o + n], gref[o:o + n]
+            den = np.maximum(np.abs(rr), np.sqrt(np.mean(rr * rr)))
+            worst = (np.abs(gg - rr) / den).max()
+            l2 = np.linalg.norm(gg - rr) / np.linalg.norm(rr)
+            print("  layer %d %s grad: rel L2 %.2e, worst element rel %.2e" % (i, part, l2, worst))
+            assert worst <= 1e-2
+            o += n
+
+
+def test_adam_matches_oracle(gpu):
+    """glbm_cnn_adam_step on seeded gradients (set through glbm_cnn_set_grads) against the
+    FP64 Adam of the oracle, four steps in a row, element by element: within 3 FP32 ulps of
+    the parameter plus 1e-5 of the learning rate (FP32 moments and update)."""
+    g = gpu
+    cnn = g.glbm_cnn_create(1, 256, 256, seed=5)
+    try:
+        n = g.glbm_cnn_num_params(cnn)
+        rng = np.random.default_rng(31)
+        p0 = (0.05 * rng.standard_normal(n)).astype(np.float32)
+        g.glbm_cnn_set_params(cnn, p0)
+        p, m, v = p0.astype(np.float64), np.zeros(n), np.zeros(n)
+        lr = 1e-3
+        for t in range(1, 5):
+            gr = (rng.standard_normal(n) * 10.0 ** rng.uniform(-6, 1, n)).astype(np.float32)
+            if t == 3:
+                gr[::7] = 0.0
+            g.glbm_cnn_set_grads(cnn, gr)
+            g.glbm_cnn_adam_step(cnn, lr)
+            p, m, v = C.adam_step(p, m, v, gr.astype(np.float64), t, lr)
+        got = g.glbm_cnn_get_params(cnn).astype(np.float64)
+        with pytest.raises(g.GlbmError):
+            g.glbm_cnn_adam_step(cnn, 0.0)
+    finally:
+        g.glbm_cnn_destroy(cnn)
+    bound = 3 * np.spacing(np.abs(p).astype(np.float32)).astype(np.float64) + 1e-5 * lr
+    err = np.abs(got - p)
+    print("adam: max err %.3e, max err / bound %.3f, mean |step| %.3e" % (err.max(), (err / bound).max(),
+                                                                         np.abs(p - p0).mean()))
+    assert np.all(err <= bound)
 
 
 def test_training_reduces_loss(gpu):

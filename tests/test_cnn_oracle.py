@@ -90,3 +90,43 @@ def test_network_gradient_finite_differences(bf16):
         lm = C.loss_and_grads(p, x, target, mask)[0]
         fd = (lp - lm) / (2 * h)
         assert abs(fd - g[i]) <= 1e-6 * max(1.0, abs(g[i])) + 1e-7, (i, fd, g[i])
+
+
+# ------------------------------------------------------------------ Adam --
+def test_adam_first_step_moves_by_lr_times_sign():
+    """Bias correction makes the first Adam step lr g / (|g| + eps): lr sign(g)
+    wherever |g| >> eps, whatever the scale of g (Kingma & Ba, 2015, Sec. 3)."""
+    rng = np.random.default_rng(1)
+    p0 = rng.standard_normal(5000)
+    g = rng.standard_normal(5000) * 10.0 ** rng.uniform(-4, 3, 5000)
+    lr = 1e-3
+    p1, m, v = C.adam_step(p0, np.zeros_like(p0), np.zeros_like(p0), g, 1, lr)
+    assert np.allclose(p0 - p1, lr * g / (np.abs(g) + 1e-8), rtol=1e-12, atol=0)
+    big = np.abs(g) > 1e-4
+    assert big.sum() > 4000
+    assert np.allclose(np.abs(p0 - p1)[big], lr, rtol=1e-3)
+    assert np.array_equal(np.sign(p0 - p1), np.sign(g))
+
+
+def test_adam_constant_and_alternating_gradients():
+    """With a constant gradient the bias-corrected moments are exactly g and g^2,
+    so every step moves by lr g / (|g| + eps).  With g then -g, the second
+    corrected first moment is -(1 - b1) g / (1 + b1) while the second moment
+    stays g^2: the step goes back by lr (1 - b1) / (1 + b1) sign(g).  A zero
+    gradient from zero moments does not move."""
+    rng = np.random.default_rng(2)
+    g = rng.standard_normal(1000) * 10.0 ** rng.uniform(-3, 2, 1000)
+    lr, b1 = 2e-3, 0.9
+    p = np.zeros(1000)
+    m = np.zeros(1000)
+    v = np.zeros(1000)
+    for t in range(1, 8):
+        pn, m, v = C.adam_step(p, m, v, g, t, lr)
+        assert np.allclose(p - pn, lr * g / (np.abs(g) + 1e-8), rtol=1e-9, atol=0)
+        p = pn
+    p1, m1, v1 = C.adam_step(np.zeros(1000), np.zeros(1000), np.zeros(1000), g, 1, lr)
+    p2, _, _ = C.adam_step(p1, m1, v1, -g, 2, lr)
+    step2 = p2 - p1
+    assert np.allclose(step2, lr * (1 - b1) / (1 + b1) * g / (np.abs(g) + 1e-8), rtol=1e-9, atol=0)
+    z, _, _ = C.adam_step(p1, np.zeros(1000), np.zeros(1000), np.zeros(1000), 3, lr)
+    assert np.array_equal(z, p1)

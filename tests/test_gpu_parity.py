@@ -83,16 +83,28 @@ def test_d2q9_tile_shapes_and_cache_policies(gpu, store):
         _compare(gpu, 9, cls, eps, k, None, store, 60, G=(2e-5, 0, 0), tile=tile, cache=cache)
 
 
-def test_d2q9_forchheimer(gpu):
+@pytest.mark.parametrize("store", ["f64", "f32", "f32loc", "f16loc"])
+def test_d2q9_forchheimer(gpu, store):
+    """Eq. (27) with F_eps > 0: the velocity is the root of Eq. (34) with c1 > 0 (Eq. 37)."""
     cls, eps, k, fe = random_case((32, 64), seed=21)
     fe = np.full(256, 0.7)
     fe[0] = 0.0
-    _compare(gpu, 9, cls, eps, k, fe, "f64", 100, G=(5e-4, 1e-4, 0))
+    _compare(gpu, 9, cls, eps, k, fe, store, 100, G=(5e-4, 1e-4, 0))
 
 
-def test_d2q9_tau(gpu):
+@pytest.mark.parametrize("store", ["f64", "f32", "f32loc", "f16loc"])
+def test_d2q9_tau(gpu, store):
     cls, eps, k, fe = random_case((33, 64), seed=4)
-    _compare(gpu, 9, cls, eps, k, None, "f64", 100, G=(2e-5, 0, 0), tau=0.8)
+    _compare(gpu, 9, cls, eps, k, None, store, 100, G=(2e-5, 0, 0), tau=0.8)
+
+
+@pytest.mark.parametrize("store", ["f64", "f32", "f16loc"])
+def test_d3q19_forchheimer_walls(gpu, store):
+    """D3Q19 with Forchheimer classes, tau != 1, face walls and wall nodes."""
+    cls, eps, k, fe = random_case((10, 14, 40), seed=33, wall_frac=0.05)
+    fe = np.full(256, 0.5)
+    fe[0] = 0.0
+    _compare(gpu, 19, cls, eps, k, fe, store, 60, G=(1e-4, 0, 4e-4), walls=0b001111, tau=0.9)
 
 
 @pytest.mark.parametrize("store", ["f64", "f32", "f16dev", "f16loc", "f32loc"])

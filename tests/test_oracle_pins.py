@@ -375,3 +375,99 @@ def test_fp64_and_extended_builds_agree():
         p = oracle.Problem(q=9, cls=cls, eps=eps, k=k, f_eps=0.0, tau=1.0, G=(1e-6, 0, 0), precision=prec)
         ks.append(oracle.solve(p, tol=0, max_steps=2000, check_every=100, stop_at=2000).k[0])
     assert abs(ks[0] - ks[1]) / ks[1] < 1e-9
+
+
+# ------------------------------------------- residual, rounding, storage --
+@pytest.mark.parametrize("q,shape", [(9, (6, 10)), (19, (4, 5, 6))])
+def test_residual_open_pore_closed_form(q, shape):
+    """R8 residual against a closed form.  In a periodic domain of open pore
+    (eps = 1, K = inf) the body force is the only momentum source, so the
+    momentum grows by rho G per step and the velocity of Eq. (34) after t steps
+    from rest is u(t) = G (t + 1/2).  Then r(t) = ||u(t) - u(t - n_c)|| /
+    (n_c ||u(t)||) = 1 / (t + 1/2) exactly, at every check, for both the C
+    residual (the solve's history) and Problem.residual."""
+    cls = np.zeros(shape, np.uint8)
+    G = (3e-6, -2e-6, 1e-6 if q == 19 else 0.0)
+    p = oracle.Problem(q=q, cls=cls, eps=1.0, k=math.inf, f_eps=0.0, tau=0.9, G=G, precision="ext")
+    nc, n = 100, 1000
+    sol = oracle.solve(p, tol=0, max_steps=n, check_every=nc, stop_at=n)
+    t = np.arange(nc, n + 1, nc)
+    assert len(sol.history) == len(t)
+    hist = np.array([h for _, h in sol.history])
+    assert np.all(np.abs(hist * (t + 0.5) - 1.0) < 1e-12)
+    assert np.allclose(sol.u[:, 0] / (n + 0.5), np.asarray(G), rtol=1e-12, atol=0)
+    f = p.rest()
+    p.run(f, n - nc)
+    _, u0 = p.fields(f)
+    p.run(f, nc)
+    _, u1 = p.fields(f)
+    assert abs(p.residual(u1, u0, nc) * (n + 0.5) - 1.0) < 1e-12
+
+
+def _half_cases():
+    rng = np.random.default_rng(2024)
+    # random magnitudes across the whole half range, subnormals and beyond the top
+    a = rng.uniform(-1, 1, 60000) * 2.0 ** rng.uniform(-27, 17, 60000)
+    # exact ties: odd multiples of half a half-precision quantum in every binade
+    e = rng.integers(-14, 16, 20000)
+    m = rng.integers(1024, 2048, 20000)
+    ties = (2 * m + 1) * 2.0 ** (e - 11.0)
+    sub = (2 * rng.integers(0, 1024, 10000) + 1) * 2.0 ** -25          # subnormal ties
+    near = 2.0 ** rng.integers(-24, 16, 10000) * (1 + rng.uniform(-1e-3, 1e-3, 10000))
+    edge = np.array([65504.0, 65519.0, 65519.999, 65520.0, 65535.0, 65536.0, 1e6, 2.0 ** -24, 2.0 ** -25,
+                     2.0 ** -25 * 1.0000001, 2.0 ** -26, 6.0e-8, 0.0, -0.0, 1.0, 2049.0, 2051.0])
+    x = np.concatenate([a, ties, -ties, sub, -sub, near, edge, -edge])
+    return x
+
+
+def test_round_half_matches_numpy_float16():
+    """The oracle's FP16 rounding (used by the FP16 storage emulations) equals
+    IEEE binary16 round-to-nearest-even as NumPy implements it, bit for bit:
+    random values over the whole range, exact ties in every binade, subnormals
+    (quantum 2^-24) and the overflow edge (65504 stays, 65520 and above go to
+    infinity)."""
+    x = _half_cases()
+    want = x.astype(np.float16).astype(np.float64)
+    got = oracle.round_half(x)
+    same = (got == want) | (np.isnan(got) & np.isnan(want))
+    assert np.all(same), x[~same][:10]
+    assert np.array_equal(np.signbit(got), np.signbit(want))
+
+
+@pytest.mark.parametrize("scale", [0, 20, 24])
+def test_store_round_modes_1_and_2(scale):
+    """Storage emulation modes 1 and 2 against NumPy's FP32 and FP16 conversions:
+    mode 1 keeps w + fp32(f - w), mode 2 keeps w + fp16((f - w) 2^s) 2^-s."""
+    rng = np.random.default_rng(7 + scale)
+    w = np.array([4 / 9, 1 / 9, 1 / 36])
+    for _ in range(3000):
+        wi = w[rng.integers(0, 3)]
+        f = wi + rng.uniform(-1, 1) * 10.0 ** rng.uniform(-14, -2)
+        want1 = float(np.float32(f - wi)) + wi
+        want2 = float(np.float16((f - wi) * 2.0 ** scale)) / 2.0 ** scale + wi
+        assert oracle.store_round(f, wi, 1) == want1
+        assert oracle.store_round(f, wi, 2, scale) == want2
+
+
+@pytest.mark.parametrize("mode,scale,tol", [(1, 0, 3e-5), (2, 20, 4e-3)])
+def test_storage_emulation_modes_deviation_forms(mode, scale, tol):
+    """Whole runs in storage modes 1 (FP32 deviations f - w) and 2 (FP16
+    deviations (f - w) 2^s) stay within their storage tolerance of the plain
+    oracle; a wrong scale or a dropped weight is off by orders of magnitude."""
+    rng = np.random.default_rng(12)
+    shape = (24, 34)
+    cls = rng.integers(0, 6, size=shape).astype(np.uint8)
+    eps = np.concatenate([[1.0], rng.uniform(0.1, 0.9, 255)])
+    k = np.concatenate([[math.inf], 10 ** rng.uniform(-3, -1, 255)])
+    G = (2e-5, 1e-5, 0)
+    runs = {}
+    for m, sc in ((0, 0), (mode, scale)):
+        p = oracle.Problem(q=9, cls=cls, eps=eps, k=k, f_eps=0.0, tau=1.0, G=G, store_mode=m, scale_log2=sc)
+        f = p.rest()
+        p.run(f, 300)
+        runs[m] = f.reshape(9, -1)
+    _, w = oracle.lattice(9)[:2]
+    dev = np.abs(runs[0] - np.asarray(w)[:, None]).max()
+    err = np.abs(runs[mode] - runs[0]).max()
+    assert dev > 1e-6
+    assert 0 < err <= tol * dev

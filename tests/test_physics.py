@@ -130,3 +130,20 @@ def test_native_class_table_rejects_bad_input():
     p.langmuir_vl = 0.0
     with pytest.raises(g.GlbmError):
         g.glbm_class_table(p, *inst.radii())
+
+
+def test_methane_reference_density_is_ideal_gas_at_standard_conditions():
+    """Reading R14 of Eq. (38): rho_CH4 is methane at 273.15 K and 101.325 kPa as an
+    ideal gas, P M / (R T) = 0.71576 kg/m^3; the constant keeps four digits."""
+    rho = 101325.0 * kapp.M_CH4 / (kapp.R_GAS * 273.15)
+    assert abs(rho - 0.715759) < 1e-6
+    assert abs(kapp.RHO_CH4_STD - rho) / rho < 1e-4
+
+
+def test_langmuir_capacity_range_over_the_batch_draws():
+    """Eq. (38) over the batch's ranges (V_L 0.002-0.008 m^3/kg, TOC 0.05-0.30,
+    eps_OM 0.3) gives a few hundred to tens of thousands of mol/m^3, bracketing the
+    1000-8000 mol/m^3 the paper quotes next to Eq. (38) for its own data.  A unit slip
+    (litres, MPa, or mass instead of volume) moves it by three orders of magnitude."""
+    q = [kapp.qsat_from_langmuir_volume(vl, 0.3, toc) for vl in (0.002, 0.008) for toc in (0.05, 0.30)]
+    assert 500 < min(q) < 1000 and 8000 < max(q) < 20000
