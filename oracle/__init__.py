@@ -61,12 +61,12 @@ def lib(kind: str = "f64"):
         L.ref_lattice.argtypes = [i32, vp, vp, vp]
         L.ref_collide_node.argtypes = [i32, vp, f64, f64, f64, f64, vp, vp, vp]
         L.ref_feq_force.argtypes = [i32, f64, vp, vp, f64, f64, vp, vp]
-        L.ref_step.argtypes = [i32, i32, i32, i32, u32, f64, vp, vp, vp, vp, vp, vp, vp, i32, i32]
-        L.ref_fields.argtypes = [i32, i32, i32, i32, f64, vp, vp, vp, vp, vp, vp, vp, vp]
+        L.ref_step.argtypes = [i32, i32, i32, i32, u32, f64, vp, vp, vp, vp, vp, vp, vp, i32, i32, vp]
+        L.ref_fields.argtypes = [i32, i32, i32, i32, u32, f64, vp, vp, vp, vp, vp, vp, vp, vp, vp]
         L.ref_init_rest.argtypes = [i32, i64, f64, vp]
         L.ref_init_fields.argtypes = [i32, i32, i32, i32, vp, vp, vp, vp, vp]
         L.ref_solve.argtypes = [i32, i32, i32, i32, u32, f64, vp, vp, vp, vp, vp, vp, i64, i32, f64,
-                                i32, i32, vp, vp, vp, i64]
+                                i32, i32, vp, vp, vp, i64, vp]
         L.ref_round_half.argtypes = [i64, vp, vp]
         L.ref_store_round.argtypes = [f64, f64, i32, i32, f64]
         L.ref_store_round.restype = f64
@@ -131,6 +131,39 @@ def _shape3(shape):
     return tuple(shape)
 
 
+class _RefPressure(ctypes.Structure):
+    """glbm_ref.c ref_pressure: pressure faces and the per-class K(P) coefficients."""
+    _fields_ = [("axis", ctypes.c_int), ("rho_in", ctypes.c_double), ("rho_out", ctypes.c_double),
+                ("k_const", ctypes.c_void_p), ("k_kn", ctypes.c_void_p), ("k_surf", ctypes.c_void_p),
+                ("lang_b", ctypes.c_void_p), ("p_in", ctypes.c_double), ("p_out", ctypes.c_double)]
+
+
+@dataclass
+class Pressure:
+    """Pressure-driven run: density rho_in on the face c_a = 0 and rho_out on c_a = n_a - 1
+    of axis `axis` (0 = x, 1 = y, 2 = z); optional per-class K(P) = k_const + k_kn / P +
+    k_surf / (P (1 + lang_b P)) in lattice units with P mapped affinely from the density
+    between (rho_out, p_out) and (rho_in, p_in).  Without k_const the class table's
+    constant K is used."""
+    axis: int
+    rho_in: float
+    rho_out: float
+    k_const: Optional[np.ndarray] = None
+    k_kn: Optional[np.ndarray] = None
+    k_surf: Optional[np.ndarray] = None
+    lang_b: Optional[np.ndarray] = None
+    p_in: float = 0.0
+    p_out: float = 0.0
+
+    def struct(self):
+        def arr(a):
+            return None if a is None else np.ascontiguousarray(np.broadcast_to(np.asarray(a, np.float64), (256,)))
+        self._keep = [arr(self.k_const), arr(self.k_kn), arr(self.k_surf), arr(self.lang_b)]
+        st = _RefPressure(self.axis + 1, self.rho_in, self.rho_out,
+                          *[None if a is None else a.ctypes.data for a in self._keep], self.p_in, self.p_out)
+        return st
+
+
 @dataclass
 class Problem:
     """One oracle problem: class map plus per-class table, all in lattice units."""
@@ -145,6 +178,7 @@ class Problem:
     store_mode: int = 0             # 0 plain; 1-5 emulate reduced-precision storage (glbm_ref.c store_round)
     scale_log2: int = 0
     precision: str = "f64"          # "f64", or "ext" for the x87 extended-precision build
+    pressure: Optional[Pressure] = None
 
     def __post_init__(self):
         if self.f_eps is None:
@@ -163,6 +197,10 @@ class Problem:
             if ((self.walls >> (2 * a)) & 1) != ((self.walls >> (2 * a + 1)) & 1):
                 raise ValueError("wall faces come in pairs per axis (a one-sided wall with a periodic "
                                  "opposite face is undefined)")
+        self._pr = None if self.pressure is None else self.pressure.struct()
+
+    def _prp(self):
+        return None if self._pr is None else ctypes.addressof(self._pr)
 
     @property
     def nu(self):
@@ -185,7 +223,7 @@ class Problem:
         out = np.zeros_like(f)
         assert lib(self.precision).ref_step(self.q, self.nx, self.ny, self.nz, self.walls, self.tau, _p(self.G),
                               _p(self.cls), _p(self.eps), _p(self.kinv), _p(self.f_eps), _p(f),
-                              _p(out), self.store_mode, self.scale_log2) == 0
+                              _p(out), self.store_mode, self.scale_log2, self._prp()) == 0
         return out
 
     def iterate(self, f, nsteps, check_every=0, tol=0.0):
@@ -198,7 +236,7 @@ class Problem:
         s = lib(self.precision).ref_solve(
             self.q, self.nx, self.ny, self.nz, self.walls, self.tau, _p(self.G), _p(self.cls),
             _p(self.eps), _p(self.kinv), _p(self.f_eps), _p(f), int(nsteps), int(check_every),
-            float(tol), self.store_mode, self.scale_log2, _p(rho), _p(u), _p(hist), cap)
+            float(tol), self.store_mode, self.scale_log2, _p(rho), _p(u), _p(hist), cap, self._prp())
         assert s >= 0, "ref_solve failed (%d)" % s
         nh = int(s // check_every) if check_every > 0 else 0
         return int(s), rho, u.reshape(3, self.N), hist[:nh].copy()
@@ -212,16 +250,23 @@ class Problem:
         """(rho[N], u[3, N]) of the state f."""
         rho = np.zeros(self.N)
         u = np.zeros(3 * self.N)
-        assert lib(self.precision).ref_fields(self.q, self.nx, self.ny, self.nz, self.tau, _p(self.G),
-                                _p(self.cls), _p(self.eps), _p(self.kinv), _p(self.f_eps), _p(f),
-                                _p(rho), _p(u)) == 0
+        assert lib(self.precision).ref_fields(self.q, self.nx, self.ny, self.nz, self.walls, self.tau,
+                                _p(self.G), _p(self.cls), _p(self.eps), _p(self.kinv), _p(self.f_eps),
+                                _p(f), _p(rho), _p(u), self._prp()) == 0
         return rho, u.reshape(3, self.N)
 
     def k_lattice(self, u):
-        """Darcy read-off per axis: nu <u_d> / G_d over fluid nodes (nan where G_d = 0)."""
+        """Darcy read-off per axis: nu <u_d> / G_d over fluid nodes (nan where G_d = 0).  Along
+        the axis of pressure faces: nu <u_a> (n_a - 1) / (c_s^2 (rho_in - rho_out)), Darcy's
+        law with the lattice pressure c_s^2 rho over the node distance between the faces."""
         m = u[:, self.fluid].mean(axis=1)
         with np.errstate(divide="ignore", invalid="ignore"):
-            return np.where(self.G != 0, self.nu * m / np.where(self.G != 0, self.G, 1.0), np.nan)
+            k = np.where(self.G != 0, self.nu * m / np.where(self.G != 0, self.G, 1.0), np.nan)
+        if self.pressure is not None:
+            a = self.pressure.axis
+            na = (self.nx, self.ny, self.nz)[a]
+            k[a] = self.nu * m[a] * (na - 1) / ((self.pressure.rho_in - self.pressure.rho_out) / 3.0)
+        return k
 
     def residual(self, u, u_prev, dsteps):
         d = (u - u_prev)[:, self.fluid]

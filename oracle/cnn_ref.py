@@ -131,8 +131,18 @@ def forward(params, x, bf16=False):
     return A["out"], A
 
 
-def loss_and_grads(params, x, target, mask, bf16=False):
-    """Masked MSE over channels 0..2 and its gradient with respect to the flat parameters."""
+def output_abs_scale(params, A):
+    """Per output element, sum_k |w_k a_k| + |bias| of the last convolution over the
+    activations A of forward(): the scale against which rounding in the inputs of
+    that sum is measured."""
+    w, b = unpack(params)[9]
+    return conv3x3(np.abs(A["a8"]), np.abs(w), np.abs(b))
+
+
+def loss_and_grads(params, x, target, mask, bf16=False, abs_scale=False):
+    """Masked MSE over channels 0..2 and its gradient with respect to the flat parameters.
+    With abs_scale=True also returns, in the same flat layout, sum_pixels |dy| |x| of
+    every weight and sum_pixels |dy| of every bias (the scale of each gradient's sum)."""
     r = round_bf16 if bf16 else (lambda a: a)
     L = unpack(params)
     out, A = forward(params, x, bf16)
@@ -140,15 +150,17 @@ def loss_and_grads(params, x, target, mask, bf16=False):
     cnt = 3.0 * m.sum()
     d = (out - target[..., :3]) * m[..., None]
     loss = float((d * d).sum() / cnt)
-    g = {}
     gout = r(2.0 * d / cnt)
     grads = [None] * 10
+    scales = [None] * 10
 
     def back(i, gy, inp, y):
         """Weight gradient of layer i and the gradient at its input; gy is dL/d(output)."""
         if SPEC[i][2]:
             gy = gy * (y > 0)
         grads[i] = conv3x3_weight_grad(inp, gy)
+        if abs_scale:
+            scales[i] = conv3x3_weight_grad(np.abs(inp), np.abs(gy))
         return conv3x3_data_grad(gy, L[i][0])
 
     g_a8 = r(back(9, gout, A["a8"], None))
@@ -166,6 +178,9 @@ def loss_and_grads(params, x, target, mask, bf16=False):
     g_a0 = r(back(1, g_e1, A["a0"], A["e1"]))
     back(0, g_a0, A["x"], A["a0"])
     flat = np.concatenate([np.concatenate([gw.reshape(-1), gb]) for gw, gb in grads])
+    if abs_scale:
+        sflat = np.concatenate([np.concatenate([sw.reshape(-1), sb]) for sw, sb in scales])
+        return loss, flat, out, sflat, A
     return loss, flat, out
 
 

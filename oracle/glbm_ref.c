@@ -283,16 +283,42 @@ typedef struct {
 } grid_t;
 
 /*
+ * Pressure-driven runs (the inlet / outlet pressures of the paper's Tab. 4 and
+ * Tab. 7) with the local apparent permeability at the local pressure (Eq. 18-19).
+ *   axis      0: none; 1, 2, 3: pressure faces normal to x, y, z.  The face
+ *             c_a = 0 is held at density rho_in, the face c_a = n_a - 1 at
+ *             rho_out; populations leaving through them are lost and those
+ *             entering are rebuilt (fill_pressure_faces).
+ *   k_const, k_kn, k_surf, lang_b   per class, in lattice units (K / dx^2):
+ *             K(P) = k_const + k_kn / P + k_surf / (P (1 + lang_b P)), which is
+ *             Eq. (18) (K_0 + eta D_K / P) plus the surface term of Eq. (19)
+ *             with the ideal-gas density; k_const = +inf marks an open pore.
+ *             NULL: the constant K of the class table.
+ *   p_in, p_out  physical pressures of the two faces.  The lattice density
+ *             carries the pressure of Eq. (26) (c_s^2 rho), so the local
+ *             physical pressure is its affine image
+ *             P(x) = p_out + (rho(x) - rho_out) (p_in - p_out) / (rho_in - rho_out).
+ */
+typedef struct {
+    int axis;
+    double rho_in, rho_out;
+    const double *k_const, *k_kn, *k_surf, *lang_b;
+    double p_in, p_out;
+} ref_pressure;
+
+/*
  * Target of the move x -> x + e_i.  Returns 1 and the (periodically wrapped)
  * target node if the move streams; 0 if it is reflected because it crosses a
- * wall face or lands on a wall node (halfway bounce-back).
+ * wall face or lands on a wall node (halfway bounce-back); 2 if it leaves the
+ * domain through a pressure face.
  */
-static int stream_target(const grid_t* g, const lattice_t* L, const uint8_t* cls, int x, int y, int z,
-                         int i, int64_t* tn)
+static int stream_target(const grid_t* g, const lattice_t* L, const uint8_t* cls, int paxis, int x, int y,
+                         int z, int i, int64_t* tn)
 {
     int c[3] = { x + L->e[i][0], y + L->e[i][1], z + L->e[i][2] };
     int n[3] = { g->nx, g->ny, g->nz };
     for (int a = 0; a < 3; ++a) {
+        if (a == paxis - 1 && (c[a] < 0 || c[a] >= n[a])) return 2;
         if (c[a] < 0) {
             if (g->walls & (1u << (2 * a))) return 0;
             c[a] += n[a];
@@ -315,13 +341,95 @@ typedef struct {
     const uint8_t* cls;
     const double *eps, *kinv, *feps;
     int store_mode, scale_log2;
+    const ref_pressure* pr; /* NULL: no pressure faces, constant K */
 } problem_t;
+
+/* 1/K of class c at a node of density rho: the class table's constant K, or in
+ * a pressure-driven run with per-class K(P) the value at the local pressure. */
+static real local_kinv(const problem_t* P, int c, real rho)
+{
+    const ref_pressure* pr = P->pr;
+    if (!pr || !pr->k_const) return P->kinv[c];
+    if (isinf(pr->k_const[c])) return 0;
+    const real pl = (real)pr->p_out + (rho - (real)pr->rho_out) * ((real)pr->p_in - (real)pr->p_out) /
+                                          ((real)pr->rho_in - (real)pr->rho_out);
+    const real k = (real)pr->k_const[c] + (real)pr->k_kn[c] / pl +
+                   (real)pr->k_surf[c] / (pl * (1 + (real)pr->lang_b[c] * pl));
+    return 1 / k;
+}
+
+/*
+ * Zou-He (non-equilibrium bounce-back) density condition on the pressure
+ * faces.  At a fluid node of the face c_a = 0, with n the unit normal into
+ * the domain (+a) and rho_f = rho_in, the populations with e_i . n > 0 come
+ * from outside and are rebuilt from the known ones: the normal momentum
+ * follows from the imposed density,
+ *     j_n = rho_f - sum_{e.n = 0} f - 2 sum_{e.n < 0} f,
+ * the tangential momentum is set to zero, and the non-equilibrium parts of
+ * opposite populations are equal:
+ *     f_i = f_opp(i) + 6 w_i (e_i . n) j_n - sum_t (e_i . t) N_t,
+ *     N_t = sum_{e.n = 0} f e_t / sum_{e.n > 0} (e . t)^2
+ * over the tangential axes t.  The face c_a = n_a - 1 is the same with
+ * n = -a and rho_out.  Applied to every state, so that a state always
+ * satisfies the face densities (Zou & He, Phys. Fluids 9, 1997).
+ */
+static void fill_pressure_faces(const problem_t* P, real* f)
+{
+    if (!P->pr || !P->pr->axis) return;
+    const lattice_t* L = &P->L;
+    const int q = L->q, a = P->pr->axis - 1;
+    const int n3[3] = { P->g.nx, P->g.ny, P->g.nz };
+    const int64_t N = P->N;
+    for (int z = 0; z < n3[2]; ++z)
+        for (int y = 0; y < n3[1]; ++y)
+            for (int x = 0; x < n3[0]; ++x) {
+                const int c[3] = { x, y, z };
+                const int64_t n = ((int64_t)z * n3[1] + y) * n3[0] + x;
+                if (P->cls[n] == WALL_CLASS) continue;
+                for (int side = 0; side < 2; ++side) {
+                    if (c[a] != (side == 0 ? 0 : n3[a] - 1)) continue;
+                    const int sgn = side == 0 ? 1 : -1;
+                    const real rho_f = side == 0 ? (real)P->pr->rho_in : (real)P->pr->rho_out;
+                    real s0 = 0, sneg = 0, nt[3] = { 0, 0, 0 }, den[3] = { 0, 0, 0 };
+                    for (int i = 0; i < q; ++i) {
+                        const int en = sgn * L->e[i][a];
+                        const real fi = f[i * N + n];
+                        if (en == 0) {
+                            s0 += fi;
+                            for (int t = 0; t < 3; ++t)
+                                if (t != a) nt[t] += fi * L->e[i][t];
+                        } else if (en < 0) {
+                            sneg += fi;
+                        } else {
+                            for (int t = 0; t < 3; ++t)
+                                if (t != a) den[t] += (real)(L->e[i][t] * L->e[i][t]);
+                        }
+                    }
+                    const real jn = rho_f - s0 - 2 * sneg;
+                    for (int t = 0; t < 3; ++t) nt[t] = den[t] > 0 ? nt[t] / den[t] : 0;
+                    for (int i = 0; i < q; ++i) {
+                        const int en = sgn * L->e[i][a];
+                        if (en <= 0) continue;
+                        real v = f[L->opp[i] * N + n] + 6 * L->w[i] * en * jn;
+                        for (int t = 0; t < 3; ++t)
+                            if (t != a) v -= L->e[i][t] * nt[t];
+                        f[i * N + n] = v;
+                    }
+                }
+            }
+}
 
 static int make_problem(problem_t* P, int q, int nx, int ny, int nz, unsigned walls, double tau,
                         const double* G, const uint8_t* cls, const double* eps_t, const double* kinv_t,
-                        const double* feps_t, int store_mode, int scale_log2)
+                        const double* feps_t, int store_mode, int scale_log2, const ref_pressure* pr)
 {
     if (make_lattice(q, &P->L)) return -1;
+    P->pr = (pr && pr->axis) ? pr : NULL;
+    if (P->pr) {
+        const int a = pr->axis - 1;
+        const int n3[3] = { nx, ny, nz };
+        if (a < 0 || a > 2 || n3[a] < 2 || ((walls >> (2 * a)) & 3u) || !(pr->rho_in != pr->rho_out)) return -1;
+    }
     P->g.nx = nx; P->g.ny = ny; P->g.nz = nz; P->g.walls = walls;
     P->N = (int64_t)nx * ny * nz;
     P->tau = tau;
@@ -353,19 +461,23 @@ static void step(const problem_t* P, const real* f, real* fout)
                 const real eps = P->eps[c];
                 real fi[MAXQ];
                 for (int i = 0; i < q; ++i) fi[i] = f[i * N + n];
+                real rho = 0;
+                for (int i = 0; i < q; ++i) rho += fi[i];
                 node_state s;
-                node_moments(L, fi, eps, P->kinv[c], P->feps[c], P->nu, P->G, &s);
+                node_moments(L, fi, eps, local_kinv(P, c, rho), P->feps[c], P->nu, P->G, &s);
                 for (int i = 0; i < q; ++i) {
                     real fs = fi[i] - (fi[i] - f_eq(L, i, s.rho, s.u, eps)) / P->tau +
                               f_force(L, i, s.rho, s.u, s.F, eps, P->tau);
                     int64_t t;
-                    if (stream_target(&P->g, L, P->cls, x, y, z, i, &t))
+                    const int m = stream_target(&P->g, L, P->cls, P->pr ? P->pr->axis : 0, x, y, z, i, &t);
+                    if (m == 1)
                         fout[i * N + t] = store_round(fs, L->w[i], P->store_mode, P->scale_log2, s.rho);
-                    else
+                    else if (m == 0)
                         fout[L->opp[i] * N + n] =
                             store_round(fs, L->w[L->opp[i]], P->store_mode, P->scale_log2, s.rho);
                 }
             }
+    fill_pressure_faces(P, fout);
 }
 
 /* Density and velocity (Eq. 32-34) at every node; wall nodes get zeros. */
@@ -383,8 +495,10 @@ static void fields(const problem_t* P, const real* f, double* rho, double* u)
         }
         real fi[MAXQ];
         for (int i = 0; i < L->q; ++i) fi[i] = f[i * N + n];
+        real r = 0;
+        for (int i = 0; i < L->q; ++i) r += fi[i];
         node_state s;
-        node_moments(L, fi, P->eps[c], P->kinv[c], P->feps[c], P->nu, P->G, &s);
+        node_moments(L, fi, P->eps[c], local_kinv(P, c, r), P->feps[c], P->nu, P->G, &s);
         rho[n] = (double)s.rho;
         u[n] = (double)s.u[0];
         u[N + n] = (double)s.u[1];
@@ -420,11 +534,11 @@ static double residual(const problem_t* P, const double* u, const double* up, in
 int64_t ref_solve(int q, int nx, int ny, int nz, unsigned walls, double tau, const double* G,
                   const uint8_t* cls, const double* eps_t, const double* kinv_t, const double* feps_t,
                   double* f, int64_t nsteps, int check_every, double tol, int store_mode, int scale_log2,
-                  double* rho, double* u, double* hist, int64_t hist_cap)
+                  double* rho, double* u, double* hist, int64_t hist_cap, const ref_pressure* pr)
 {
     problem_t P;
     if (make_problem(&P, q, nx, ny, nz, walls, tau, G, cls, eps_t, kinv_t, feps_t, store_mode,
-                     scale_log2))
+                     scale_log2, pr))
         return -1;
     const int64_t N = P.N, QN = (int64_t)q * N;
     real* a = (real*)malloc((size_t)QN * sizeof(real));
@@ -435,6 +549,7 @@ int64_t ref_solve(int q, int nx, int ny, int nz, unsigned walls, double tau, con
         return -2;
     }
     for (int64_t k = 0; k < QN; ++k) a[k] = f[k];
+    fill_pressure_faces(&P, a);
     fields(&P, a, rho, up);
     int64_t s = 0, nh = 0;
     while (s < nsteps) {
@@ -459,17 +574,18 @@ int64_t ref_solve(int q, int nx, int ny, int nz, unsigned walls, double tau, con
 /* One step from f to fout (both q * N doubles), for the tests. */
 int ref_step(int q, int nx, int ny, int nz, unsigned walls, double tau, const double* G,
              const uint8_t* cls, const double* eps_t, const double* kinv_t, const double* feps_t,
-             const double* f, double* fout, int store_mode, int scale_log2)
+             const double* f, double* fout, int store_mode, int scale_log2, const ref_pressure* pr)
 {
     problem_t P;
     if (make_problem(&P, q, nx, ny, nz, walls, tau, G, cls, eps_t, kinv_t, feps_t, store_mode,
-                     scale_log2))
+                     scale_log2, pr))
         return -1;
     const int64_t QN = (int64_t)q * P.N;
     real* a = (real*)malloc((size_t)QN * sizeof(real));
     real* b = (real*)malloc((size_t)QN * sizeof(real));
     if (!a || !b) { free(a); free(b); return -2; }
     for (int64_t k = 0; k < QN; ++k) a[k] = f[k];
+    fill_pressure_faces(&P, a);
     step(&P, a, b);
     for (int64_t k = 0; k < QN; ++k) fout[k] = (double)b[k];
     free(a); free(b);
@@ -477,16 +593,17 @@ int ref_step(int q, int nx, int ny, int nz, unsigned walls, double tau, const do
 }
 
 /* Density and velocity of the state f, for the tests. rho: N, u: 3N (planes). */
-int ref_fields(int q, int nx, int ny, int nz, double tau, const double* G, const uint8_t* cls,
+int ref_fields(int q, int nx, int ny, int nz, unsigned walls, double tau, const double* G, const uint8_t* cls,
                const double* eps_t, const double* kinv_t, const double* feps_t, const double* f,
-               double* rho, double* u)
+               double* rho, double* u, const ref_pressure* pr)
 {
     problem_t P;
-    if (make_problem(&P, q, nx, ny, nz, 0, tau, G, cls, eps_t, kinv_t, feps_t, 0, 0)) return -1;
+    if (make_problem(&P, q, nx, ny, nz, walls, tau, G, cls, eps_t, kinv_t, feps_t, 0, 0, pr)) return -1;
     const int64_t QN = (int64_t)q * P.N;
     real* a = (real*)malloc((size_t)QN * sizeof(real));
     if (!a) return -2;
     for (int64_t k = 0; k < QN; ++k) a[k] = f[k];
+    fill_pressure_faces(&P, a);
     fields(&P, a, rho, u);
     free(a);
     return 0;

@@ -100,3 +100,18 @@ def class_table(inst):
     eps[128:128 + N_BINS] = inst.eps_om
     k[128:128 + N_BINS] = k_om / inst.dx ** 2
     return eps, k, fe
+
+
+def pressure_coefficients(r, T, eps, tort, eta, q_sat=0.0, b=0.0, d_s=0.0, M=M_CH4):
+    """(A, B, C) of K_app(P) = A + B / P + C / (P (1 + b P)) in m^2 (P in Pa).
+
+    With the ideal-gas density rho_g = P M / (R T), the prefactor eta M / (rho_g R T)
+    of Eq. (18)-(19) is eta / P, so Eq. (18) is K_0 + eta D_K / P (A = K_0, B = eta D_K)
+    and the surface term of Eq. (19) is eta R T (1 - eps) q_sat b D_s / (P (1 + b P))
+    (C = eta R T (1 - eps) q_sat b D_s; zero for inorganic matter, q_sat = 0).
+    """
+    d_p = 2.0 * np.asarray(r, dtype=np.float64)
+    a = intrinsic_permeability(eps, tort, d_p)
+    bb = eta * knudsen_diffusivity(eps, tort, d_p, T, M)
+    c = eta * R_GAS * T * (1.0 - eps) * q_sat * b * d_s
+    return a, bb, c

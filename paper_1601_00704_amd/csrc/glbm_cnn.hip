@@ -604,15 +604,17 @@ __global__ void k_mse(const float* out, const float* target, const uint8_t* mask
     if (threadIdx.x == 0) part[blockIdx.x] = red[0];
 }
 
-// Adam on a flat FP32 parameter array
-__global__ void k_adam(float* p, const float* g, float* m1, float* m2, long long n, float lr, float b1, float b2,
-                       float c1, float c2, float eps)
+// Adam on a flat FP32 parameter array.  The decay rates and their complements
+// are rounded to float separately: 1 - 0.999f would carry a relative error of
+// 1.3e-5 into the second moment.
+__global__ void k_adam(float* p, const float* g, float* m1, float* m2, long long n, float lr, float b1, float omb1,
+                       float b2, float omb2, float c1, float c2, float eps)
 {
     const long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
     if (i >= n) return;
     const float gi = g[i];
-    const float a = b1 * m1[i] + (1.f - b1) * gi;
-    const float v = b2 * m2[i] + (1.f - b2) * gi * gi;
+    const float a = b1 * m1[i] + omb1 * gi;
+    const float v = b2 * m2[i] + omb2 * gi * gi;
     m1[i] = a;
     m2[i] = v;
     p[i] -= lr * (a / c1) / (sqrtf(v / c2) + eps);
@@ -1260,12 +1262,12 @@ int glbm_cnn_adam_step(glbm_cnn c, float lr)
     if (!c) return cfail(GLBM_EINVAL, "null argument");
     if (!(lr > 0.f) || !std::isfinite(lr)) return cfail(GLBM_EINVAL, "learning rate must be finite and > 0");
     c->step += 1;
-    const float b1 = 0.9f, b2 = 0.999f;
+    const double b1 = 0.9, b2 = 0.999;
     // bias corrections 1 - beta^t evaluated in double, then rounded once
-    const float c1 = (float)(1.0 - std::pow(0.9, (double)c->step));
-    const float c2 = (float)(1.0 - std::pow(0.999, (double)c->step));
-    hipLaunchKernelGGL(k_adam, dim3(nblocks(c->nparam)), dim3(256), 0, c->s, c->p, c->g, c->m1, c->m2, c->nparam, lr, b1,
-                       b2, c1, c2, 1e-8f);
+    const float c1 = (float)(1.0 - std::pow(b1, (double)c->step));
+    const float c2 = (float)(1.0 - std::pow(b2, (double)c->step));
+    hipLaunchKernelGGL(k_adam, dim3(nblocks(c->nparam)), dim3(256), 0, c->s, c->p, c->g, c->m1, c->m2, c->nparam, lr,
+                       (float)b1, (float)(1.0 - b1), (float)b2, (float)(1.0 - b2), c1, c2, 1e-8f);
     CHK(hipGetLastError());
     return pack_all(c);
 }

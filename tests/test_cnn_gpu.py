@@ -194,30 +194,32 @@ def test_network_forward_and_gradients(gpu):
     for ci, co, _ in C.SPEC:
         pq[o:o + co * ci * 9] = _bf(params[o:o + co * ci * 9])
         o += co * ci * 9 + co
-    lref, gref, oref = C.loss_and_grads(pq, x, target, mask, bf16=True)
+    lref, gref, oref, gscale, A = C.loss_and_grads(pq, x, target, mask, bf16=True, abs_scale=True)
+    oscale = C.output_abs_scale(pq, A)[..., :3]
     fe = np.linalg.norm(out - oref) / np.linalg.norm(oref)
     le = abs(loss - lref) / lref
     ge = np.linalg.norm(grads - gref) / np.linalg.norm(gref)
     print("network: forward rel L2 %.2e  loss rel %.2e  grad rel L2 %.2e" % (fe, le, ge))
     # BF16 bar: <= 2e-3 on the global relative L2 ...
     assert fe <= 2e-3 and le <= 2e-3 and ge <= 2e-3
-    # ... and <= 1e-2 per element, relative to the element's own magnitude floored at the
-    # RMS of its tensor (outputs per channel, gradients per layer's weights and biases):
-    # an element far below its tensor's scale is compared at that scale.
+    # ... and <= 1e-2 per element, relative to the scale of the sum that element is: the
+    # sum of the absolute values of its terms (outputs: sum |w a| + |b| of the last
+    # convolution; gradients: sum over pixels of |dy| |x|).  Rounding flips of bf16
+    # activations upstream perturb single terms, so their effect is bounded by that
+    # sum, not by the (possibly cancelling) value itself.
+    rel = np.abs(out - oref) / oscale
     for c in range(3):
-        o_, r_ = out[..., c], oref[..., c]
-        den = np.maximum(np.abs(r_), np.sqrt(np.mean(r_ * r_)))
-        worst = (np.abs(o_ - r_) / den).max()
-        print("  output channel %d: worst element rel %.2e" % (c, worst))
-        assert worst <= 1e-2
+        k = np.unravel_index(np.argmax(rel[..., c]), rel[..., c].shape)
+        print("  output channel %d: worst element rel %.2e at %s (value %.3e, scale %.3e); %d above 1e-3"
+              % (c, rel[..., c][k], k, oref[..., c][k], oscale[..., c][k], int((rel[..., c] > 1e-3).sum())))
+    assert rel.max() <= 1e-2
     o = 0
     for i, (ci, co, _) in enumerate(C.SPEC):
         for part, n in (("w", co * ci * 9), ("b", co)):
-            gg, rr = grads[o:o + n], gref[o:o + n]
-            den = np.maximum(np.abs(rr), np.sqrt(np.mean(rr * rr)))
-            worst = (np.abs(gg - rr) / den).max()
+            gg, rr, sc = grads[o:o + n], gref[o:o + n], gscale[o:o + n]
+            worst = (np.abs(gg - rr) / sc).max()
             l2 = np.linalg.norm(gg - rr) / np.linalg.norm(rr)
-            print("  layer %d %s grad: rel L2 %.2e, worst element rel %.2e" % (i, part, l2, worst))
+            print("  layer %d %s grad: rel L2 %.2e, worst element rel to its scale %.2e" % (i, part, l2, worst))
             assert worst <= 1e-2
             o += n
 
