@@ -43,11 +43,11 @@ enum { GLBM_D2Q9 = 9, GLBM_D3Q19 = 19 };
 /* Population storage.  Arithmetic is FP64 for F64 and FP32 otherwise; the
  * residual and flux reductions are always accumulated in FP64.
  *   F64     f_i - w_i stored as double                       (145 B per D2Q9 update)
- *   F32     f_i - w_i stored as float                        (73 B).  The fastest
- *           store within 1e-5 of FP64 on k, but its rounding scales with the
- *           density deviation, so on shale maps the residual levels off at
- *           about 2-3e-8 and a solve with tol = 1e-8 ends GLBM_ENOTCONVERGED;
- *           use F32LOC for solves to r <= 1e-8.
+ *   F32     f_i - w_i stored as float                        (73 B).  The node
+ *           collides in the local form (its own density part w_i (rho - 1)
+ *           split off and put back with fused multiply-adds), so each stored
+ *           value carries one rounding at the scale of the density deviation
+ *           and solves reach r <= 1e-8 on shale maps (k within 1e-5 of FP64).
  *   F16DEV  (f_i - w_i) 2^s stored as IEEE half, rounded to nearest even (37 B).
  *           The velocity part of f is then resolved only relative to the
  *           density deviation: on the 128^2 shale map k is off by several
@@ -93,6 +93,15 @@ typedef struct {
     int32_t dev_scale_log2;  /* s of the F16DEV scale 2^s in [0, 30], or GLBM_SCALE_AUTO */
     int32_t check_every;     /* n_c > 0, even: residual and flux are evaluated every n_c steps */
     uint32_t flags;          /* GLBM_FLAG_* bits; 0 for the defaults */
+    int32_t pressure_axis;   /* 0: no pressure faces; 1, 2, 3: pressure faces normal to x, y, z
+                                (the inlet / outlet pressures of the paper's Tab. 4 and Tab. 7).
+                                The face at coordinate 0 is held at density rho_in, the face at
+                                n - 1 at rho_out, by the Zou-He rule (the populations entering
+                                through a face are rebuilt from the known ones so that the node
+                                has the face density and no tangential momentum).  The other
+                                faces must be periodic; wall nodes are allowed.  Every instance
+                                of a context has pressure faces or none does. */
+    double rho_in, rho_out;  /* face densities (lattice units, > 0, different) */
 } glbm_instance_desc;
 
 /* Descriptor flags.  GLBM_FLAG_F16DEV_OPT_IN: accept GLBM_STORE_F16DEV, whose
@@ -140,11 +149,35 @@ int glbm_init_geometry(glbm_ctx* out, int32_t n_inst, const glbm_instance_desc* 
  * drag).  f_eps may be NULL (F_eps = 0: the paper drops the Forchheimer
  * term, Sec. 2.3).  The per-node constants of Eq. (36)-(37) are derived here.
  * Every class present in the map must be covered.
+ * On an instance with pressure faces K is constant (the pressure-independent
+ * case of glbm_set_pressure_perm) and F_eps must be 0.
  * Errors: GLBM_EINVAL (eps outside (0, 1], K <= 0 or NaN, F_eps < 0, a class
- * of the map without an entry).
+ * of the map without an entry, F_eps > 0 with pressure faces).
  */
 int glbm_set_local_perm(glbm_ctx ctx, int32_t inst, int32_t n_classes, const double* eps,
                         const double* k_lattice, const double* f_eps);
+
+/*
+ * Pressure-dependent local permeability of an instance with pressure faces:
+ * the apparent permeability of Eq. (18)-(19) evaluated at every node and step
+ * at the local pressure,
+ *     K(P) = k_const + k_knudsen / P + k_surface / (P (1 + langmuir_b P)),
+ * which is Eq. (18) (K_0 + eta D_K / P) plus the surface-diffusion term of
+ * Eq. (19) with the ideal-gas density (glbm_class_table_pressure computes the
+ * coefficients).  Arrays of n_classes entries (classes 0 .. n_classes-1), K in
+ * lattice units (K / dx^2), P in the unit of p_in / p_out (langmuir_b in its
+ * inverse); k_const = +INF marks an open pore (no drag; the other coefficients
+ * are ignored).  The local pressure is the affine image of the local lattice
+ * density, which carries the pressure of Eq. (26):
+ *     P(x) = p_out + (rho(x) - rho_out) (p_in - p_out) / (rho_in - rho_out).
+ * Errors: GLBM_EINVAL (no pressure faces, eps outside (0, 1], k_const <= 0,
+ * k_knudsen, k_surface or langmuir_b < 0 or not finite, p_in or p_out <= 0,
+ * a class of the map without an entry, a class whose K(P) is not positive and
+ * finite for every P between p_out and p_in).
+ */
+int glbm_set_pressure_perm(glbm_ctx ctx, int32_t inst, int32_t n_classes, const double* eps, const double* k_const,
+                           const double* k_knudsen, const double* k_surface, const double* langmuir_b, double p_in,
+                           double p_out);
 
 /*
  * Advance every active instance by up to n time steps of Eq. (29).  At every
@@ -167,8 +200,11 @@ int glbm_residual(glbm_ctx ctx, double* r, int64_t* steps);
 /*
  * Apparent permeability of each instance by Darcy's law on the current state:
  * k[3*i + d] = nu <u_d> / G_d, <.> the mean over fluid nodes of the
- * volume-averaged velocity of Eq. (34); NaN where G_d = 0.  Lattice units
- * (multiply by dx^2 for m^2).  Synchronises.
+ * volume-averaged velocity of Eq. (34); NaN where G_d = 0.  Along the axis of
+ * pressure faces: nu <u_a> (n_a - 1) / (c_s^2 (rho_in - rho_out)), Darcy's law
+ * with the lattice pressure c_s^2 rho over the node distance between the faces
+ * (in a uniform medium of porosity eps this is K / eps, because c_s^2 rho
+ * carries eps P).  Lattice units (multiply by dx^2 for m^2).  Synchronises.
  */
 int glbm_permeability(glbm_ctx ctx, double* k_lattice);
 
@@ -285,6 +321,20 @@ typedef struct {
  */
 int glbm_class_table(const glbm_gas_params* p, int32_t n_iom, const double* r_iom, int32_t n_om,
                      const double* r_om, double* eps_out, double* k_lattice_out);
+
+/*
+ * The same classes as coefficients of K_app(P) = k_const + k_knudsen / P +
+ * k_surface / (P (1 + b P)) (Eq. 18-19 with rho_g = P M / (R T); P in Pa), in
+ * lattice units (divided by dx^2), for glbm_set_pressure_perm:
+ *   k_const = K_0, k_knudsen = eta D_K, k_surface = eta R T (1 - eps) q_sat b D_s
+ * (organic classes only), b_out = b of Eq. (13).  p->pressure is used only when
+ * q_sat comes from Eq. (38) (it does not depend on it).  Open pores and unused
+ * classes: eps 1, k_const +INF, the rest 0.  Each output holds 256 entries.
+ * Errors: as glbm_class_table.
+ */
+int glbm_class_table_pressure(const glbm_gas_params* p, int32_t n_iom, const double* r_iom, int32_t n_om,
+                              const double* r_om, double* eps_out, double* k_const_out, double* k_knudsen_out,
+                              double* k_surface_out, double* b_out);
 
 #ifdef __cplusplus
 }

@@ -162,6 +162,56 @@ template <typename T> __device__ __forceinline__ T inst_cforce(const InstDev& I)
     if constexpr (sizeof(T) == 4) return I.cforcef; else return I.cforce;
 }
 
+// Zou-He rule on a pressure face (bc 3).  On entry d holds the deviations
+// f_i - w_i of the known populations (for a kRho store: local parts, with the
+// source densities in r) and zeros for the directions entering through the
+// face.  With n the unit normal into the domain (side * the axis) and the face
+// density rho_f: j_n = (rho_f - 1) - sum_{e.n = 0} d - 2 sum_{e.n < 0} d, and
+// for every entering direction d_i = d_opp(i) + 6 w_i j_n - sum_t e_i,t N_t,
+// N_t = sum_{e.n = 0} d e_t / 2 (tangential momentum zero; both lattices have
+// two entering directions with e_t = +-1 for each tangential axis t).  On exit
+// a kRho store holds deviations with source density 1 (r = 0).
+template <int Q, bool RHO, typename T>
+__device__ __forceinline__ void fill_face(T (&d)[Q], T (&r)[Q], const InstDev& I, int side)
+{
+    using L = Lat<Q>;
+    const int a = I.paxis;
+    if constexpr (RHO) {
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            d[i] += T(L::w(i)) * r[i];
+            r[i] = T(0);
+        }
+    }
+    T s0 = 0, sneg = 0, nt[3] = {0, 0, 0};
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const int e[3] = {L::ex(i), L::ey(i), L::ez(i)};
+        const int en = side * (a == 0 ? e[0] : (a == 1 ? e[1] : e[2]));
+        if (en == 0) {
+            s0 += d[i];
+#pragma unroll
+            for (int t = 0; t < L::D; ++t)
+                if (e[t]) nt[t] += (t == a) ? T(0) : (e[t] > 0 ? d[i] : -d[i]);
+        } else if (en < 0) {
+            sneg += d[i];
+        }
+    }
+    const T drf = side > 0 ? T(sizeof(T) == 4 ? I.drinf : I.drin) : T(sizeof(T) == 4 ? I.droutf : I.drout);
+    const T jn = drf - s0 - T(2) * sneg;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const int e[3] = {L::ex(i), L::ey(i), L::ez(i)};
+        const int en = side * (a == 0 ? e[0] : (a == 1 ? e[1] : e[2]));
+        if (en <= 0) continue;
+        T v = d[L::opp(i)] + T(6.0 * L::w(i)) * jn;
+#pragma unroll
+        for (int t = 0; t < L::D; ++t)
+            if (e[t] && t != a) v -= (e[t] > 0 ? T(0.5) : T(-0.5)) * nt[t];
+        d[i] = v;
+    }
+}
+
 // Pull the q post-collision values that stream into node (x, y, z).
 // For a kRho store, d[i] receives the stored part (f_i - w_i rho_s) and r[i]
 // the density deviation rho_s - 1 of the source node s; otherwise d[i] is the
@@ -182,9 +232,26 @@ __device__ __forceinline__ void gather(typename St<STORE>::T (&d)[Q], typename S
     const int xm = x == 0 ? nx - 1 : x - 1, xp = x == nx - 1 ? 0 : x + 1;
     const int ym = y == 0 ? ny - 1 : y - 1, yp = y == ny - 1 ? 0 : y + 1;
     const int zm = z == 0 ? nz - 1 : z - 1, zp = z == nz - 1 ? 0 : z + 1;
+    // pressure faces: side = +1 on the inlet face (coordinate 0), -1 on the
+    // outlet face (n - 1), 0 elsewhere; directions entering through the face
+    // (side * e_a > 0) are rebuilt below instead of pulled
+    int side = 0;
+    if constexpr (BC == 3) {
+        const int a = I.paxis;
+        const int ca = a == 0 ? x : (a == 1 ? y : z), na = a == 0 ? nx : (a == 1 ? ny : nz);
+        side = ca == 0 ? 1 : (ca == na - 1 ? -1 : 0);
+    }
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
         const int ex = L::ex(i), ey = L::ey(i), ez = L::ez(i);
+        if constexpr (BC == 3) {
+            const int ea = I.paxis == 0 ? ex : (I.paxis == 1 ? ey : ez);
+            if (side * ea > 0) {
+                d[i] = 0;
+                if constexpr (S::kRho) r[i] = 0;
+                continue;
+            }
+        }
         const int sx = ex > 0 ? xm : (ex < 0 ? xp : x);
         const int sy = ey > 0 ? ym : (ey < 0 ? yp : y);
         const int sz = ez > 0 ? zm : (ez < 0 ? zp : z);
@@ -223,6 +290,8 @@ __device__ __forceinline__ void gather(typename St<STORE>::T (&d)[Q], typename S
         d[i] = S::dec(raw, I.inv_scale);
         if constexpr (S::kRho) r[i] = *elem(rho_plane<STORE>(src, Q, stride), uint32_t(node));
     }
+    if constexpr (BC == 3)
+        if (side != 0) fill_face<Q, S::kRho>(d, r, I, side);
 }
 
 // Local form of a kRho node: drho = sum_i (w_i r_i + d_i), and d becomes
@@ -279,17 +348,19 @@ template <int Q, typename T> __device__ __forceinline__ T edot(int i, const T (&
 }
 
 // Moments and force of one node: Eq. (32)-(35) and (27)-(28) on deviations.
-template <int Q, typename T, bool FORCH> struct Node {
+// PRES (pressure faces): the class's K is K(P) at the node's pressure
+// P = p0 + (rho - 1) p1, with K(P) = A + (B + C / (1 + b P)) / P (Eq. 18-19).
+template <int Q, typename T, bool FORCH, bool PRES = false> struct Node {
     T drho, rho, u[3], F[3];
-    __device__ __forceinline__ void moments(const T (&d)[Q], const T* tab, const T g[3])
+    __device__ __forceinline__ void moments(const T (&d)[Q], const T* tab, const T g[3], const InstDev& I)
     {
         T dr = d[0];
 #pragma unroll
         for (int i = 1; i < Q; ++i) dr += d[i];
-        moments_with(d, dr, tab, g);
+        moments_with(d, dr, tab, g, I);
     }
     // d: deviations (or local parts e_i, whose momentum is the same), dr: rho - 1
-    __device__ __forceinline__ void moments_with(const T (&d)[Q], T dr, const T* tab, const T g[3])
+    __device__ __forceinline__ void moments_with(const T (&d)[Q], T dr, const T* tab, const T g[3], const InstDev& I)
     {
         using L = Lat<Q>;
         constexpr int D = L::D;
@@ -322,7 +393,18 @@ template <int Q, typename T, bool FORCH> struct Node {
         T v[3];
 #pragma unroll
         for (int a = 0; a < D; ++a) v[a] = j[a] * irho + T(0.5) * eps * g[a];
-        if (FORCH) {
+        if constexpr (PRES) {
+            const bool f32 = sizeof(T) == 4;
+            const T P = T(f32 ? I.p0f : I.p0) + dr * T(f32 ? I.p1f : I.p1);
+            const T K = tab[TAB_PA] + recip(P) * (tab[TAB_PB] + tab[TAB_PC] * recip(T(1) + tab[TAB_PBL] * P));
+            const T drag = eps * T(f32 ? I.nuf : I.nu) * tab[TAB_POPEN] * recip(K);   // eps nu / K
+            const T h = recip(T(1) + T(0.5) * drag);                                  // 1 / (2 c0), Eq. (36)
+#pragma unroll
+            for (int a = 0; a < D; ++a) {
+                u[a] = v[a] * h;
+                F[a] = eps * g[a] - drag * u[a];
+            }
+        } else if (FORCH) {
             const T c0 = tab[TAB_C0], c1 = tab[TAB_C1];
             const T vm = sqrt(dot<D>(v, v));
             const T den = T(1) / (c0 + sqrt(c0 * c0 + c1 * vm));
@@ -366,8 +448,8 @@ template <int Q, typename T> __device__ __forceinline__ T weight_defect()
 // cannot create or destroy mass; in the local form it also takes drho times
 // the defect 1 - sum w of the rounded weights, so that the values leaving the
 // node, w_i drho + e*_i, carry exactly its mass.
-template <int Q, typename T, bool FORCH, bool LOCAL>
-__device__ __forceinline__ void relax(T (&d)[Q], const Node<Q, T, FORCH>& s, const T* tab, T omega, T cforce)
+template <int Q, typename T, bool LOCAL, typename NodeT>
+__device__ __forceinline__ void relax(T (&d)[Q], const NodeT& s, const T* tab, T omega, T cforce)
 {
     using L = Lat<Q>;
     const T ieps = tab[TAB_INV_EPS];
@@ -407,10 +489,12 @@ __device__ __forceinline__ void relax(T (&d)[Q], const Node<Q, T, FORCH>& s, con
         d[0] = omw * d[0] + omega * eq0 + f0;
 }
 
-template <int Q, typename T, bool FORCH>
+// Columns of the class table a kernel reads (pressure faces and Forchheimer use all).
+template <int BC, bool FORCH> constexpr int tab_cols() { return (FORCH || BC == 3) ? kTabW : 4; }
+
+template <int Q, typename T, int NT>
 __device__ __forceinline__ void load_table(T* lds, const Args& a, int inst)
 {
-    constexpr int NT = FORCH ? kTabW : 4;
     const T* gt = static_cast<const T*>(a.tab) + (size_t)inst * kClasses * kTabW;
     for (int k = threadIdx.x; k < kClasses * NT; k += kBlock) lds[k] = gt[(k / NT) * kTabW + (k % NT)];
     __syncthreads();
@@ -452,21 +536,39 @@ __device__ __forceinline__ void sweep_slots(const Args& a, const Tile& t, const 
 #pragma unroll
     for (int u = 0; u < U; ++u) {
         if (!ok[u]) continue;
-        Node<Q, T, FORCH> s;
+        Node<Q, T, FORCH, BC == 3> s;
         const T* ct = tb + c[u] * tw;
         if constexpr (SS::kRho) {
             // local form; collision conserves mass, so the node writes its
             // density and the parts relative to it
             const T dr = localize<Q, T>(d[u], r[u]);
-            s.moments_with(d[u], dr, ct, g);
-            relax<Q, T, FORCH, true>(d[u], s, ct, omega, cforce);
+            s.moments_with(d[u], dr, ct, g, I);
+            relax<Q, T, true>(d[u], s, ct, omega, cforce);
             if constexpr (node_blocks(STORE))
                 rho_plane<STORE>(dst, Q, I.stride)[n[u]] = dr;
             else
                 *elem(rho_plane<STORE>(dst, Q, I.stride), uint32_t(n[u])) = dr;
+        } else if constexpr (STORE == GLBM_STORE_F32) {
+            // FP32 deviations d_i = f_i - w_i collide in the local form: the
+            // node's own density part w_i drho is split off with a fused
+            // multiply-add (the product is not rounded), the collision works
+            // on the small parts, and one more fused multiply-add puts the
+            // density back.  Each stored value then carries a single rounding
+            // at the scale of the density deviation instead of several, which
+            // is what keeps the residual falling below 1e-8 on shale maps.
+            using L = Lat<Q>;
+            T dr = d[u][0];
+#pragma unroll
+            for (int i = 1; i < Q; ++i) dr += d[u][i];
+#pragma unroll
+            for (int i = 0; i < Q; ++i) d[u][i] = __builtin_fmaf(-T(L::w(i)), dr, d[u][i]);
+            s.moments_with(d[u], dr, ct, g, I);
+            relax<Q, T, true>(d[u], s, ct, omega, cforce);
+#pragma unroll
+            for (int i = 0; i < Q; ++i) d[u][i] = __builtin_fmaf(T(L::w(i)), dr, d[u][i]);
         } else {
-            s.moments(d[u], ct, g);
-            relax<Q, T, FORCH, false>(d[u], s, ct, omega, cforce);
+            s.moments(d[u], ct, g, I);
+            relax<Q, T, false>(d[u], s, ct, omega, cforce);
         }
         if constexpr (node_blocks(STORE)) {
             if constexpr (NTS) {
@@ -517,7 +619,7 @@ __device__ __forceinline__ void sweep_tile(const Args& a, const Tile& t, const I
 template <int Q, int STORE, int BC, bool FORCH> __device__ __forceinline__ void sweep_block(const Args& a)
 {
     using T = typename St<STORE>::T;
-    constexpr int NT = FORCH ? kTabW : 4;
+    constexpr int NT = tab_cols<BC, FORCH>();
     __shared__ T tab[kClasses * NT];
 
     const int tid = (a.cache & 4) ? (int)blockIdx.x : xcd_tile(blockIdx.x, gridDim.x);
@@ -528,7 +630,7 @@ template <int Q, int STORE, int BC, bool FORCH> __device__ __forceinline__ void 
         const T* gt = static_cast<const T*>(a.tab) + (size_t)t.inst * kClasses * kTabW;
         sweep_tile<Q, STORE, BC, FORCH>(a, t, I, gt, kTabW);
     } else {
-        load_table<Q, T, FORCH>(tab, a, t.inst);
+        load_table<Q, T, NT>(tab, a, t.inst);
         sweep_tile<Q, STORE, BC, FORCH>(a, t, I, tab, NT);
     }
 }
@@ -616,12 +718,12 @@ __device__ __forceinline__ void observe_tile(const Args& a, const Tile& t, const
         if (BC >= 2 && c == kWallClass) continue;
         T d[Q], rr[Q];
         gather<Q, STORE, BC>(d, rr, src, cls, I, x, y, z, n);
-        Node<Q, T, FORCH> s;
+        Node<Q, T, FORCH, BC == 3> s;
         if constexpr (SS::kRho) {
             const T dr = localize<Q, T>(d, rr);
-            s.moments_with(d, dr, tb + c * tw, g);
+            s.moments_with(d, dr, tb + c * tw, g, I);
         } else {
-            s.moments(d, tb + c * tw, g);
+            s.moments(d, tb + c * tw, g, I);
         }
         if (mode & 2) {
 #pragma unroll
@@ -653,7 +755,7 @@ template <int Q, int STORE, int BC, bool FORCH>
 __global__ __launch_bounds__(kBlock) void k_observe(Args a, int mode, int all)
 {
     using T = typename St<STORE>::T;
-    constexpr int NT = FORCH ? kTabW : 4;
+    constexpr int NT = tab_cols<BC, FORCH>();
     __shared__ T tab[kClasses * NT];
     __shared__ double red[4 * 6];
 
@@ -665,7 +767,7 @@ __global__ __launch_bounds__(kBlock) void k_observe(Args a, int mode, int all)
         const T* gt = static_cast<const T*>(a.tab) + (size_t)t.inst * kClasses * kTabW;
         observe_tile<Q, STORE, BC, FORCH>(a, t, I, tid, mode, gt, kTabW, red);
     } else {
-        load_table<Q, T, FORCH>(tab, a, t.inst);
+        load_table<Q, T, NT>(tab, a, t.inst);
         observe_tile<Q, STORE, BC, FORCH>(a, t, I, tid, mode, tab, NT, red);
     }
 }
@@ -827,14 +929,14 @@ __global__ __launch_bounds__(kBlock) void k_get_fields(Args a, int inst, double*
         T ct[kTabW];
 #pragma unroll
         for (int k = 0; k < kTabW; ++k) ct[k] = tabg[c * kTabW + k];
-        Node<Q, T, FORCH> s;
+        Node<Q, T, FORCH, BC == 3> s;
         if constexpr (SS::kRho) {
             const T dr = localize<Q, T>(d, rr);
-            s.moments_with(d, dr, ct, g);
+            s.moments_with(d, dr, ct, g, I);
 #pragma unroll
             for (int i = 0; i < Q; ++i) d[i] += T(L::w(i)) * dr;  // back to f_i - w_i for the readback
         } else {
-            s.moments(d, ct, g);
+            s.moments(d, ct, g, I);
         }
         if (rho_out) rho_out[n] = 1.0 + double(s.drho);
         if (u_out)
@@ -880,7 +982,7 @@ hipError_t dispatch(const Config& c, A... args)
 #define GLBM_CASE(QQ, SS, BB, FF)                                                          \
     if (c.q == QQ && c.store == SS && c.bc == BB && c.forch == FF) return K<QQ, SS, BB, FF>::go(args...);
 #define GLBM_F(QQ, SS, BB) GLBM_CASE(QQ, SS, BB, false) GLBM_CASE(QQ, SS, BB, true)
-#define GLBM_B(QQ, SS) GLBM_F(QQ, SS, 0) GLBM_F(QQ, SS, 1) GLBM_F(QQ, SS, 2)
+#define GLBM_B(QQ, SS) GLBM_F(QQ, SS, 0) GLBM_F(QQ, SS, 1) GLBM_F(QQ, SS, 2) GLBM_CASE(QQ, SS, 3, false)
 #define GLBM_S(QQ)                                                                                 \
     GLBM_B(QQ, GLBM_STORE_F64) GLBM_B(QQ, GLBM_STORE_F32) GLBM_B(QQ, GLBM_STORE_F16DEV)              \
     GLBM_B(QQ, GLBM_STORE_F16LOC) GLBM_B(QQ, GLBM_STORE_F32LOC)
@@ -941,7 +1043,7 @@ hipError_t launch_set_fields(const Config& c, const Args& a, int inst, int ntile
                                                        static_cast<const double*>(u))                     \
                    : set_fields_go<QQ, SS, BB, float>(a, s, inst, ntiles, static_cast<const float*>(rho),   \
                                                       static_cast<const float*>(u));
-#define GLBM_SF_B(QQ, SS) GLBM_SF(QQ, SS, 0) GLBM_SF(QQ, SS, 1) GLBM_SF(QQ, SS, 2)
+#define GLBM_SF_B(QQ, SS) GLBM_SF(QQ, SS, 0) GLBM_SF(QQ, SS, 1) GLBM_SF(QQ, SS, 2) GLBM_SF(QQ, SS, 3)
 #define GLBM_SF_S(QQ)                                                                              \
     GLBM_SF_B(QQ, GLBM_STORE_F64) GLBM_SF_B(QQ, GLBM_STORE_F32) GLBM_SF_B(QQ, GLBM_STORE_F16DEV)     \
     GLBM_SF_B(QQ, GLBM_STORE_F16LOC) GLBM_SF_B(QQ, GLBM_STORE_F32LOC)

@@ -75,10 +75,12 @@ def test_shale128_convergence_stop_matches_oracle(gpu):
     assert abs(k - ref["k_lattice"][0]) / ref["k_lattice"][0] < 1e-11
 
 
-@pytest.mark.parametrize("store,tol,budget", [("f64", 1e-11, 60000), ("f32loc", 1e-5, 150000)])
+@pytest.mark.parametrize("store,tol,budget", [("f64", 1e-11, 60000), ("f32loc", 1e-5, 150000),
+                                              ("f32", 1e-5, 150000)])
 def test_shale128_converges_to_tol(gpu, store, tol, budget):
     """A solve with tol = 1e-8 reaches r <= 1e-8 (GLBM_OK) and k matches the oracle's
-    converged k.  F32LOC is the FP32-arithmetic store for solves to 1e-8."""
+    converged k, for both FP32-arithmetic stores (plain F32 collides in the local form,
+    so its rounding no longer scales with the density deviation)."""
     s, ref = _shale128_solver(gpu, store)
     try:
         rc = s.step(budget, tol=1e-8)
@@ -91,24 +93,6 @@ def test_shale128_converges_to_tol(gpu, store, tol, budget):
     assert rc == gpu.GLBM_OK
     assert r[0] <= 1e-8
     assert rel <= tol
-
-
-def test_shale128_f32_residual_floor(gpu):
-    """Plain F32 storage: its rounding scales with the density deviation, so the residual
-    levels off above 1e-8 on this map (glbm.h says so) and a solve with tol = 1e-8 ends
-    GLBM_ENOTCONVERGED; k at the budget is still within 1e-5 of the converged oracle k."""
-    s, ref = _shale128_solver(gpu, "f32")
-    try:
-        rc = s.step(120000, tol=1e-8)
-        r, st = s.residual()
-        k = s.permeability()[0, 0]
-    finally:
-        s.close()
-    rel = abs(k - ref["k_lattice"][0]) / ref["k_lattice"][0]
-    print("store f32: rc %d steps %d r %.3e k rel %.2e" % (rc, st[0], r[0], rel))
-    assert rc in (gpu.GLBM_OK, gpu.GLBM_ENOTCONVERGED)
-    assert r[0] < 1e-7
-    assert rel <= 1e-5
 
 
 def test_shale128_f16dev_error_is_recorded(gpu):
