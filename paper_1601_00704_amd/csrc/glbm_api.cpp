@@ -90,6 +90,20 @@ int validate(int32_t n_inst, const glbm_instance_desc* d)
                         i);
         if (x.lattice != d[0].lattice || x.store != d[0].store || x.check_every != d[0].check_every)
             return fail(GLBM_EINVAL, "instance %d: lattice, store and check_every must match instance 0", i);
+        if (x.pressure_axis < 0 || x.pressure_axis > (x.lattice == GLBM_D2Q9 ? 2 : 3))
+            return fail(GLBM_EINVAL, "instance %d: pressure_axis must be 0 (none) or 1 .. %d", i,
+                        x.lattice == GLBM_D2Q9 ? 2 : 3);
+        if ((x.pressure_axis != 0) != (d[0].pressure_axis != 0))
+            return fail(GLBM_EINVAL, "instance %d: every instance of a context has pressure faces or none does", i);
+        if (x.pressure_axis) {
+            const int32_t na = x.pressure_axis == 1 ? x.nx : (x.pressure_axis == 2 ? x.ny : x.nz);
+            if (na < 2) return fail(GLBM_EINVAL, "instance %d: the pressure axis needs at least 2 nodes", i);
+            if (x.wall_faces)
+                return fail(GLBM_EINVAL, "instance %d: pressure faces need periodic faces elsewhere (wall nodes are allowed)", i);
+            if (!(x.rho_in > 0.0) || !(x.rho_out > 0.0) || !std::isfinite(x.rho_in) || !std::isfinite(x.rho_out) ||
+                x.rho_in == x.rho_out)
+                return fail(GLBM_EINVAL, "instance %d: face densities must be finite, > 0 and different", i);
+        }
     }
     return GLBM_OK;
 }
@@ -419,6 +433,20 @@ void set_parities(glbm_ctx c)
     for (int i = 0; i < c->n_inst; ++i) c->inst_h[i].par = (int32_t)((c->steps[i] - c->gstep) & 1);
 }
 
+// Copy one instance's class table (kClasses x kTabW doubles) to the device in the compute type.
+int upload_table(glbm_ctx c, int inst, const std::vector<double>& row)
+{
+    char* dst = static_cast<char*>(c->tab_d) + (size_t)inst * kClasses * kTabW * c->tsz;
+    if (c->tsz == 8) {
+        HIPCHK(hipMemcpyAsync(dst, row.data(), row.size() * 8, hipMemcpyHostToDevice, c->work));
+    } else {
+        std::vector<float> rf(row.begin(), row.end());
+        HIPCHK(hipMemcpyAsync(dst, rf.data(), rf.size() * 4, hipMemcpyHostToDevice, c->work));
+    }
+    HIPCHK(hipStreamSynchronize(c->work));
+    return GLBM_OK;
+}
+
 int read_results(glbm_ctx c)
 {
     HIPCHK(hipMemcpyAsync(c->res_p, c->res_d, (size_t)c->n_inst * kPartW * sizeof(double), hipMemcpyDeviceToHost,
@@ -520,6 +548,16 @@ int glbm_init_geometry(glbm_ctx* out, int32_t n_inst, const glbm_instance_desc* 
         const int s = half ? (d.dev_scale_log2 == GLBM_SCALE_AUTO ? auto_scale(d) : d.dev_scale_log2) : 0;
         I.scale = std::ldexp(1.0f, s);
         I.inv_scale = std::ldexp(1.0f, -s);
+        I.paxis = d.pressure_axis ? d.pressure_axis - 1 : 0;
+        I.drin = d.pressure_axis ? d.rho_in - 1.0 : 0.0;
+        I.drout = d.pressure_axis ? d.rho_out - 1.0 : 0.0;
+        I.p0 = 1.0;   // pressure map: set by glbm_set_pressure_perm (unused by a constant K)
+        I.p1 = 0.0;
+        I.drinf = (float)I.drin;
+        I.droutf = (float)I.drout;
+        I.p0f = (float)I.p0;
+        I.p1f = (float)I.p1;
+        I.nuf = (float)I.nu;
         c->inst_h.push_back(I);
         c->cls_h[i].assign(cls_host[i], cls_host[i] + n);
         int64_t nf = 0;
@@ -533,7 +571,7 @@ int glbm_init_geometry(glbm_ctx* out, int32_t n_inst, const glbm_instance_desc* 
         cls_total += round_up(n, 256);
         snap_total += round_up(3 * n, 64);
     }
-    c->cfg.bc = any_wall_node ? 2 : (any_wall_face ? 1 : 0);
+    c->cfg.bc = desc[0].pressure_axis ? 3 : (any_wall_node ? 2 : (any_wall_face ? 1 : 0));
     c->steps.assign(n_inst, 0);
     c->snap_step.assign(n_inst, 0);
     c->active_h.assign(n_inst, 1);
@@ -610,6 +648,7 @@ int glbm_set_local_perm(glbm_ctx c, int32_t inst, int32_t n_classes, const doubl
     bool forch = false;
     for (int k = 0; k < n_classes && f_eps; ++k)
         if (f_eps[k] > 0.0 && std::isfinite(k_lattice[k])) forch = true;
+    if (forch && c->cfg.bc == 3) return fail(GLBM_EINVAL, "F_eps > 0 is not supported with pressure faces");
 
     int rc = enter(c);
     if (rc) return rc;
@@ -628,20 +667,22 @@ int glbm_set_local_perm(glbm_ctx c, int32_t inst, int32_t n_classes, const doubl
             double* r = &row[(size_t)k * kTabW];
             r[TAB_EPS] = e;
             r[TAB_INV_EPS] = 1.0 / e;
+            if (c->cfg.bc == 3) {
+                // pressure-driven format with a pressure-independent K: K(P) = A
+                const bool open = kinv == 0.0;
+                r[TAB_PA] = open ? 1.0 : k_lattice[k];
+                r[TAB_PB] = r[TAB_PC] = r[TAB_PBL] = 0.0;
+                r[TAB_POPEN] = open ? 0.0 : 1.0;
+                continue;
+            }
             r[TAB_INV_2C0] = 1.0 / (2.0 * c0);
             r[TAB_DRAG] = e * nu * kinv;
             r[TAB_C0] = c0;
             r[TAB_C1] = c1;
             r[TAB_FORCH] = e * fe * std::sqrt(kinv);
         }
-        char* dst = static_cast<char*>(c->tab_d) + (size_t)i * kClasses * kTabW * c->tsz;
-        if (c->tsz == 8) {
-            HIPCHK(hipMemcpyAsync(dst, row.data(), row.size() * 8, hipMemcpyHostToDevice, c->work));
-        } else {
-            std::vector<float> rf(row.begin(), row.end());
-            HIPCHK(hipMemcpyAsync(dst, rf.data(), rf.size() * 4, hipMemcpyHostToDevice, c->work));
-        }
-        HIPCHK(hipStreamSynchronize(c->work));
+        int rc2 = upload_table(c, i, row);
+        if (rc2) return rc2;
         c->has_table[i] = 1;
         for (int k = 0; k < n_classes; ++k) {
             c->eps_h[i][k] = eps[k];
@@ -652,6 +693,75 @@ int glbm_set_local_perm(glbm_ctx c, int32_t inst, int32_t n_classes, const doubl
         c->cfg.forch = true;
         free_graph(c);
     }
+    c->snap_valid = false;
+    free_graph(c);
+    return joined.done();
+}
+
+int glbm_set_pressure_perm(glbm_ctx c, int32_t inst, int32_t n_classes, const double* eps, const double* k_const,
+                           const double* k_kn, const double* k_surf, const double* lb, double p_in, double p_out)
+{
+    g_err.clear();
+    if (!c) return fail(GLBM_EINVAL, "null context");
+    if (c->cfg.bc != 3) return fail(GLBM_EINVAL, "the instances of this context have no pressure faces");
+    if (inst < -1 || inst >= c->n_inst) return fail(GLBM_EINVAL, "instance %d out of range", inst);
+    if (n_classes < 1 || n_classes > 255) return fail(GLBM_EINVAL, "n_classes must be in [1, 255]");
+    if (!eps || !k_const || !k_kn || !k_surf || !lb) return fail(GLBM_EINVAL, "every coefficient array is required");
+    if (!(p_in > 0.0) || !(p_out > 0.0) || !std::isfinite(p_in) || !std::isfinite(p_out))
+        return fail(GLBM_EINVAL, "p_in and p_out must be finite and > 0");
+    const double plo = std::min(p_in, p_out), phi = std::max(p_in, p_out);
+    for (int k = 0; k < n_classes; ++k) {
+        if (!(eps[k] > 0.0 && eps[k] <= 1.0)) return fail(GLBM_EINVAL, "class %d: eps %g outside (0, 1]", k, eps[k]);
+        if (!(k_const[k] > 0.0)) return fail(GLBM_EINVAL, "class %d: k_const %g must be > 0", k, k_const[k]);
+        if (std::isinf(k_const[k])) continue;
+        if (!(k_kn[k] >= 0.0) || !(k_surf[k] >= 0.0) || !(lb[k] >= 0.0) || !std::isfinite(k_kn[k]) ||
+            !std::isfinite(k_surf[k]) || !std::isfinite(lb[k]))
+            return fail(GLBM_EINVAL, "class %d: k_knudsen, k_surface and langmuir_b must be finite and >= 0", k);
+        for (double P : {plo, phi}) {
+            const double K = k_const[k] + (k_kn[k] + k_surf[k] / (1.0 + lb[k] * P)) / P;
+            if (!(K > 0.0) || !std::isfinite(K)) return fail(GLBM_EINVAL, "class %d: K(%g) = %g", k, P, K);
+        }
+    }
+    const int i0 = inst < 0 ? 0 : inst, i1 = inst < 0 ? c->n_inst : inst + 1;
+    for (int i = i0; i < i1; ++i)
+        for (uint8_t v : c->cls_h[i])
+            if (v != kWallClass && v >= n_classes)
+                return fail(GLBM_EINVAL, "instance %d: class %d of the map has no table entry", i, (int)v);
+    int rc = enter(c);
+    if (rc) return rc;
+    Joined joined(c);
+    std::vector<double> row((size_t)kClasses * kTabW, 0.0);
+    for (int i = i0; i < i1; ++i) {
+        std::fill(row.begin(), row.end(), 0.0);
+        for (int k = 0; k < kClasses; ++k) {
+            const bool have = k < n_classes;
+            const bool open = !have || std::isinf(k_const[k]);
+            double* r = &row[(size_t)k * kTabW];
+            r[TAB_EPS] = have ? eps[k] : 1.0;
+            r[TAB_INV_EPS] = 1.0 / r[TAB_EPS];
+            r[TAB_PA] = open ? 1.0 : k_const[k];
+            r[TAB_PB] = open ? 0.0 : k_kn[k];
+            r[TAB_PC] = open ? 0.0 : k_surf[k];
+            r[TAB_PBL] = open ? 0.0 : lb[k];
+            r[TAB_POPEN] = open ? 0.0 : 1.0;
+        }
+        rc = upload_table(c, i, row);
+        if (rc) return rc;
+        InstDev& I = c->inst_h[i];
+        const glbm_instance_desc& d = c->desc[i];
+        // P = p_out + (rho - rho_out) (p_in - p_out) / (rho_in - rho_out) = p0 + (rho - 1) p1
+        I.p1 = (p_in - p_out) / (d.rho_in - d.rho_out);
+        I.p0 = p_out - (d.rho_out - 1.0) * I.p1;
+        I.p0f = (float)I.p0;
+        I.p1f = (float)I.p1;
+        c->has_table[i] = 1;
+        for (int k = 0; k < n_classes; ++k) {
+            c->eps_h[i][k] = eps[k];
+            c->k_h[i][k] = k_const[k];
+        }
+    }
+    rc = upload_state(c);
+    if (rc) return rc;
     c->snap_valid = false;
     free_graph(c);
     return joined.done();
@@ -783,10 +893,16 @@ int glbm_permeability(glbm_ctx c, double* k)
     HIPCHK(hipStreamSynchronize(c->work));
     for (int i = 0; i < c->n_inst; ++i) {
         const double nu = c->inst_h[i].nu;
+        const glbm_instance_desc& D = c->desc[i];
         for (int d = 0; d < 3; ++d) {
             const double g = c->inst_h[i].g[d];
             const double mean = h[i * kPartW + P_UX + d] / (double)c->n_fluid[i];
             k[3 * i + d] = g != 0.0 ? nu * mean / g : NAN;
+            if (D.pressure_axis == d + 1) {
+                // Darcy's law with the lattice pressure c_s^2 rho across the n - 1 node spacings between the faces
+                const int32_t na = d == 0 ? D.nx : (d == 1 ? D.ny : D.nz);
+                k[3 * i + d] = nu * mean * (double)(na - 1) / ((D.rho_in - D.rho_out) / 3.0);
+            }
         }
     }
     return joined.done();

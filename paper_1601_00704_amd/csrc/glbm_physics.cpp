@@ -72,3 +72,48 @@ extern "C" int glbm_class_table(const glbm_gas_params* p, int32_t n_iom, const d
     }
     return GLBM_OK;
 }
+
+extern "C" int glbm_class_table_pressure(const glbm_gas_params* p, int32_t n_iom, const double* r_iom, int32_t n_om,
+                                         const double* r_om, double* eps_out, double* kc_out, double* kkn_out,
+                                         double* ksf_out, double* b_out)
+{
+    if (!p || !eps_out || !kc_out || !kkn_out || !ksf_out || !b_out) return GLBM_EINVAL;
+    if (n_iom < 0 || n_iom > 127 || n_om < 0 || n_om > 127) return GLBM_EINVAL;
+    if ((n_iom && !r_iom) || (n_om && !r_om)) return GLBM_EINVAL;
+    if (!positive(p->temperature) || !positive(p->viscosity) || !positive(p->molar_mass) ||
+        !positive(p->tortuosity) || !positive(p->dx))
+        return GLBM_EINVAL;
+    if (!(p->eps_iom > 0 && p->eps_iom <= 1) || !(p->eps_om > 0 && p->eps_om <= 1)) return GLBM_EINVAL;
+    if (!(p->langmuir_b >= 0) || !(p->d_s >= 0)) return GLBM_EINVAL;
+    double q_sat = p->q_sat;
+    if (!(q_sat > 0)) {
+        if (!positive(p->langmuir_vl) || !positive(p->toc) || p->eps_om >= 1.0) return GLBM_EINVAL;
+        q_sat = p->langmuir_vl * kRhoKerogen / ((1.0 - p->eps_om) * p->toc) * kRhoMethaneStd / p->molar_mass;
+    }
+    const double T = p->temperature, eta = p->viscosity;
+    const double vbar = std::sqrt(8.0 * kR * T / (kPi * p->molar_mass));
+    const double dx2 = p->dx * p->dx;
+    for (int k = 0; k < 256; ++k) {
+        eps_out[k] = 1.0;
+        kc_out[k] = INFINITY;
+        kkn_out[k] = ksf_out[k] = b_out[k] = 0.0;
+    }
+    auto fill = [&](int k, double eps, double r, bool organic) {
+        const double d = 2.0 * r;
+        const double kc = eps / p->tortuosity * d / 4.0;   // Eq. (4)
+        eps_out[k] = eps;
+        kc_out[k] = kc * d / 8.0 / dx2;                      // K_0
+        kkn_out[k] = eta * (4.0 / 3.0 * kc * vbar) / dx2;    // eta D_K, Eq. (3)
+        ksf_out[k] = organic ? eta * kR * T * (1.0 - eps) * q_sat * p->langmuir_b * p->d_s / dx2 : 0.0;
+        b_out[k] = organic ? p->langmuir_b : 0.0;
+    };
+    for (int k = 0; k < n_iom; ++k) {
+        if (!positive(r_iom[k])) return GLBM_EINVAL;
+        fill(1 + k, p->eps_iom, r_iom[k], false);
+    }
+    for (int k = 0; k < n_om; ++k) {
+        if (!positive(r_om[k])) return GLBM_EINVAL;
+        fill(128 + k, p->eps_om, r_om[k], true);
+    }
+    return GLBM_OK;
+}

@@ -46,7 +46,8 @@ EXPORTS = ("glbm_required_bytes", "glbm_init_geometry", "glbm_set_local_perm", "
            "glbm_conv3x3_backward_weight", "glbm_cnn_create", "glbm_cnn_destroy", "glbm_cnn_num_params",
            "glbm_cnn_get_params", "glbm_cnn_set_params", "glbm_cnn_get_grads", "glbm_cnn_forward",
            "glbm_cnn_backward", "glbm_cnn_train_step", "glbm_cnn_features", "glbm_cnn_targets",
-           "glbm_cnn_apply", "glbm_cnn_set_grads", "glbm_cnn_adam_step", "glbm_cnn_apply_noalloc")
+           "glbm_cnn_apply", "glbm_cnn_set_grads", "glbm_cnn_adam_step", "glbm_cnn_apply_noalloc",
+           "glbm_set_pressure_perm", "glbm_class_table_pressure")
 
 
 class GlbmError(RuntimeError):
@@ -60,7 +61,8 @@ class glbm_instance_desc(ctypes.Structure):
                 ("ny", ctypes.c_int32), ("nz", ctypes.c_int32), ("wall_faces", ctypes.c_uint32),
                 ("tau", ctypes.c_double), ("g", ctypes.c_double * 3),
                 ("dev_scale_log2", ctypes.c_int32), ("check_every", ctypes.c_int32),
-                ("flags", ctypes.c_uint32)]
+                ("flags", ctypes.c_uint32), ("pressure_axis", ctypes.c_int32),
+                ("rho_in", ctypes.c_double), ("rho_out", ctypes.c_double)]
 
 
 class glbm_gas_params(ctypes.Structure):
@@ -79,6 +81,8 @@ def _load():
         "glbm_required_bytes": (sz, [i32, vp]),
         "glbm_init_geometry": (i32, [vp, i32, vp, vp, vp, sz, vp]),
         "glbm_set_local_perm": (i32, [vp, i32, i32, vp, vp, vp]),
+        "glbm_set_pressure_perm": (i32, [vp, i32, i32, vp, vp, vp, vp, vp, f64, f64]),
+        "glbm_class_table_pressure": (i32, [vp, i32, vp, i32, vp, vp, vp, vp, vp, vp]),
         "glbm_step_n": (i32, [vp, i64, f64]),
         "glbm_residual": (i32, [vp, vp, vp]),
         "glbm_permeability": (i32, [vp, vp]),
@@ -143,8 +147,10 @@ def _ptr(a: np.ndarray):
 
 
 def make_desc(shape, lattice=GLBM_D2Q9, store=GLBM_STORE_F32, tau=1.0, g=(1e-6, 0.0, 0.0),
-              wall_faces=0, dev_scale_log2=GLBM_SCALE_AUTO, check_every=100, flags=0) -> glbm_instance_desc:
-    """Descriptor of one instance; shape is (ny, nx) or (nz, ny, nx)."""
+              wall_faces=0, dev_scale_log2=GLBM_SCALE_AUTO, check_every=100, flags=0, pressure_axis=None,
+              rho_in=1.0, rho_out=1.0) -> glbm_instance_desc:
+    """Descriptor of one instance; shape is (ny, nx) or (nz, ny, nx).  pressure_axis (0 = x,
+    1 = y, 2 = z) puts pressure faces of densities rho_in / rho_out on that axis."""
     if len(shape) == 2:
         nz, ny, nx = 1, shape[0], shape[1]
     else:
@@ -155,6 +161,8 @@ def make_desc(shape, lattice=GLBM_D2Q9, store=GLBM_STORE_F32, tau=1.0, g=(1e-6, 
     for a in range(3):
         d.g[a] = float(g[a])
     d.dev_scale_log2, d.check_every, d.flags = dev_scale_log2, check_every, flags
+    d.pressure_axis = 0 if pressure_axis is None else int(pressure_axis) + 1
+    d.rho_in, d.rho_out = float(rho_in), float(rho_out)
     return d
 
 
@@ -183,6 +191,13 @@ def glbm_set_local_perm(ctx, inst: int, eps, k_lattice, f_eps=None):
     k = np.ascontiguousarray(k_lattice, dtype=np.float64)
     fe = None if f_eps is None else np.ascontiguousarray(f_eps, dtype=np.float64)
     _check(_lib.glbm_set_local_perm(ctx, inst, len(eps), _ptr(eps), _ptr(k), None if fe is None else _ptr(fe)))
+
+
+def glbm_set_pressure_perm(ctx, inst: int, eps, k_const, k_knudsen, k_surface, langmuir_b, p_in, p_out):
+    arrs = [np.ascontiguousarray(a, dtype=np.float64) for a in (eps, k_const, k_knudsen, k_surface, langmuir_b)]
+    n = len(arrs[0])
+    assert all(len(a) == n for a in arrs)
+    _check(_lib.glbm_set_pressure_perm(ctx, inst, n, *[_ptr(a) for a in arrs], float(p_in), float(p_out)))
 
 
 def glbm_step_n(ctx, n: int, tol: float = 0.0) -> int:
@@ -284,6 +299,18 @@ def glbm_class_table(params: glbm_gas_params, r_iom, r_om):
     if rc != GLBM_OK:
         raise GlbmError(rc, "glbm_class_table: invalid parameters")
     return eps, k
+
+
+def glbm_class_table_pressure(params: glbm_gas_params, r_iom, r_om):
+    """(eps, k_const, k_knudsen, k_surface, b), 256 entries each (lattice units, P in Pa)."""
+    r_iom = np.ascontiguousarray(r_iom, dtype=np.float64)
+    r_om = np.ascontiguousarray(r_om, dtype=np.float64)
+    out = [np.zeros(256) for _ in range(5)]
+    rc = _lib.glbm_class_table_pressure(ctypes.byref(params), len(r_iom), _ptr(r_iom), len(r_om), _ptr(r_om),
+                                        *[_ptr(a) for a in out])
+    if rc != GLBM_OK:
+        raise GlbmError(rc, "glbm_class_table_pressure: invalid parameters")
+    return tuple(out)
 
 
 def gas_params(inst, molar_mass=0.016043) -> glbm_gas_params:
@@ -435,6 +462,9 @@ class Solver:
 
     def set_local_perm(self, eps, k_lattice, f_eps=None, inst=-1):
         glbm_set_local_perm(self.ctx, inst, eps, k_lattice, f_eps)
+
+    def set_pressure_perm(self, eps, k_const, k_knudsen, k_surface, langmuir_b, p_in, p_out, inst=-1):
+        glbm_set_pressure_perm(self.ctx, inst, eps, k_const, k_knudsen, k_surface, langmuir_b, p_in, p_out)
 
     def step(self, n, tol=0.0):
         return glbm_step_n(self.ctx, n, tol)

@@ -25,19 +25,20 @@ pytestmark = pytest.mark.gpu
 TOL = {"f64": 1e-11, "f32": 3e-5, "f16dev": 4e-3, "f16loc": 4e-3, "f32loc": 3e-5}
 
 
-def _compare(g, q, cls, eps, k, fe, store, steps, G, walls=0, tau=1.0, tile=None, cache=None, scale=20):
-    print("case q=%d shape=%s store=%s steps=%d walls=%d tile=%s cache=%s" % (q, cls.shape, store, steps, walls,
-                                                                             tile, cache), flush=True)
+def _compare(g, q, cls, eps, k, fe, store, steps, G, walls=0, tau=1.0, tile=None, cache=None, scale=20,
+             pressure=None):
+    print("case q=%d shape=%s store=%s steps=%d walls=%d tile=%s cache=%s pressure=%s" % (
+        q, cls.shape, store, steps, walls, tile, cache, None if pressure is None else pressure.axis), flush=True)
     if store == "f16loc" and scale == 20:
         scale = 24
     emul = {"f64": (0, 0), "f32": (0, 0), "f16dev": (2, scale), "f16loc": (3, scale), "f32loc": (4, 0)}[store]
     prob = oracle_problem(q, cls, eps, k, fe, tau=tau, G=G, walls=walls, store_mode=emul[0],
-                          scale_log2=emul[1])
+                          scale_log2=emul[1], pressure=pressure)
     f = prob.rest()
     prob.run(f, steps)
     rho_o, u_o = prob.fields(f)
     s = gpu_solver(g, q, cls, eps, k, fe, tau=tau, G=G, walls=walls, store=store, tile=tile, cache=cache,
-                   scale_log2=scale if store in ("f16dev", "f16loc") else None)
+                   scale_log2=scale if store in ("f16dev", "f16loc") else None, pressure=pressure)
     try:
         s.step(steps)
         fg = s.populations()

@@ -147,3 +147,31 @@ def test_langmuir_capacity_range_over_the_batch_draws():
     (litres, MPa, or mass instead of volume) moves it by three orders of magnitude."""
     q = [kapp.qsat_from_langmuir_volume(vl, 0.3, toc) for vl in (0.002, 0.008) for toc in (0.05, 0.30)]
     assert 500 < min(q) < 1000 and 8000 < max(q) < 20000
+
+
+def test_native_pressure_coefficients_match_oracle():
+    """glbm_class_table_pressure (native) against the oracle's K(P) coefficients of
+    Eq. (18)-(19), class by class, and K(P) at the instance pressure equals the constant
+    class table of the same classes."""
+    import paper_1601_00704_amd.glbm as g
+    import shale_inputs as si
+    inst = si.batch_instance(7)
+    prm = g.gas_params(inst)
+    r_iom, r_om = inst.radii()
+    eps, kc, kk, ks, b = g.glbm_class_table_pressure(prm, r_iom, r_om)
+    eps0, k0 = g.glbm_class_table(prm, r_iom, r_om)
+    q_sat = kapp.qsat_from_langmuir_volume(inst.langmuir_vl, inst.eps_om, inst.toc)
+    dx2 = inst.dx ** 2
+    for lo, radii, ep, qs in ((1, r_iom, inst.eps_iom, 0.0), (128, r_om, inst.eps_om, q_sat)):
+        A, B, C = kapp.pressure_coefficients(radii, inst.temperature, ep, inst.tortuosity, inst.viscosity, qs,
+                                             1.0 / inst.langmuir_pl, inst.d_s)
+        sl = slice(lo, lo + len(radii))
+        assert np.allclose(kc[sl], A / dx2, rtol=1e-14, atol=0)
+        assert np.allclose(kk[sl], B / dx2, rtol=1e-14, atol=0)
+        assert np.allclose(ks[sl], C / dx2, rtol=1e-13, atol=0)
+        assert np.all(eps[sl] == ep)
+    P = inst.pressure
+    kp = kc + (kk + ks / (1 + b * P)) / P
+    m = np.isfinite(k0)
+    assert np.allclose(kp[m], k0[m], rtol=1e-13, atol=0)
+    assert np.all(np.isinf(kc[~m]))
