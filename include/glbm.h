@@ -336,6 +336,49 @@ int glbm_class_table_pressure(const glbm_gas_params* p, int32_t n_iom, const dou
                               const double* r_om, double* eps_out, double* k_const_out, double* k_knudsen_out,
                               double* k_surface_out, double* b_out);
 
+/* ---------------------------------------------- pore-size distributions -- */
+
+#define GLBM_GMM_MAX_COMPONENTS 8
+
+/*
+ * Batched EM fit of one-dimensional Gaussian mixtures to pore-size samples
+ * (Sec. 2.2, Eq. 20-24): the E-step responsibilities of Eq. (20) with the
+ * Gaussian of Eq. (21) (input length 1, exponent negative), and the M-step
+ * updates of Eq. (22)-(24), the variance taken about the updated mean.
+ *   n_sets      independent sample sets
+ *   offsets     host, n_sets + 1 entries: set s holds x_dev[offsets[s] ..
+ *               offsets[s + 1]) (increasing, non-empty)
+ *   x_dev       device array of the samples (double; e.g. pore radii or their
+ *               logarithms)
+ *   k           components, 1 .. GLBM_GMM_MAX_COMPONENTS
+ *   phi, mu, var  host arrays of n_sets * k (set-major): in, the starting
+ *               point (fractions > 0 summing to 1, variances > 0); out, the fit
+ *   iters       maximum iterations
+ *   tol         0: run exactly `iters` iterations; > 0: a set stops after the
+ *               first iteration (from the second on) whose log-likelihood gain
+ *               is <= tol times the log-likelihood
+ *   loglik      host, n_sets (may be NULL): log-likelihood of the returned
+ *               parameters, sum_i log sum_j Phi_j g_j(x_i)
+ *   iters_done  host, n_sets (may be NULL): iterations each set ran
+ * FP64 throughout; the sums are reduced in a fixed order, so results are
+ * deterministic and do not depend on the other sets of the batch.  A
+ * component whose responsibilities all vanish keeps its parameters.  Work is
+ * queued on hip_stream (NULL: null stream) and the call synchronises it.
+ * Errors: GLBM_EINVAL (bad sizes or starting point), GLBM_ENOMEM, GLBM_EDEVICE.
+ */
+int glbm_gmm_fit(int32_t n_sets, const int64_t* offsets, const double* x_dev, int32_t k, double* phi, double* mu,
+                 double* var, int32_t iters, double tol, double* loglik, int32_t* iters_done, void* hip_stream);
+
+/*
+ * Radius classes of one pore-size mode fitted in the logarithm of the radius
+ * (a Gaussian of mean mu_ln and standard deviation sigma_ln in ln r): n
+ * equal-probability bins, r_k = exp(mu_ln + sigma_ln z_k) with z_k the standard
+ * normal quantile of (k + 1/2) / n, for the r_iom / r_om arguments of
+ * glbm_class_table.  Errors: GLBM_EINVAL (n outside [1, 127], sigma_ln <= 0 or
+ * a non-finite input).
+ */
+int glbm_radius_bins(double mu_ln, double sigma_ln, int32_t n, double* r_out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -15,6 +15,7 @@
 // 273.15 K and 101.325 kPa, the reference state of a volume in m^3/kg).
 #include "glbm.h"
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <string>
@@ -115,5 +116,27 @@ extern "C" int glbm_class_table_pressure(const glbm_gas_params* p, int32_t n_iom
         if (!positive(r_om[k])) return GLBM_EINVAL;
         fill(128 + k, p->eps_om, r_om[k], true);
     }
+    return GLBM_OK;
+}
+
+namespace {
+// Standard normal quantile: the z with Phi(z) = p, Phi(z) = erfc(-z / sqrt 2) / 2,
+// by bisection to the resolution of a double (Phi is monotone).
+double normal_quantile(double p)
+{
+    double lo = -40.0, hi = 40.0;
+    for (int it = 0; it < 200 && hi - lo > 1e-15 * std::max(1.0, std::fabs(lo)); ++it) {
+        const double mid = 0.5 * (lo + hi);
+        if (0.5 * std::erfc(-mid / std::sqrt(2.0)) < p) lo = mid;
+        else hi = mid;
+    }
+    return 0.5 * (lo + hi);
+}
+}  // namespace
+
+extern "C" int glbm_radius_bins(double mu_ln, double sigma_ln, int32_t n, double* r_out)
+{
+    if (!r_out || n < 1 || n > 127 || !std::isfinite(mu_ln) || !positive(sigma_ln)) return GLBM_EINVAL;
+    for (int k = 0; k < n; ++k) r_out[k] = std::exp(mu_ln + sigma_ln * normal_quantile((k + 0.5) / n));
     return GLBM_OK;
 }

@@ -47,7 +47,7 @@ EXPORTS = ("glbm_required_bytes", "glbm_init_geometry", "glbm_set_local_perm", "
            "glbm_cnn_get_params", "glbm_cnn_set_params", "glbm_cnn_get_grads", "glbm_cnn_forward",
            "glbm_cnn_backward", "glbm_cnn_train_step", "glbm_cnn_features", "glbm_cnn_targets",
            "glbm_cnn_apply", "glbm_cnn_set_grads", "glbm_cnn_adam_step", "glbm_cnn_apply_noalloc",
-           "glbm_set_pressure_perm", "glbm_class_table_pressure")
+           "glbm_set_pressure_perm", "glbm_class_table_pressure", "glbm_gmm_fit", "glbm_radius_bins")
 
 
 class GlbmError(RuntimeError):
@@ -82,6 +82,8 @@ def _load():
         "glbm_init_geometry": (i32, [vp, i32, vp, vp, vp, sz, vp]),
         "glbm_set_local_perm": (i32, [vp, i32, i32, vp, vp, vp]),
         "glbm_set_pressure_perm": (i32, [vp, i32, i32, vp, vp, vp, vp, vp, f64, f64]),
+        "glbm_gmm_fit": (i32, [i32, vp, vp, i32, vp, vp, vp, i32, f64, vp, vp, vp]),
+        "glbm_radius_bins": (i32, [f64, f64, i32, vp]),
         "glbm_class_table_pressure": (i32, [vp, i32, vp, i32, vp, vp, vp, vp, vp, vp]),
         "glbm_step_n": (i32, [vp, i64, f64]),
         "glbm_residual": (i32, [vp, vp, vp]),
@@ -311,6 +313,26 @@ def glbm_class_table_pressure(params: glbm_gas_params, r_iom, r_om):
     if rc != GLBM_OK:
         raise GlbmError(rc, "glbm_class_table_pressure: invalid parameters")
     return tuple(out)
+
+
+def glbm_gmm_fit(offsets, x_dev, phi, mu, var, iters, tol=0.0, stream=None):
+    """Batched EM fit (Eq. 20-24).  offsets: n_sets + 1 sample offsets into the device array
+    x_dev (a pointer to doubles); phi, mu, var: (n_sets, k) starting points.  Returns
+    (phi, mu, var, loglik, iters_done)."""
+    offsets = np.ascontiguousarray(offsets, dtype=np.int64)
+    phi, mu, var = (np.array(a, dtype=np.float64, order="C", copy=True) for a in (phi, mu, var))
+    n_sets, k = phi.shape
+    ll = np.zeros(n_sets)
+    it = np.zeros(n_sets, dtype=np.int32)
+    _check(_lib.glbm_gmm_fit(n_sets, _ptr(offsets), x_dev, k, _ptr(phi), _ptr(mu), _ptr(var), int(iters), float(tol),
+                             _ptr(ll), _ptr(it), _stream() if stream is None else stream))
+    return phi, mu, var, ll, it
+
+
+def glbm_radius_bins(mu_ln, sigma_ln, n=127):
+    r = np.zeros(n)
+    _check(_lib.glbm_radius_bins(float(mu_ln), float(sigma_ln), int(n), _ptr(r)))
+    return r
 
 
 def gas_params(inst, molar_mass=0.016043) -> glbm_gas_params:

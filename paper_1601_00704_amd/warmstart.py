@@ -245,6 +245,14 @@ def main(argv=None):
                                        args.eval_store or args.store, args.trace_every)
     if args.params_out:
         np.save(args.params_out, g.glbm_cnn_get_params(cnn))
+        manifest = {"command": "python -m paper_1601_00704_amd.warmstart " + " ".join(argv if argv is not None
+                                                                                    else sys.argv[1:]),
+                    "train_seeds": [train_seeds[0], train_seeds[-1]], "test_seeds": [test_seeds[0], test_seeds[-1]],
+                    "side": args.side, "epochs": args.epochs, "batch": args.batch, "lr": args.lr,
+                    "store": args.store, "tol": args.tol, "final_loss": hist[-1] if hist else None,
+                    "params": int(g.glbm_cnn_num_params(cnn)), "layout": "glbm_cnn_get_params (float32)"}
+        with open(os.path.splitext(args.params_out)[0] + ".json", "w") as fh:
+            json.dump(manifest, fh, indent=1)
     g.glbm_cnn_destroy(cnn)
     cs = np.array([r["cold_steps"] for r in res], float)
     ws = np.array([r["warm_steps"] for r in res], float)

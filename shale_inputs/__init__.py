@@ -288,3 +288,30 @@ def random_table(n_classes: int, seed: int, k_range=(1e-3, 1e-1), eps_range=(0.1
         k[0] = math.inf
         fe[0] = 0.0
     return eps, k, fe
+
+
+# ------------------------------------------------------------- pore-size samples
+# The paper's validation set of the EM fit (Sec. 2.2, Tab. 3): two Gaussian
+# clusters as (mean, standard deviation, fraction).
+TAB3_CLUSTERS = ((10.0, 1.0, 0.25), (20.0, 4.0, 0.75))
+
+
+def mixture_samples(seed: int, m: int, clusters=TAB3_CLUSTERS) -> np.ndarray:
+    """m draws from a one-dimensional Gaussian mixture given as (mean, sd, fraction)
+    triples: component counts from one multinomial draw, then normal draws, shuffled."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    frac = np.array([c[2] for c in clusters], dtype=np.float64)
+    counts = rng.multinomial(m, frac / frac.sum())
+    x = np.concatenate([rng.normal(c[0], c[1], n) for c, n in zip(clusters, counts)])
+    rng.shuffle(x)
+    return x
+
+
+def pore_radius_samples(seed: int, m: int, r_iom_median: float = 20e-9, r_om_median: float = 5e-9,
+                        sigma_ln_r: float = 0.5, om_fraction: float = 0.3) -> np.ndarray:
+    """A synthetic measured pore-size distribution of a shale matrix: m pore radii (m),
+    a lognormal mode per phase (inorganic and organic matter) mixed in the given
+    fraction; the paper's Eagle Ford data are not available."""
+    clusters = ((math.log(r_om_median), sigma_ln_r, om_fraction),
+                (math.log(r_iom_median), sigma_ln_r, 1.0 - om_fraction))
+    return np.exp(mixture_samples(seed, m, clusters))

@@ -1,0 +1,99 @@
+"""Batched EM fit of pore-size mixtures on the GPU (glbm_gmm_fit) against the oracle's
+EM (Sec. 2.2, Eq. 20-24), and the pipeline that feeds the class table from a
+measured pore-size distribution."""
+import math
+
+import numpy as np
+import pytest
+
+import shale_inputs as si
+from oracle import gmm
+
+pytestmark = pytest.mark.gpu
+
+
+def _fit_gpu(g, sets, starts, iters, tol=0.0):
+    import torch
+    offs = np.concatenate([[0], np.cumsum([len(x) for x in sets])]).astype(np.int64)
+    xd = torch.from_numpy(np.concatenate(sets)).cuda()
+    phi, mu, var = (np.array([s[i] for s in starts]) for i in range(3))
+    out = g.glbm_gmm_fit(offs, xd.data_ptr(), phi, mu, var, iters, tol)
+    torch.cuda.synchronize()
+    return out
+
+
+def test_gmm_batch_matches_oracle(gpu):
+    """Uneven batch of sets (Tab. 3 mixture, lognormal pore radii in ln r, three
+    components, a single Gaussian; sizes from 3 to 300k samples, chunk tails), fixed
+    iteration counts: parameters within 1e-11 relative of the oracle, log-likelihood
+    within 1e-11 (FP64 with a different summation order)."""
+    g = gpu
+    sets, starts, ks = [], [], []
+    sets.append(si.mixture_samples(11, 300000))
+    starts.append(([0.5, 0.5], [8.0, 25.0], [4.0, 25.0]))
+    sets.append(np.log(si.pore_radius_samples(12, 50001)))
+    starts.append(([0.5, 0.5], [math.log(3e-9), math.log(30e-9)], [0.5, 0.5]))
+    sets.append(si.mixture_samples(13, 4097, ((0.0, 1.0, 0.2), (5.0, 1.5, 0.5), (12.0, 0.7, 0.3))))
+    starts.append(([0.3, 0.3, 0.4], [1.0, 4.0, 10.0], [2.0, 2.0, 2.0]))
+    sets.append(si.mixture_samples(14, 3, ((2.0, 1.0, 1.0),)))
+    starts.append(([1.0], [0.0], [1.0]))
+    for k in (1, 2, 3):
+        idx = [i for i, s in enumerate(starts) if len(s[0]) == k]
+        if not idx:
+            continue
+        print("case k=%d sets %s" % (k, [len(sets[i]) for i in idx]), flush=True)
+        iters = 40
+        phi, mu, var, ll, it = _fit_gpu(g, [sets[i] for i in idx], [starts[i] for i in idx], iters)
+        for r, i in enumerate(idx):
+            p0, m0, v0, hist = gmm.fit(sets[i], *starts[i], iters)
+            assert it[r] == iters
+            assert np.allclose(phi[r], p0, rtol=1e-11, atol=1e-14)
+            assert np.allclose(mu[r], m0, rtol=1e-11, atol=1e-14)
+            assert np.allclose(var[r], v0, rtol=1e-10, atol=1e-14)
+            assert abs(ll[r] - hist[-1]) <= 1e-11 * abs(hist[-1]) + 1e-12
+            print("  set %d (%d samples): mu %s, loglik %.12e vs %.12e" % (i, len(sets[i]), mu[r], ll[r], hist[-1]))
+
+
+def test_gmm_tolerance_stop_and_batch_independence(gpu):
+    """With tol > 0 each set stops on its own; a set's result does not depend on what
+    else is in the batch (bitwise)."""
+    g = gpu
+    a = si.mixture_samples(21, 20000)
+    b = si.mixture_samples(22, 70000)
+    st = ([0.5, 0.5], [8.0, 25.0], [4.0, 25.0])
+    pa, ma, va, la, ia = _fit_gpu(g, [a], [st], 2000, tol=1e-12)
+    pb, mb, vb, lb, ib = _fit_gpu(g, [b, a], [st, st], 2000, tol=1e-12)
+    assert 2 <= ia[0] < 2000
+    assert np.array_equal(pa[0], pb[1]) and np.array_equal(ma[0], mb[1]) and np.array_equal(va[0], vb[1])
+    assert ia[0] == ib[1] and la[0] == lb[1]
+    # the stopped fit agrees with the oracle run for the same number of iterations
+    p0, m0, v0, _ = gmm.fit(a, *st, int(ia[0]))
+    assert np.allclose(ma[0], m0, rtol=1e-11)
+
+
+def test_class_table_from_measured_pore_sizes(gpu):
+    """A synthetic measured PSD of both phases (lognormal modes, medians 5 / 20 nm,
+    sigma 0.5 in ln r) is fitted in ln r with two components; the smaller mode is the
+    organic matter.  Its radius bins and class table reproduce those of the true modes
+    to the sampling error (medians within 3 %, K within 8 %)."""
+    import torch
+    g = gpu
+    r = si.pore_radius_samples(31, 200000)
+    lr = np.log(r)
+    phi, mu, var, ll, it = _fit_gpu(g, [lr], [([0.5, 0.5], [math.log(3e-9), math.log(30e-9)], [0.5, 0.5])], 500,
+                                    tol=1e-13)
+    o = np.argsort(mu[0])
+    om, iom = o[0], o[1]
+    r_om = g.glbm_radius_bins(mu[0][om], math.sqrt(var[0][om]))
+    r_iom = g.glbm_radius_bins(mu[0][iom], math.sqrt(var[0][iom]))
+    inst = si.shale128()
+    prm = g.gas_params(inst)
+    eps_fit, k_fit = g.glbm_class_table(prm, r_iom, r_om)
+    eps_true, k_true = g.glbm_class_table(prm, *inst.radii())
+    assert abs(math.exp(mu[0][om]) / 5e-9 - 1) < 0.03 and abs(math.exp(mu[0][iom]) / 20e-9 - 1) < 0.03
+    m = np.isfinite(k_true)
+    rel = np.abs(k_fit[m] / k_true[m] - 1)
+    print("fitted medians %.3e / %.3e, sigma %.3f / %.3f, max K rel diff %.3f" % (
+        math.exp(mu[0][om]), math.exp(mu[0][iom]), math.sqrt(var[0][om]), math.sqrt(var[0][iom]), rel.max()))
+    assert rel.max() < 0.08
+    assert np.array_equal(eps_fit, eps_true)

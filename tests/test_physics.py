@@ -175,3 +175,16 @@ def test_native_pressure_coefficients_match_oracle():
     m = np.isfinite(k0)
     assert np.allclose(kp[m], k0[m], rtol=1e-13, atol=0)
     assert np.all(np.isinf(kc[~m]))
+
+
+def test_native_radius_bins_match_scipy_quantiles():
+    """glbm_radius_bins (bisection on erfc) equals the equal-probability lognormal bins
+    built from SciPy's normal quantile (the input generator's radius_bins)."""
+    import paper_1601_00704_amd.glbm as g
+    import shale_inputs as si
+    for med, sig in ((20e-9, 0.5), (5e-9, 0.25), (1e-7, 1.0)):
+        got = g.glbm_radius_bins(np.log(med), sig)
+        want = si.radius_bins(med, sig)
+        assert np.allclose(got, want, rtol=1e-13, atol=0)
+    with pytest.raises(g.GlbmError):
+        g.glbm_radius_bins(0.0, 0.0)
