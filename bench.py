@@ -23,6 +23,7 @@ from __future__ import annotations
 import argparse
 import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -87,22 +88,38 @@ def calibrate_copy(nbytes=1 << 30, reps=5):
 
 
 def copy_bandwidth(nbytes=1 << 30, reps=10):
-    """HBM bandwidth of a plain device-to-device copy on this GPU (GB/s, read + write)."""
+    """HBM bandwidth (GB/s, read + write) of the library's streaming copy (16-byte
+    nontemporal loads and stores) and of torch's copy_, on the current stream."""
     import torch
+    import paper_1601_00704_amd.glbm as g
     a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
     b = torch.empty_like(a)
-    b.copy_(a)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    e0.record()
-    for _ in range(reps):
-        b.copy_(a)
-    e1.record()
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / reps
+    out = {}
+    for name, fn in (("stream_copy", lambda: g.glbm_stream_copy(a.data_ptr(), b.data_ptr(), nbytes)),
+                     ("torch_copy", lambda: b.copy_(a))):
+        fn()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        out[name] = round(2.0 * nbytes / (e0.elapsed_time(e1) / reps * 1e-3) / 1e9, 1)
     del a, b
     torch.cuda.empty_cache()
-    return 2.0 * nbytes / (ms * 1e-3) / 1e9
+    return out
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def _pmc_per_kernel(path):
@@ -156,16 +173,77 @@ def sweep_kernel(q, store):
     return ("k_sweep9<%s>" if store in ("f64", "f32", "f32loc") else "k_sweep<9,%s>") % store
 
 
-def cpu_baseline(cls_crop, table, steps):
+def cpu_baseline(cls_crop, table, steps, threads=None):
+    """Oracle MLUPS on a crop (all host threads, or `threads`)."""
     import oracle
     eps, k, fe = table
-    prob = oracle.Problem(q=9, cls=cls_crop, eps=eps, k=k, f_eps=fe, tau=1.0, G=(1e-6, 0, 0))
-    f = prob.rest()
-    prob.run(f, 2)
+    all_threads = oracle.num_threads()
+    if threads:
+        oracle.set_threads(threads)
+    try:
+        prob = oracle.Problem(q=9, cls=cls_crop, eps=eps, k=k, f_eps=fe, tau=1.0, G=(1e-6, 0, 0))
+        f = prob.rest()
+        prob.run(f, 2)
+        t0 = time.perf_counter()
+        prob.run(f, steps)
+        dt = time.perf_counter() - t0
+        used = oracle.num_threads()
+    finally:
+        if threads:
+            oracle.set_threads(all_threads)
+    return cls_crop.size * steps / dt / 1e6, dt, used
+
+
+def time_to_converge(store="f32", n=8, side=512, tol=1e-8, max_steps=2000000):
+    """Time to converged k_app, plain (from rest) vs learned warm start, on held-out
+    512^2 warm-start problems (seeds 200000 + k): both solves run all problems in one
+    batched context to r <= tol; the warm time includes the network's inference and the
+    equilibrium write of its prediction.  Network weights: paper_1601_00704_amd/weights."""
+    import torch
+    import shale_inputs as si
+    import paper_1601_00704_amd.glbm as g
+    from paper_1601_00704_amd import warmstart as ws
+    wpath = os.path.join(ROOT, "paper_1601_00704_amd", "weights", "warmstart_cnn.npy")
+    params = np.load(wpath, allow_pickle=False)
+    with open(os.path.splitext(wpath)[0] + ".json") as fh:
+        manifest = json.load(fh)
+    insts = [si.warmstart_instance(200000 + k, side) for k in range(n)]
+    maps = si.batch_classes(insts, processes=8)
+    s_rho, s_u = ws._scales(insts[0].g)
+    cold = ws.Batch(insts, maps, store)
+    wc, rcc, rcold, stc = cold.solve(tol, max_steps)
+    kc = cold.s.permeability()[:, 0]
+    cold.close()
+    print("time to converge: cold %.2fs, max steps %d" % (wc, int(stc.max())), file=sys.stderr, flush=True)
+    cnn = g.glbm_cnn_create(1, side, side, seed=0)
+    g.glbm_cnn_set_params(cnn, params)
+    xb = torch.empty((1, side, side, 8), dtype=torch.int16, device="cuda")
+    yb = torch.empty((1, side, side, 4), dtype=torch.float32, device="cuda")
+    warm = ws.Batch(insts, maps, store)
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
-    prob.run(f, steps)
-    dt = time.perf_counter() - t0
-    return cls_crop.size * steps / dt / 1e6, dt, oracle.num_threads()
+    for j, inst in enumerate(insts):
+        g.glbm_cnn_features(warm.s.ctx, j, math.log10(inst.pressure / 1e6), xb.data_ptr())
+        g.glbm_cnn_forward(cnn, xb.data_ptr(), yb.data_ptr(), 1)
+        g.glbm_cnn_apply(warm.s.ctx, j, yb.data_ptr(), s_rho, s_u)
+    torch.cuda.synchronize()
+    ti = time.perf_counter() - t0
+    ww, rcw, rwarm, stw = warm.solve(tol, max_steps)
+    kw = warm.s.permeability()[:, 0]
+    warm.close()
+    g.glbm_cnn_destroy(cnn)
+    print("time to converge: warm %.2fs + inference %.3fs, max steps %d" % (ww, ti, int(stw.max())),
+          file=sys.stderr, flush=True)
+    kd = np.abs(kw - kc) / np.abs(kc)
+    return {"problems": n, "side": side, "tol": tol, "store": store,
+            "cold": {"wall_s": round(wc, 3), "converged": int(rcc) == g.GLBM_OK, "steps": [int(v) for v in stc],
+                     "steps_median": float(np.median(stc))},
+            "warm": {"wall_s": round(ww + ti, 3), "inference_s": round(ti, 4), "converged": int(rcw) == g.GLBM_OK,
+                     "steps": [int(v) for v in stw], "steps_median": float(np.median(stw))},
+            "speedup_wall": round(wc / (ww + ti), 4), "steps_ratio_median": round(float(np.median(stc / stw)), 4),
+            "k_rel_diff_max": float(kd.max()),
+            "network": {"weights": "paper_1601_00704_amd/weights/warmstart_cnn.npy", "trained_by": manifest["command"],
+                        "train_side": manifest["side"], "final_loss": manifest["final_loss"]}}
 
 
 def _json_line(metric_unit_value, steps, warmup, ms_per_step, dtype, config, roofline, extra=None):
@@ -339,6 +417,108 @@ def run_d3q19(args):
                       DTYPE[args.store], cfg, roof)
 
 
+def run_pressure(args):
+    """The 4096^2 map driven by pressure faces along x (10.5 -> 9.5 MPa around the map's
+    10 MPa) with K_app of Eq. 18-19 evaluated at every node's local pressure."""
+    import torch
+    import shale_inputs as si
+    import paper_1601_00704_amd.glbm as g
+    inst = si.shale4096(args.side)
+    cls = inst.classes()
+    torch.cuda.set_device(0)
+    store = g.STORE_NAMES[args.store]
+    prm = g.gas_params(inst)
+    eps, kc, kk, ks, b = g.glbm_class_table_pressure(prm, *inst.radii())
+    d = g.make_desc(cls.shape, store=store, tau=inst.tau, g=(0, 0, 0), check_every=N_C, flags=opt_in(store),
+                    pressure_axis=0, rho_in=1.0 + 5e-5, rho_out=1.0 - 5e-5)
+    s = g.Solver([d], [cls])
+    s.set_pressure_perm(eps[:255], kc[:255], kk[:255], ks[:255], b[:255], inst.pressure + 0.5e6,
+                        inst.pressure - 0.5e6)
+    N = cls.size
+    tile = _choose_tile(s, g, args)
+    wall = _timed_chunks(s, g, args.steps, args.warmup, graph=False)
+    ms, n = g.glbm_sweep_time(s.ctx)
+    per_launch = ms / max(n, 1)
+    r, st = s.residual()
+    kx = s.permeability()[0, 0]
+    s.close()
+    bpl = g.bytes_per_update(9, store)
+    achieved = bpl * N / (per_launch * 1e-3) / 1e9
+    cfg = {"workload": "D2Q9 GLBM %dx%d QSGS map (TOC 0.10), pressure faces on x 10.5 -> 9.5 MPa, K_app(P) at every "
+                       "node, %s populations" % (args.side, args.side, args.store.upper()),
+           "nodes": N, "sweeps_per_step": N_C, "steps_total": int(st[0]), "residual": float(r[0]),
+           "k_p_lattice": float(kx), "tile": tile}
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+            "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None,
+            "kernel": "%s, pressure faces + K(P)" % sweep_kernel(9, args.store), "bytes_per_lu": bpl,
+            "mean_launch_ms": round(per_launch, 5), "launches": n}
+    return _json_line(N * N_C * args.steps / wall / 1e6, args.steps, args.warmup, wall / args.steps * 1e3,
+                      DTYPE[args.store], cfg, roof)
+
+
+def run_gmm(args):
+    """Batched EM fit of pore-size mixtures (Sec. 2.2): 64 sets of 2^20 log-radius samples,
+    two components, a fixed number of iterations; throughput in samples x iterations / s."""
+    import torch
+    import shale_inputs as si
+    import paper_1601_00704_amd.glbm as g
+    torch.cuda.set_device(0)
+    n_sets, m, iters = 64, 1 << 20, args.gmm_iters
+    xs = np.concatenate([np.log(si.pore_radius_samples(9000 + k, m)) for k in range(n_sets)])
+    xd = torch.from_numpy(xs).cuda()
+    offs = np.arange(n_sets + 1, dtype=np.int64) * m
+    st = (np.full((n_sets, 2), 0.5), np.tile([math.log(3e-9), math.log(30e-9)], (n_sets, 1)),
+          np.full((n_sets, 2), 0.5))
+    g.glbm_gmm_fit(offs, xd.data_ptr(), *st, 2)   # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    phi, mu, var, ll, it = g.glbm_gmm_fit(offs, xd.data_ptr(), *st, iters)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    passes = iters + 1
+    bytes_ = 8.0 * n_sets * m * passes
+    achieved = bytes_ / wall / 1e9
+    cfg = {"workload": "batched EM fit, %d sets x %d samples (ln r of a two-phase lognormal PSD), k = 2, %d "
+                       "iterations, FP64" % (n_sets, m, iters),
+           "sets": n_sets, "samples_per_set": m, "iterations": iters,
+           "median_fitted_medians_nm": [float(np.median(np.exp(np.sort(mu, axis=1)[:, j])) * 1e9) for j in (0, 1)]}
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+            "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None,
+            "kernel": "k_gmm_pass<2> + k_gmm_update (8 B per sample and pass, wall time of the whole fit)"}
+    return {"metric": "EM pore-size fit throughput", "value": round(n_sets * m * passes / wall / 1e9, 3),
+            "unit": "Gsample-iterations/s", "n_gpus": 1, "steps": iters, "warmup": 1,
+            "ms_per_step": round(wall / passes * 1e3, 3), "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f64", "data": "synthetic (seeded lognormal pore radii)", "config": cfg,
+            "roofline": roof}
+
+
+def run_studies(args):
+    """The paper's layout (Sec. 3.2) and TOC (Sec. 3.3) studies at its 16 x 8 um domain
+    (256 x 128 nodes), pressure-driven 0.2 -> 0.1 MPa, every sample of a study in one
+    batched context, solved to r <= 1e-8."""
+    import torch
+    import shale_inputs as si
+    from paper_1601_00704_amd import studies
+    torch.cuda.set_device(0)
+    out = {}
+    total_lu, total_wall = 0.0, 0.0
+    for name, cases in (("layout", si.layout_study(realizations=2)), ("toc", si.toc_study())):
+        res, run = studies.solve_study(cases, store=args.store, tol=1e-8, max_steps=args.max_steps)
+        total_lu += run["lattice_updates"]
+        total_wall += run["wall_s"]
+        out[name] = {"run": run, "samples": [{k: v for k, v in r.items() if k not in ("name",)} for r in res]}
+        print("study %s: %.1fs, max steps %d, rc %d" % (name, run["wall_s"], run["max_steps"], run["rc"]),
+              file=sys.stderr, flush=True)
+    cfg = {"workload": "paper studies (layout cases 1-4 x 2 realizations; TOC 0.2-0.8 x D_s 1e-9..1e-5), "
+                       "256 x 128 nodes each, pressure faces 0.2 -> 0.1 MPa, K_app(P) per node, %s" % args.store.upper(),
+           "studies": out}
+    return {"metric": "GLBM study throughput (solved to r <= 1e-8)", "value": round(total_lu / total_wall / 1e6, 1),
+            "unit": "MLUPS", "n_gpus": 1, "steps": 1, "warmup": 0, "ms_per_step": round(total_wall * 1e3, 1),
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": DTYPE[args.store],
+            "data": "synthetic (seeded layout and QSGS maps, Tab. 6 / Tab. 7 inputs)", "config": cfg,
+            "roofline": None}
+
+
 # (cin, cout, level) of the ten convolutions of the warm-start network; level l runs at H/2^l
 CNN_LAYERS = [(8, 32, 0), (32, 32, 0), (32, 64, 1), (64, 64, 1), (64, 128, 2), (128, 128, 2),
               (192, 64, 1), (64, 64, 1), (96, 32, 0), (32, 3, 0)]
@@ -421,8 +601,10 @@ def main():
     ap.add_argument("--store", default="f32", choices=("f32", "f16dev", "f16loc", "f32loc", "f64"))
     ap.add_argument("--cpu-steps", type=int, default=4000, help="oracle steps of the CPU baseline (about 10 s)")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--workload", default="shale4096", choices=("shale4096", "batch", "d3q19", "cnn"),
-                    help="shale4096: the benchmark line; batch / d3q19 / cnn: supplementary workloads")
+    ap.add_argument("--workload", default="shale4096",
+                    choices=("shale4096", "batch", "d3q19", "cnn", "pressure", "gmm", "studies"),
+                    help="shale4096: the benchmark line; the others: supplementary workloads")
+    ap.add_argument("--gmm-iters", type=int, default=50)
     ap.add_argument("--cnn-batch", type=int, default=8)
     ap.add_argument("--cnn-side", type=int, default=512)
     ap.add_argument("--batch", type=int, default=256)
@@ -435,6 +617,9 @@ def main():
     ap.add_argument("--converge-tol", type=float, default=0.0,
                     help="d3q19: after the timed steps, solve from rest to this residual and report it")
     ap.add_argument("--max-steps", type=int, default=400000)
+    ap.add_argument("--no-converge", action="store_true",
+                    help="skip the time-to-converge leg (plain vs warm start) of the benchmark line")
+    ap.add_argument("--converge-problems", type=int, default=8)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run only a plain 1 GiB elementwise copy (counter calibration)")
     ap.add_argument("--pmc-summary", nargs=4, metavar=("FETCH", "WRITE", "COPY_FETCH", "COPY_WRITE"),
@@ -455,6 +640,10 @@ def main():
     if args.workload == "cnn":
         print(json.dumps(run_cnn(args)), flush=True)
         return
+    for name, fn in (("pressure", run_pressure), ("gmm", run_gmm), ("studies", run_studies)):
+        if args.workload == name:
+            print(json.dumps(fn(args)), flush=True)
+            return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the GLBM hot path here is built and timed on a single "
               "MI355X; sharding over several GPUs is not implemented.", file=sys.stderr)
@@ -529,8 +718,11 @@ def main():
                      "traffic": traffic,
                      "kernel": sweep_kernel(9, args.store), "bytes_per_lu": bytes_per_lu,
                      "mean_launch_ms": round(per_launch, 5), "launches": launches,
-                     "measured_copy_gbs": round(copy_bandwidth(), 1)},
+                     "measured_copy_gbs": copy_bandwidth()},
     }
+    if not args.no_converge:
+        out["time_to_converge"] = time_to_converge(args.store if args.store in ("f32", "f32loc", "f64") else "f32",
+                                                   n=args.converge_problems)
     if not args.no_cpu:
         y0, x0 = 0, 0
         crop = np.ascontiguousarray(cls[y0:y0 + 512, x0:x0 + 512])
@@ -538,9 +730,14 @@ def main():
         from oracle import kapp
         e_o, k_o, f_o = kapp.class_table(inst)
         v, dt, cores = cpu_baseline(crop, (e_o, k_o, f_o), args.cpu_steps)
+        v1, dt1, _ = cpu_baseline(crop, (e_o, k_o, f_o), max(args.cpu_steps // 16, 20), threads=1)
         out["cpu_baseline"] = {"value": round(v, 2), "unit": "MLUPS", "cores": cores, "kind": "oracle",
                                "sample": "%d steps of a 512x512 crop of the same map (FP64 oracle, %.1f s)"
-                                         % (args.cpu_steps, dt)}
+                                         % (args.cpu_steps, dt),
+                               "single_thread_value": round(v1, 2), "single_thread_sample":
+                                   "%d steps of the same crop on 1 thread (%.1f s)" % (max(args.cpu_steps // 16, 20),
+                                                                                      dt1),
+                               "cpu_model": cpu_model(), "host_threads": os.cpu_count()}
     print(json.dumps(out), flush=True)
 
 

@@ -285,6 +285,15 @@ int glbm_autotune(glbm_ctx ctx, int32_t steps, int32_t* chosen);
  */
 int glbm_velocity_set(int32_t lattice, int32_t* e, double* w);
 
+/*
+ * Copy `bytes` of device memory with nontemporal 16-byte loads and stores (the
+ * memory pattern of a sweep without its gathers and arithmetic): a measured
+ * streaming ceiling of the GPU, for reporting a kernel's bandwidth against.
+ * Queued on hip_stream; does not synchronise.  Errors: GLBM_EINVAL (null
+ * pointers, or pointers or size not multiples of 16 bytes); GLBM_EDEVICE.
+ */
+int glbm_stream_copy(const void* src, void* dst, size_t bytes, void* hip_stream);
+
 /* Release every resource of the context (the caller's population buffer is not freed). */
 int glbm_destroy(glbm_ctx ctx);
 

@@ -85,6 +85,14 @@ def num_threads() -> int:
     return int(L.ref_num_threads())
 
 
+def set_threads(n: int) -> None:
+    """OpenMP threads of the oracle's later parallel regions (both builds)."""
+    for kind in _LIBS:
+        L = lib(kind)
+        L.ref_set_threads.restype = ctypes.c_int
+        assert L.ref_set_threads(int(n)) == 0
+
+
 def round_half(x):
     """The oracle's nearest-float16 rounding (ties to even) of every element, as float64."""
     x = np.ascontiguousarray(x, dtype=np.float64)

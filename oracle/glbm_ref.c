@@ -637,3 +637,11 @@ int ref_init_fields(int q, int nx, int ny, int nz, const uint8_t* cls, const dou
 
 /* OpenMP threads a parallel region of the oracle uses. */
 int ref_num_threads(void) { return omp_get_max_threads(); }
+
+/* Set the OpenMP thread count of later parallel regions (for timing at one thread). */
+int ref_set_threads(int n)
+{
+    if (n < 1) return -1;
+    omp_set_num_threads(n);
+    return 0;
+}

@@ -1332,6 +1332,16 @@ int glbm_cnn_apply_noalloc(glbm_ctx c, int32_t inst, const float* y, double rho_
     return joined.done();
 }
 
+int glbm_stream_copy(const void* src, void* dst, size_t bytes, void* hip_stream)
+{
+    g_err.clear();
+    if (!src || !dst) return fail(GLBM_EINVAL, "null pointer");
+    if ((bytes & 15) || (reinterpret_cast<uintptr_t>(src) & 15) || (reinterpret_cast<uintptr_t>(dst) & 15))
+        return fail(GLBM_EINVAL, "pointers and size must be multiples of 16 bytes");
+    HIPCHK(launch_stream_copy(src, dst, bytes, static_cast<hipStream_t>(hip_stream)));
+    return GLBM_OK;
+}
+
 int glbm_velocity_set(int32_t lattice, int32_t* e, double* w)
 {
     g_err.clear();

@@ -120,6 +120,7 @@ hipError_t launch_observe(const Config& c, const Args& a, int mode, hipStream_t 
 hipError_t launch_finalize(const Args& a, int n_inst, double tol, int with_r, int count_check,
                            hipStream_t s);
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
+hipError_t launch_stream_copy(const void* src, void* dst, size_t bytes, hipStream_t s);
 // Write the equilibrium of (rho, u) of instance `inst` (device arrays): src_is_double = 1 reads
 // rho as double, 0 reads rho - 1 as float; u is 3 planes of N of the same type
 hipError_t launch_set_fields(const Config& c, const Args& a, int inst, int ntiles, const void* rho,

@@ -826,6 +826,16 @@ __global__ __launch_bounds__(kFinBlock) void k_finalize(Args a, double tol, int 
     }
 }
 
+// Streaming copy, 16 bytes per lane per iteration with nontemporal loads and
+// stores: the memory pattern of a sweep without its gathers or arithmetic, as a
+// practical bandwidth ceiling for this GPU.
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+__global__ __launch_bounds__(256) void k_stream_copy(const u32x4* __restrict__ src, u32x4* __restrict__ dst, size_t n)
+{
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        __builtin_nontemporal_store(__builtin_nontemporal_load(src + i), dst + i);
+}
+
 __global__ void k_zero(uint32_t* p, size_t n)
 {
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
@@ -1020,6 +1030,16 @@ hipError_t launch_finalize(const Args& a, int n_inst, double tol, int with_r, in
 {
     const int all = with_r ? 0 : 1;
     hipLaunchKernelGGL(k_finalize, dim3(n_inst), dim3(kFinBlock), 0, s, a, tol, with_r, count_check, all);
+    return hipGetLastError();
+}
+
+hipError_t launch_stream_copy(const void* src, void* dst, size_t bytes, hipStream_t s)
+{
+    const size_t n = bytes / 16;
+    if (n == 0) return hipSuccess;
+    const size_t blocks = std::min<size_t>((n + 255) / 256, 8192);
+    hipLaunchKernelGGL(k_stream_copy, dim3((unsigned)blocks), dim3(256), 0, s, static_cast<const u32x4*>(src),
+                       static_cast<u32x4*>(dst), n);
     return hipGetLastError();
 }
 

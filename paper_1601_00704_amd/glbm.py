@@ -47,7 +47,8 @@ EXPORTS = ("glbm_required_bytes", "glbm_init_geometry", "glbm_set_local_perm", "
            "glbm_cnn_get_params", "glbm_cnn_set_params", "glbm_cnn_get_grads", "glbm_cnn_forward",
            "glbm_cnn_backward", "glbm_cnn_train_step", "glbm_cnn_features", "glbm_cnn_targets",
            "glbm_cnn_apply", "glbm_cnn_set_grads", "glbm_cnn_adam_step", "glbm_cnn_apply_noalloc",
-           "glbm_set_pressure_perm", "glbm_class_table_pressure", "glbm_gmm_fit", "glbm_radius_bins")
+           "glbm_set_pressure_perm", "glbm_class_table_pressure", "glbm_gmm_fit", "glbm_radius_bins",
+           "glbm_stream_copy")
 
 
 class GlbmError(RuntimeError):
@@ -84,6 +85,7 @@ def _load():
         "glbm_set_pressure_perm": (i32, [vp, i32, i32, vp, vp, vp, vp, vp, f64, f64]),
         "glbm_gmm_fit": (i32, [i32, vp, vp, i32, vp, vp, vp, i32, f64, vp, vp, vp]),
         "glbm_radius_bins": (i32, [f64, f64, i32, vp]),
+        "glbm_stream_copy": (i32, [vp, vp, sz, vp]),
         "glbm_class_table_pressure": (i32, [vp, i32, vp, i32, vp, vp, vp, vp, vp, vp]),
         "glbm_step_n": (i32, [vp, i64, f64]),
         "glbm_residual": (i32, [vp, vp, vp]),
@@ -327,6 +329,10 @@ def glbm_gmm_fit(offsets, x_dev, phi, mu, var, iters, tol=0.0, stream=None):
     _check(_lib.glbm_gmm_fit(n_sets, _ptr(offsets), x_dev, k, _ptr(phi), _ptr(mu), _ptr(var), int(iters), float(tol),
                              _ptr(ll), _ptr(it), _stream() if stream is None else stream))
     return phi, mu, var, ll, it
+
+
+def glbm_stream_copy(src, dst, nbytes, stream=None):
+    _check(_lib.glbm_stream_copy(src, dst, int(nbytes), _stream() if stream is None else stream))
 
 
 def glbm_radius_bins(mu_ln, sigma_ln, n=127):

@@ -315,3 +315,126 @@ def pore_radius_samples(seed: int, m: int, r_iom_median: float = 20e-9, r_om_med
     clusters = ((math.log(r_om_median), sigma_ln_r, om_fraction),
                 (math.log(r_iom_median), sigma_ln_r, 1.0 - om_fraction))
     return np.exp(mixture_samples(seed, m, clusters))
+
+
+# ---------------------------------------------------- the paper's parameter studies
+# Sec. 3.2-3.3 inputs.  Tab. 6 lists the pore-size modes of organic (OM) and
+# inorganic (IOM) matter as mu = 0.4 / 1.4 and sigma = 0.18 / 0.44 "nm"; read as
+# the mean and standard deviation of ln(r / nm) (medians 1.49 and 4.06 nm, a
+# ratio of e: the "roughly 3 times smaller" OM pores of Sec. 3.2).  Tab. 7 gives
+# the pressures, Langmuir and diffusion inputs, porosities and the 16 x 8 um
+# domain.
+TAB6_OM = (0.4, 0.18)     # mean, sd of ln(r / nm)
+TAB6_IOM = (1.4, 0.44)
+TAB7 = dict(p_in=0.2e6, p_out=0.1e6, q_sat=4000.0, d_s=1e-8, langmuir_b=0.25e-6, tortuosity=2.0,
+            eps_iom=0.02, eps_om=0.04, length=16e-6, width=8e-6)
+
+
+@dataclasses.dataclass
+class StudyCase:
+    """One pressure-driven study sample: a matter-only map (IOM / OM, no open pore),
+    per-node radius classes drawn from each phase's mode, Tab. 7-type inputs.
+    Flow along x from p_in (x = 0) to p_out."""
+    name: str
+    phase: np.ndarray                 # uint8 (ny, nx): IOM = 1, OM = 2
+    seed: int
+    r_om_median: float = math.exp(TAB6_OM[0]) * 1e-9
+    r_iom_median: float = math.exp(TAB6_IOM[0]) * 1e-9
+    sigma_om: float = TAB6_OM[1]
+    sigma_iom: float = TAB6_IOM[1]
+    eps_iom: float = TAB7["eps_iom"]
+    eps_om: float = TAB7["eps_om"]
+    temperature: float = 400.0
+    p_in: float = TAB7["p_in"]
+    p_out: float = TAB7["p_out"]
+    q_sat: float = TAB7["q_sat"]
+    langmuir_b: float = TAB7["langmuir_b"]
+    d_s: float = TAB7["d_s"]
+    tortuosity: float = TAB7["tortuosity"]
+    viscosity: float = 18.231e-6
+    dx: float = TAB7["width"] / 128
+    labels: dict = dataclasses.field(default_factory=dict)
+
+    def classes(self) -> np.ndarray:
+        return class_map(self.phase, self.seed)
+
+    def radii(self) -> Tuple[np.ndarray, np.ndarray]:
+        return radius_bins(self.r_iom_median, self.sigma_iom), radius_bins(self.r_om_median, self.sigma_om)
+
+
+def layout_phase(case: int, shape: Tuple[int, int], seed: int, toc: float = 0.5) -> np.ndarray:
+    """Sec. 3.2 layout cases of OM and IOM (flow along x): 1 layers parallel to the flow
+    (OM in the lower rows), 2 OM upstream then IOM, 3 IOM upstream then OM (both in
+    sequence along the flow), 4 OM grown at random by QSGS inside the matter.  TOC is
+    the OM fraction (0.5 for the layered cases, a reading: the paper's figure is
+    not available)."""
+    ny, nx = shape
+    ph = np.full(shape, IOM, np.uint8)
+    if case == 1:
+        ph[:int(round(toc * ny)), :] = OM
+    elif case == 2:
+        ph[:, :int(round(toc * nx))] = OM
+    elif case == 3:
+        ph[:, nx - int(round(toc * nx)):] = OM
+    elif case == 4:
+        om = qsgs_grow(shape, np.ones(shape, np.uint8), int(round(toc * ny * nx)), seed, 2)
+        ph[om.astype(bool)] = OM
+    else:
+        raise ValueError("layout case must be 1..4")
+    return ph
+
+
+def layout_study(shape=(128, 256), realizations: int = 4, seed0: int = 5000):
+    """Cases 1-4 of Sec. 3.2, several radius realizations each (Tab. 6, Tab. 7)."""
+    out = []
+    for case in (1, 2, 3, 4):
+        for r in range(realizations):
+            seed = seed0 + 100 * case + r
+            out.append(StudyCase("layout%d_r%d" % (case, r), layout_phase(case, shape, seed), seed,
+                                 labels={"case": case, "realization": r}))
+    return out
+
+
+def toc_study(shape=(128, 256), tocs=(0.2, 0.4, 0.6, 0.8), d_s=(1e-9, 1e-8, 1e-7, 1e-6, 1e-5), seed0: int = 6000):
+    """Sec. 3.3: OM grown by QSGS inside the matter to each TOC (one map per TOC, shared
+    by every surface diffusivity), times the surface diffusivities of Fig. 15."""
+    out = []
+    for i, toc in enumerate(tocs):
+        seed = seed0 + i
+        ph = layout_phase(4, shape, seed, toc)
+        for ds in d_s:
+            out.append(StudyCase("toc%.1f_ds%.0e" % (toc, ds), ph, seed, d_s=ds, labels={"toc": toc, "d_s": ds}))
+    return out
+
+
+def single_phase_study(phase: int, shape=(64, 64), r_medians=(2e-9, 5e-9, 11e-9, 20e-9, 50e-9, 100e-9),
+                       pressures=((22e6, 20e6),), q_sats=(4000.0,), bs=(0.25e-6,), d_s=5e-7, sigma_ln=0.25,
+                       k_lattice=1e-3, seed0: int = 7000):
+    """Sec. 3.1 (Figs. 5, 6, 9-11): single-phase samples (IOM with eps 0.04, or OM) whose
+    per-node radii follow one lognormal mode (sigma 0.25 in ln r), swept over the mean
+    radius, the pressures, q_sat and b (Tab. 4 inputs: 22 -> 20 MPa, tortuosity 2).
+    The lattice spacing of each sample is chosen so that its K at the mean pressure is
+    about k_lattice in lattice units (Darcy regime; dx only scales the time to converge)."""
+    out = []
+    k = 0
+    for rm in r_medians:
+        for (pin, pout) in pressures:
+            for qs in q_sats:
+                for b in bs:
+                    seed = seed0 + k
+                    k += 1
+                    ph = np.full(shape, phase, np.uint8)
+                    eps = 0.04
+                    # K_0 + Knudsen of the median radius at the mean pressure sets dx
+                    pm = 0.5 * (pin + pout)
+                    d = 2 * rm
+                    kc = eps / 2.0 * d / 4.0
+                    kk = kc * d / 8.0 + 18.231e-6 * (4.0 / 3.0) * kc * math.sqrt(8 * 8.314462618 * 400.0 /
+                                                                              (math.pi * 0.016043)) / pm
+                    dx = math.sqrt(kk / k_lattice)
+                    out.append(StudyCase("phase%d_r%.0e_p%.0f_q%.0f_b%.2e" % (phase, rm, pm / 1e6, qs, b), ph, seed,
+                                         r_om_median=rm, r_iom_median=rm, sigma_om=sigma_ln, sigma_iom=sigma_ln,
+                                         eps_iom=eps, eps_om=eps, p_in=pin, p_out=pout, q_sat=qs, langmuir_b=b,
+                                         d_s=d_s, dx=dx, labels={"phase": phase, "r_median": rm, "p_mean": pm,
+                                                                 "q_sat": qs, "b": b}))
+    return out
