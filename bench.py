@@ -598,7 +598,9 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--side", type=int, default=4096)
-    ap.add_argument("--store", default="f32", choices=("f32", "f16dev", "f16loc", "f32loc", "f64"))
+    ap.add_argument("--store", default=None, choices=("f32", "f16dev", "f16loc", "f32loc", "f64"),
+                    help="population store (default: f64 for the studies, which are solved to r <= 1e-8 "
+                         "under a pressure drive, f32 otherwise)")
     ap.add_argument("--cpu-steps", type=int, default=4000, help="oracle steps of the CPU baseline (about 10 s)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--workload", default="shale4096",
@@ -625,6 +627,8 @@ def main():
     ap.add_argument("--pmc-summary", nargs=4, metavar=("FETCH", "WRITE", "COPY_FETCH", "COPY_WRITE"),
                     help="summarise rocprofv3 --pmc output directories into profiles/")
     args = ap.parse_args()
+    if args.store is None:
+        args.store = "f64" if args.workload == "studies" else "f32"
     if args.pmc_summary:
         pmc_summary(*args.pmc_summary, args)
         return

@@ -257,7 +257,10 @@ int glbm_load_state(glbm_ctx ctx, const void* host, size_t bytes);
  *                            1 nontemporal loads of the planes without an x shift;
  *                            2 workgroups in launch order (clear: grouped per XCD);
  *                            3 per-class constants read through L1 (clear: staged
- *                            in LDS)
+ *                            in LDS); 4 no LDS staging of the population rows in
+ *                            the D2Q9 FP16 sweep (which otherwise stages them for
+ *                            periodic instances with nx a multiple of 8 and tiles
+ *                            of at most 256 x 4 nodes)
  * Errors: GLBM_EINVAL for unknown options or values.
  */
 enum { GLBM_OPT_GRAPH = 1, GLBM_OPT_TIMING = 2, GLBM_OPT_TILE_ROWS = 3, GLBM_OPT_TILE_WIDTH = 4,
@@ -268,7 +271,8 @@ int glbm_sweep_time(glbm_ctx ctx, double* ms_total, int64_t* launches);
 /*
  * Autotuner: time every (tile width, tile rows, cache policy) candidate for
  * `steps` sweeps and keep the fastest.  Widths 64 .. 1024 (up to twice the
- * widest instance), rows 1 .. 16, cache policies 1, 3, 4, 5, 9, 12, 13, 15.
+ * widest instance), rows 1 .. 16, cache policies 1, 3, 4, 5, 9, 12, 13, 15
+ * (and 29, 31 where the LDS-staged FP16 sweep applies).
  * The state advances by those sweeps (an even number per candidate); the
  * residual snapshot is reset.  If chosen is not NULL it receives {width,
  * rows, cache}.  Errors: GLBM_EINVAL for a null context or odd or < 2 steps;

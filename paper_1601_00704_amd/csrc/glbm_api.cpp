@@ -214,6 +214,7 @@ struct glbm_ctx_s {
     int tw_log2 = 6;   // tile width 2^tw_log2
     int th = 4;        // tile height
     int cache = 13;    // memory policy, see Args::cache (nontemporal stores, plain order, L1 table)
+    bool staged_ok = false;  // D2Q9 FP16 store, periodic, every nx a multiple of 8: k_sweep9h applies
     int ntiles = 0;
     bool use_graph = true;
     hipGraphExec_t graph = nullptr;
@@ -245,6 +246,7 @@ struct glbm_ctx_s {
         a.tw_log2 = tw_log2;
         a.nslot = ((1 << tw_log2) * th) / kBlock;
         a.cache = cache;
+        a.staged = (staged_ok && !(cache & 16) && tw_log2 <= 8 && th <= 4) ? 1 : 0;
         return a;
     }
 };
@@ -571,7 +573,11 @@ int glbm_init_geometry(glbm_ctx* out, int32_t n_inst, const glbm_instance_desc* 
         cls_total += round_up(n, 256);
         snap_total += round_up(3 * n, 64);
     }
-    c->cfg.bc = desc[0].pressure_axis ? 3 : (any_wall_node ? 2 : (any_wall_face ? 1 : 0));
+    c->cfg.bc = desc[0].pressure_axis ? (any_wall_node ? 4 : 3) : (any_wall_node ? 2 : (any_wall_face ? 1 : 0));
+    c->staged_ok = c->cfg.q == GLBM_D2Q9 && c->cfg.bc == 0 &&
+                   (c->cfg.store == GLBM_STORE_F16DEV || c->cfg.store == GLBM_STORE_F16LOC);
+    for (int i = 0; i < n_inst; ++i)
+        if (desc[i].nx % 8) c->staged_ok = false;
     c->steps.assign(n_inst, 0);
     c->snap_step.assign(n_inst, 0);
     c->active_h.assign(n_inst, 1);
@@ -648,7 +654,7 @@ int glbm_set_local_perm(glbm_ctx c, int32_t inst, int32_t n_classes, const doubl
     bool forch = false;
     for (int k = 0; k < n_classes && f_eps; ++k)
         if (f_eps[k] > 0.0 && std::isfinite(k_lattice[k])) forch = true;
-    if (forch && c->cfg.bc == 3) return fail(GLBM_EINVAL, "F_eps > 0 is not supported with pressure faces");
+    if (forch && c->cfg.bc >= 3) return fail(GLBM_EINVAL, "F_eps > 0 is not supported with pressure faces");
 
     int rc = enter(c);
     if (rc) return rc;
@@ -667,7 +673,7 @@ int glbm_set_local_perm(glbm_ctx c, int32_t inst, int32_t n_classes, const doubl
             double* r = &row[(size_t)k * kTabW];
             r[TAB_EPS] = e;
             r[TAB_INV_EPS] = 1.0 / e;
-            if (c->cfg.bc == 3) {
+            if (c->cfg.bc >= 3) {
                 // pressure-driven format with a pressure-independent K: K(P) = A
                 const bool open = kinv == 0.0;
                 r[TAB_PA] = open ? 1.0 : k_lattice[k];
@@ -703,7 +709,7 @@ int glbm_set_pressure_perm(glbm_ctx c, int32_t inst, int32_t n_classes, const do
 {
     g_err.clear();
     if (!c) return fail(GLBM_EINVAL, "null context");
-    if (c->cfg.bc != 3) return fail(GLBM_EINVAL, "the instances of this context have no pressure faces");
+    if (c->cfg.bc < 3) return fail(GLBM_EINVAL, "the instances of this context have no pressure faces");
     if (inst < -1 || inst >= c->n_inst) return fail(GLBM_EINVAL, "instance %d out of range", inst);
     if (n_classes < 1 || n_classes > 255) return fail(GLBM_EINVAL, "n_classes must be in [1, 255]");
     if (!eps || !k_const || !k_kn || !k_surf || !lb) return fail(GLBM_EINVAL, "every coefficient array is required");
@@ -1120,7 +1126,7 @@ int glbm_set_option(glbm_ctx c, int32_t option, int64_t value)
         return build_tiles(c);
     }
     case GLBM_OPT_CACHE:
-        if (value < 0 || value > 15) return fail(GLBM_EINVAL, "memory policy must be in [0, 15]");
+        if (value < 0 || value > 31) return fail(GLBM_EINVAL, "memory policy must be in [0, 31]");
         c->cache = (int)value;
         free_graph(c);
         return GLBM_OK;
@@ -1156,8 +1162,10 @@ int glbm_autotune(glbm_ctx c, int32_t steps, int32_t* chosen)
         if (twl > 6 && (1 << twl) > 2 * max_nx) break;
         for (int th : {1, 2, 4, 8, 16}) {
             if (!tile_ok(twl, th)) continue;
-            // policies with and without nontemporal stores (bit 0)
-            for (int cache : {1, 3, 4, 5, 9, 12, 13, 15}) {
+            // policies with and without nontemporal stores (bit 0), and (bit 4) the
+            // plain FP16 sweep where the LDS-staged one would apply
+            for (int cache : {1, 3, 4, 5, 9, 12, 13, 15, 29, 31}) {
+                if ((cache & 16) && !(c->staged_ok && twl <= 8 && th <= 4)) continue;
                 c->cache = cache;
                 rc = glbm_set_option(c, GLBM_OPT_TILE_WIDTH, 1 << twl);
                 if (!rc) rc = glbm_set_option(c, GLBM_OPT_TILE_ROWS, th);

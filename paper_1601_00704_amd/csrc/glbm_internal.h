@@ -26,7 +26,7 @@ enum TabSlot {
     TAB_C0 = 4,         // c0, Eq. (36)
     TAB_C1 = 5,         // c1, Eq. (37)
     TAB_FORCH = 6,      // eps F_eps / sqrt(K)
-    // pressure-driven instances (bc 3): K(P) = A + (B + C / (1 + b P)) / P, 1/K scaled by OPEN
+    // pressure-driven instances (bc 3, 4): K(P) = A + (B + C / (1 + b P)) / P, 1/K scaled by OPEN
     TAB_PA = 2,         // A (K_0 / dx^2; 1 for an open pore)
     TAB_PB = 3,         // B (eta D_K / dx^2)
     TAB_PC = 4,         // C (surface-diffusion coefficient / dx^2)
@@ -74,7 +74,7 @@ struct InstDev {
     float scale, inv_scale;  // FP16 deviation scale 2^s and 2^-s
     float gf[3];             // g, omega and cforce rounded to float (FP32 kernels)
     float omegaf, cforcef;
-    // pressure faces (bc 3): axis 0..2, face densities as rho - 1, and the local
+    // pressure faces (bc 3, 4): axis 0..2, face densities as rho - 1, and the local
     // pressure P = p0 + (rho - 1) p1 (double, and float copies)
     int32_t paxis;
     double drin, drout, p0, p1;
@@ -102,13 +102,14 @@ struct Args {
     int32_t tw_log2;       // tile width 2^tw_log2 nodes along x (64 .. 1024)
     int32_t nslot;         // tile nodes / kBlock: nodes each thread visits
     int32_t cache;         // bit 0: nontemporal population stores; bit 1: nontemporal loads of x-aligned planes
+    int32_t staged;        // D2Q9 FP16 sweep with LDS-staged rows (k_sweep9h)
 };
 
 // Kernel configuration of a context.
 struct Config {
     int q;        // 9 or 19
     int store;    // GLBM_STORE_*
-    int bc;       // 0 periodic only, 1 face walls, 2 face walls + wall nodes, 3 pressure faces (+ wall nodes)
+    int bc;       // 0 periodic only, 1 face walls, 2 face walls + wall nodes, 3 pressure faces, 4 pressure faces + wall nodes
     bool forch;   // any F_eps > 0
 };
 

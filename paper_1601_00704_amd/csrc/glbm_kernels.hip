@@ -59,6 +59,12 @@ template <> struct Lat<19> {
     static constexpr double w(int i) { return i == 0 ? 1.0 / 3.0 : (i < 7 ? 1.0 / 18.0 : 1.0 / 36.0); }
 };
 
+// Boundary modes (Config::bc): 0 periodic, 1 face walls, 2 face walls and wall
+// nodes, 3 pressure faces, 4 pressure faces and wall nodes.
+constexpr bool face_walls(int bc) { return bc == 1 || bc == 2; }
+constexpr bool wall_nodes(int bc) { return bc == 2 || bc == 4; }
+constexpr bool pressure_faces(int bc) { return bc >= 3; }
+
 // ----------------------------------------------------------------- storage --
 template <int STORE> struct St;
 // kRho: the stored value is relative to w_i rho(x) of the node that wrote it,
@@ -162,7 +168,7 @@ template <typename T> __device__ __forceinline__ T inst_cforce(const InstDev& I)
     if constexpr (sizeof(T) == 4) return I.cforcef; else return I.cforce;
 }
 
-// Zou-He rule on a pressure face (bc 3).  On entry d holds the deviations
+// Zou-He rule on a pressure face (bc 3 and 4).  On entry d holds the deviations
 // f_i - w_i of the known populations (for a kRho store: local parts, with the
 // source densities in r) and zeros for the directions entering through the
 // face.  With n the unit normal into the domain (side * the axis) and the face
@@ -236,7 +242,7 @@ __device__ __forceinline__ void gather(typename St<STORE>::T (&d)[Q], typename S
     // outlet face (n - 1), 0 elsewhere; directions entering through the face
     // (side * e_a > 0) are rebuilt below instead of pulled
     int side = 0;
-    if constexpr (BC == 3) {
+    if constexpr (pressure_faces(BC)) {
         const int a = I.paxis;
         const int ca = a == 0 ? x : (a == 1 ? y : z), na = a == 0 ? nx : (a == 1 ? ny : nz);
         side = ca == 0 ? 1 : (ca == na - 1 ? -1 : 0);
@@ -244,7 +250,7 @@ __device__ __forceinline__ void gather(typename St<STORE>::T (&d)[Q], typename S
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
         const int ex = L::ex(i), ey = L::ey(i), ez = L::ez(i);
-        if constexpr (BC == 3) {
+        if constexpr (pressure_faces(BC)) {
             const int ea = I.paxis == 0 ? ex : (I.paxis == 1 ? ey : ez);
             if (side * ea > 0) {
                 d[i] = 0;
@@ -262,16 +268,18 @@ __device__ __forceinline__ void gather(typename St<STORE>::T (&d)[Q], typename S
         else
             idx = i * stride + sn;
         int node = sn;
-        if (BC >= 1) {
+        if constexpr (face_walls(BC) || wall_nodes(BC)) {
             const uint32_t w = I.walls;
             bool blocked = false;
-            if (ex > 0) blocked |= (x == 0) && (w & 1u);
-            if (ex < 0) blocked |= (x == nx - 1) && (w & 2u);
-            if (ey > 0) blocked |= (y == 0) && (w & 4u);
-            if (ey < 0) blocked |= (y == ny - 1) && (w & 8u);
-            if (ez > 0) blocked |= (z == 0) && (w & 16u);
-            if (ez < 0) blocked |= (z == nz - 1) && (w & 32u);
-            if (BC >= 2 && i != 0) blocked |= cls[sn] == kWallClass;
+            if constexpr (face_walls(BC)) {
+                if (ex > 0) blocked |= (x == 0) && (w & 1u);
+                if (ex < 0) blocked |= (x == nx - 1) && (w & 2u);
+                if (ey > 0) blocked |= (y == 0) && (w & 4u);
+                if (ey < 0) blocked |= (y == ny - 1) && (w & 8u);
+                if (ez > 0) blocked |= (z == 0) && (w & 16u);
+                if (ez < 0) blocked |= (z == nz - 1) && (w & 32u);
+            }
+            if (wall_nodes(BC) && i != 0) blocked |= cls[sn] == kWallClass;
             if (blocked) {
                 if constexpr (node_blocks(STORE))
                     idx = pidx<Q, STORE>(L::opp(i), n, stride);
@@ -290,7 +298,7 @@ __device__ __forceinline__ void gather(typename St<STORE>::T (&d)[Q], typename S
         d[i] = S::dec(raw, I.inv_scale);
         if constexpr (S::kRho) r[i] = *elem(rho_plane<STORE>(src, Q, stride), uint32_t(node));
     }
-    if constexpr (BC == 3)
+    if constexpr (pressure_faces(BC))
         if (side != 0) fill_face<Q, S::kRho>(d, r, I, side);
 }
 
@@ -490,7 +498,7 @@ __device__ __forceinline__ void relax(T (&d)[Q], const NodeT& s, const T* tab, T
 }
 
 // Columns of the class table a kernel reads (pressure faces and Forchheimer use all).
-template <int BC, bool FORCH> constexpr int tab_cols() { return (FORCH || BC == 3) ? kTabW : 4; }
+template <int BC, bool FORCH> constexpr int tab_cols() { return (FORCH || pressure_faces(BC)) ? kTabW : 4; }
 
 template <int Q, typename T, int NT>
 __device__ __forceinline__ void load_table(T* lds, const Args& a, int inst)
@@ -506,6 +514,73 @@ __device__ __forceinline__ void load_table(T* lds, const Args& a, int inst)
 // stores.  It is a template parameter so that the two store forms stay
 // separate code: as a run-time branch over otherwise identical stores, the
 // optimizer merges them and drops the nontemporal hint.
+// Collide one node (moments, Eq. 32-37; relaxation towards Eq. 30 with the
+// forcing of Eq. 31) and write its q post-collision values (and, for a kRho
+// store, its density) to the other buffer.  d and r hold what gather()
+// returned for the node; ct is its row of the class table.
+template <int Q, int STORE, int BC, bool FORCH, bool NTS>
+__device__ __forceinline__ void collide_store(typename St<STORE>::T (&d)[Q], typename St<STORE>::T (&r)[Q], int n,
+                                              const typename St<STORE>::T* ct, const InstDev& I,
+                                              const typename St<STORE>::T (&g)[3], typename St<STORE>::T omega,
+                                              typename St<STORE>::T cforce, typename St<STORE>::S* __restrict__ dst)
+{
+    using SS = St<STORE>;
+    using T = typename SS::T;
+    Node<Q, T, FORCH, pressure_faces(BC)> s;
+    if constexpr (SS::kRho) {
+        // local form; collision conserves mass, so the node writes its
+        // density and the parts relative to it
+        const T dr = localize<Q, T>(d, r);
+        s.moments_with(d, dr, ct, g, I);
+        relax<Q, T, true>(d, s, ct, omega, cforce);
+        if constexpr (node_blocks(STORE))
+            rho_plane<STORE>(dst, Q, I.stride)[n] = dr;
+        else
+            *elem(rho_plane<STORE>(dst, Q, I.stride), uint32_t(n)) = dr;
+    } else if constexpr (STORE == GLBM_STORE_F32) {
+        // FP32 deviations d_i = f_i - w_i collide in the local form: the
+        // node's own density part w_i drho is split off with a fused
+        // multiply-add (the product is not rounded), the collision works
+        // on the small parts, and one more fused multiply-add puts the
+        // density back.  Each stored value then carries a single rounding
+        // at the scale of the density deviation instead of several, which
+        // is what keeps the residual falling below 1e-8 on shale maps.
+        using L = Lat<Q>;
+        T dr = d[0];
+#pragma unroll
+        for (int i = 1; i < Q; ++i) dr += d[i];
+#pragma unroll
+        for (int i = 0; i < Q; ++i) d[i] = __builtin_fmaf(-T(L::w(i)), dr, d[i]);
+        s.moments_with(d, dr, ct, g, I);
+        relax<Q, T, true>(d, s, ct, omega, cforce);
+#pragma unroll
+        for (int i = 0; i < Q; ++i) d[i] = __builtin_fmaf(T(L::w(i)), dr, d[i]);
+    } else {
+        s.moments(d, ct, g, I);
+        relax<Q, T, false>(d, s, ct, omega, cforce);
+    }
+    if constexpr (node_blocks(STORE)) {
+        if constexpr (NTS) {
+#pragma unroll
+            for (int i = 0; i < Q; ++i)
+                __builtin_nontemporal_store(SS::enc(d[i], I.scale), dst + pidx<Q, STORE>(i, n, 0));
+        } else {
+#pragma unroll
+            for (int i = 0; i < Q; ++i) dst[pidx<Q, STORE>(i, n, 0)] = SS::enc(d[i], I.scale);
+        }
+    } else {
+        // plane base uniform, one 32-bit byte offset shared by the q stores
+        if constexpr (NTS) {
+#pragma unroll
+            for (int i = 0; i < Q; ++i)
+                __builtin_nontemporal_store(SS::enc(d[i], I.scale), elem(dst + (size_t)i * I.stride, uint32_t(n)));
+        } else {
+#pragma unroll
+            for (int i = 0; i < Q; ++i) *elem(dst + (size_t)i * I.stride, uint32_t(n)) = SS::enc(d[i], I.scale);
+        }
+    }
+}
+
 template <int U, int Q, int STORE, int BC, bool FORCH, bool NTS>
 __device__ __forceinline__ void sweep_slots(const Args& a, const Tile& t, const InstDev& I, int sl0,
                                             const typename St<STORE>::T* __restrict__ tb, int tw,
@@ -530,66 +605,13 @@ __device__ __forceinline__ void sweep_slots(const Args& a, const Tile& t, const 
         ok[u] = x < I.nx && y < I.ny;
         n[u] = ok[u] ? (z * I.ny + y) * I.nx + x : 0;
         c[u] = ok[u] ? cls[n[u]] : 0;
-        if (BC >= 2 && c[u] == kWallClass) ok[u] = false;
+        if (wall_nodes(BC) && c[u] == kWallClass) ok[u] = false;
         if (ok[u]) gather<Q, STORE, BC>(d[u], r[u], src, cls, I, x, y, z, n[u], nt_load);
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
         if (!ok[u]) continue;
-        Node<Q, T, FORCH, BC == 3> s;
-        const T* ct = tb + c[u] * tw;
-        if constexpr (SS::kRho) {
-            // local form; collision conserves mass, so the node writes its
-            // density and the parts relative to it
-            const T dr = localize<Q, T>(d[u], r[u]);
-            s.moments_with(d[u], dr, ct, g, I);
-            relax<Q, T, true>(d[u], s, ct, omega, cforce);
-            if constexpr (node_blocks(STORE))
-                rho_plane<STORE>(dst, Q, I.stride)[n[u]] = dr;
-            else
-                *elem(rho_plane<STORE>(dst, Q, I.stride), uint32_t(n[u])) = dr;
-        } else if constexpr (STORE == GLBM_STORE_F32) {
-            // FP32 deviations d_i = f_i - w_i collide in the local form: the
-            // node's own density part w_i drho is split off with a fused
-            // multiply-add (the product is not rounded), the collision works
-            // on the small parts, and one more fused multiply-add puts the
-            // density back.  Each stored value then carries a single rounding
-            // at the scale of the density deviation instead of several, which
-            // is what keeps the residual falling below 1e-8 on shale maps.
-            using L = Lat<Q>;
-            T dr = d[u][0];
-#pragma unroll
-            for (int i = 1; i < Q; ++i) dr += d[u][i];
-#pragma unroll
-            for (int i = 0; i < Q; ++i) d[u][i] = __builtin_fmaf(-T(L::w(i)), dr, d[u][i]);
-            s.moments_with(d[u], dr, ct, g, I);
-            relax<Q, T, true>(d[u], s, ct, omega, cforce);
-#pragma unroll
-            for (int i = 0; i < Q; ++i) d[u][i] = __builtin_fmaf(T(L::w(i)), dr, d[u][i]);
-        } else {
-            s.moments(d[u], ct, g, I);
-            relax<Q, T, false>(d[u], s, ct, omega, cforce);
-        }
-        if constexpr (node_blocks(STORE)) {
-            if constexpr (NTS) {
-#pragma unroll
-                for (int i = 0; i < Q; ++i)
-                    __builtin_nontemporal_store(SS::enc(d[u][i], I.scale), dst + pidx<Q, STORE>(i, n[u], 0));
-            } else {
-#pragma unroll
-                for (int i = 0; i < Q; ++i) dst[pidx<Q, STORE>(i, n[u], 0)] = SS::enc(d[u][i], I.scale);
-            }
-        } else {
-            // plane base uniform, one 32-bit byte offset shared by the q stores
-            if constexpr (NTS) {
-#pragma unroll
-                for (int i = 0; i < Q; ++i)
-                    __builtin_nontemporal_store(SS::enc(d[u][i], I.scale), elem(dst + (size_t)i * I.stride, uint32_t(n[u])));
-            } else {
-#pragma unroll
-                for (int i = 0; i < Q; ++i) *elem(dst + (size_t)i * I.stride, uint32_t(n[u])) = SS::enc(d[u][i], I.scale);
-            }
-        }
+        collide_store<Q, STORE, BC, FORCH, NTS>(d[u], r[u], n[u], tb + c[u] * tw, I, g, omega, cforce, dst);
     }
 }
 
@@ -667,6 +689,114 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1, W))) 
 }
 constexpr int kWaves9 = 6;
 
+// ---------------------------------------------------- LDS-staged FP16 sweep --
+// D2Q9 with an FP16 store on periodic instances whose nx is a multiple of 8,
+// tiles of at most kStW x kStH nodes.  A workgroup first copies into LDS, for
+// each of the nine planes, the rows its nodes pull from (the tile shifted by
+// -e_i, with one 8-half chunk more on each side, wrapped periodically) and,
+// for F16LOC, the density rows y0 - 1 .. y0 + th, all with 16-byte loads;
+// every node then reads its nine values and source densities from LDS.  That
+// replaces nine 2-byte and nine 4-byte loads per node, which kept the address
+// unit busy for 85 % of the plain kernel's cycles, by about two 16-byte loads.
+// The arithmetic and the stores are those of k_sweep (collide_store), so the
+// results are bitwise equal.
+constexpr int kStW = 256;                  // widest staged tile
+constexpr int kStH = 4;                    // most rows
+constexpr int kStPad = 8;                  // halo: one 8-half chunk on each side
+constexpr int kStRow = kStW + 2 * kStPad;  // staged columns per row
+// e_y + 1 of the D2Q9 directions, two bits per direction
+constexpr uint32_t pack9(bool y)
+{
+    uint32_t v = 0;
+    for (int i = 0; i < 9; ++i) v |= uint32_t((y ? Lat<9>::ey(i) : Lat<9>::ex(i)) + 1) << (2 * i);
+    return v;
+}
+constexpr uint32_t kEy9 = pack9(true);
+
+template <int STORE, bool FORCH, bool NTS>
+__device__ __forceinline__ void sweep_staged_tile(const Args& a, const Tile& t, const InstDev& I, const float* tb,
+                                                  int tcols, uint16_t (*sp)[kStH][kStRow],
+                                                  float (*srho)[kStRow])
+{
+    using SS = St<STORE>;
+    using S = typename SS::S;
+    using T = typename SS::T;
+    using L = Lat<9>;
+    typedef unsigned int u32x4v __attribute__((ext_vector_type(4)));
+    const int twl = a.tw_log2, tw = 1 << twl, th = (a.nslot * kBlock) >> twl;
+    const int nx = I.nx, ny = I.ny;
+    const int sel = (a.parity + I.par) & 1;
+    const S* __restrict__ src = static_cast<const S*>(a.buf[sel]) + I.pop_off;
+    S* __restrict__ dst = static_cast<S*>(a.buf[sel ^ 1]) + I.pop_off;
+    const uint8_t* __restrict__ cls = a.cls + I.cls_off;
+    // populations: plane i, staged row rr <- grid row y0 + rr - e_y(i), staged
+    // column 8 cc .. 8 cc + 7 <- grid columns x0 - 8 + 8 cc .. (wrapped)
+    const int cpr = (tw >> 3) + 2;
+    for (int k = threadIdx.x; k < 9 * th * cpr; k += kBlock) {
+        const int i = k / (th * cpr), rem = k - i * th * cpr, rr = rem / cpr, cc = rem - rr * cpr;
+        const int ey = int((kEy9 >> (2 * i)) & 3u) - 1;
+        const int gy = (t.y0 + rr - ey + ny) % ny;
+        const int gx = (t.x0 - kStPad + 8 * cc + nx) % nx;
+        const S* p = src + (size_t)i * I.stride + (size_t)gy * nx + gx;
+        *reinterpret_cast<u32x4v*>(&sp[i][rr][8 * cc]) = *reinterpret_cast<const u32x4v*>(p);
+    }
+    if constexpr (SS::kRho) {
+        // density rows y0 - 1 .. y0 + th, columns x0 - 8 .. x0 + tw + 7, four floats a load
+        const float* rp = rho_plane<STORE>(src, 9, I.stride);
+        const int cpr4 = (tw >> 2) + 4;
+        for (int k = threadIdx.x; k < (th + 2) * cpr4; k += kBlock) {
+            const int rr = k / cpr4, cc = k - rr * cpr4;
+            const int gy = (t.y0 - 1 + rr + ny) % ny;
+            const int gx = (t.x0 - kStPad + 4 * cc + nx) % nx;
+            *reinterpret_cast<u32x4v*>(&srho[rr][4 * cc]) =
+                *reinterpret_cast<const u32x4v*>(rp + (size_t)gy * nx + gx);
+        }
+    }
+    __syncthreads();
+    const T g[3] = {inst_g<T>(I, 0), inst_g<T>(I, 1), inst_g<T>(I, 2)};
+    const T omega = inst_omega<T>(I), cforce = inst_cforce<T>(I);
+    for (int sl = 0; sl < a.nslot; ++sl) {
+        const int slot = sl * kBlock + threadIdx.x;
+        const int lx = slot & (tw - 1), ry = slot >> twl;
+        const int x = t.x0 + lx, y = t.y0 + ry;
+        if (x >= nx || y >= ny) continue;
+        const int n = y * nx + x;
+        T d[9], r[9];
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+            const int col = lx + kStPad - L::ex(i);
+            d[i] = SS::dec(sp[i][ry][col], I.inv_scale);
+            if constexpr (SS::kRho) r[i] = srho[ry + 1 - L::ey(i)][col];
+        }
+        collide_store<9, STORE, 0, FORCH, NTS>(d, r, n, tb + cls[n] * tcols, I, g, omega, cforce, dst);
+    }
+}
+
+template <int STORE, bool FORCH>
+__global__ __launch_bounds__(kBlock) void k_sweep9h(Args a)
+{
+    constexpr int NT = tab_cols<0, FORCH>();
+    __shared__ float tab[kClasses * NT];
+    __shared__ __align__(16) uint16_t sp[9][kStH][kStRow];
+    __shared__ __align__(16) float srho[St<STORE>::kRho ? kStH + 2 : 1][kStRow];
+    const int tid = (a.cache & 4) ? (int)blockIdx.x : xcd_tile(blockIdx.x, gridDim.x);
+    const Tile t = a.tiles[tid];
+    if (!a.active[t.inst]) return;
+    const InstDev& I = a.inst[t.inst];
+    const float* tb;
+    int tcols;
+    if (a.cache & 8) {
+        tb = static_cast<const float*>(a.tab) + (size_t)t.inst * kClasses * kTabW;
+        tcols = kTabW;
+    } else {
+        load_table<9, float, NT>(tab, a, t.inst);   // ends with a barrier before tab is read
+        tb = tab;
+        tcols = NT;
+    }
+    if (a.cache & 1) sweep_staged_tile<STORE, FORCH, true>(a, t, I, tb, tcols, sp, srho);
+    else sweep_staged_tile<STORE, FORCH, false>(a, t, I, tb, tcols, sp, srho);
+}
+
 // ------------------------------------------------------------ observations --
 __device__ __forceinline__ double wave_sum(double v)
 {
@@ -715,10 +845,10 @@ __device__ __forceinline__ void observe_tile(const Args& a, const Tile& t, const
         if (x >= I.nx || y >= I.ny) continue;
         const int n = (z * I.ny + y) * I.nx + x;
         const int c = cls[n];
-        if (BC >= 2 && c == kWallClass) continue;
+        if (wall_nodes(BC) && c == kWallClass) continue;
         T d[Q], rr[Q];
         gather<Q, STORE, BC>(d, rr, src, cls, I, x, y, z, n);
-        Node<Q, T, FORCH, BC == 3> s;
+        Node<Q, T, FORCH, pressure_faces(BC)> s;
         if constexpr (SS::kRho) {
             const T dr = localize<Q, T>(d, rr);
             s.moments_with(d, dr, tb + c * tw, g, I);
@@ -830,10 +960,19 @@ __global__ __launch_bounds__(kFinBlock) void k_finalize(Args a, double tol, int 
 // stores: the memory pattern of a sweep without its gathers or arithmetic, as a
 // practical bandwidth ceiling for this GPU.
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+constexpr int kCopyUnroll = 4;   // independent 16-byte loads in flight per lane
 __global__ __launch_bounds__(256) void k_stream_copy(const u32x4* __restrict__ src, u32x4* __restrict__ dst, size_t n)
 {
-    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
-        __builtin_nontemporal_store(__builtin_nontemporal_load(src + i), dst + i);
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+    for (; i + (kCopyUnroll - 1) * stride < n; i += kCopyUnroll * stride) {
+        u32x4 v[kCopyUnroll];
+#pragma unroll
+        for (int u = 0; u < kCopyUnroll; ++u) v[u] = __builtin_nontemporal_load(src + i + u * stride);
+#pragma unroll
+        for (int u = 0; u < kCopyUnroll; ++u) __builtin_nontemporal_store(v[u], dst + i + u * stride);
+    }
+    for (; i < n; i += stride) __builtin_nontemporal_store(__builtin_nontemporal_load(src + i), dst + i);
 }
 
 __global__ void k_zero(uint32_t* p, size_t n)
@@ -893,7 +1032,7 @@ __global__ __launch_bounds__(kBlock) void k_set_fields(Args a, int inst, const R
             if (sz < 0) { blocked |= (I.walls & 16u) != 0; sz += I.nz; }
             if (sz >= I.nz) { blocked |= (I.walls & 32u) != 0; sz -= I.nz; }
             const int sn = (sz * I.ny + sy) * I.nx + sx;
-            if (BC >= 2 && !blocked && i != 0) blocked = cls[sn] == kWallClass;
+            if (wall_nodes(BC) && !blocked && i != 0) blocked = cls[sn] == kWallClass;
             const int idx = blocked ? pidx<Q, STORE>(L::opp(i), n, I.stride) : pidx<Q, STORE>(i, sn, I.stride);
             // a kRho value is decoded with the density of the node whose slot it occupies
             const T dr = SS::kRho ? drho_at(blocked ? n : sn) : T(0);
@@ -939,7 +1078,7 @@ __global__ __launch_bounds__(kBlock) void k_get_fields(Args a, int inst, double*
         T ct[kTabW];
 #pragma unroll
         for (int k = 0; k < kTabW; ++k) ct[k] = tabg[c * kTabW + k];
-        Node<Q, T, FORCH, BC == 3> s;
+        Node<Q, T, FORCH, pressure_faces(BC)> s;
         if constexpr (SS::kRho) {
             const T dr = localize<Q, T>(d, rr);
             s.moments_with(d, dr, ct, g, I);
@@ -961,6 +1100,12 @@ __global__ __launch_bounds__(kBlock) void k_get_fields(Args a, int inst, double*
 template <int Q, int STORE, int BC, bool FORCH> struct SweepK {
     static hipError_t go(const Args& a, hipStream_t s)
     {
+        if constexpr (Q == 9 && !node_blocks(STORE) && BC == 0) {
+            if (a.staged) {
+                hipLaunchKernelGGL((k_sweep9h<STORE, FORCH>), dim3(a.ntiles), dim3(kBlock), 0, s, a);
+                return hipGetLastError();
+            }
+        }
         if constexpr (Q == 19)
             hipLaunchKernelGGL((k_sweep19<STORE, BC, FORCH, waves19<STORE>()>), dim3(a.ntiles), dim3(kBlock), 0, s, a);
         else if constexpr (node_blocks(STORE))
@@ -992,7 +1137,8 @@ hipError_t dispatch(const Config& c, A... args)
 #define GLBM_CASE(QQ, SS, BB, FF)                                                          \
     if (c.q == QQ && c.store == SS && c.bc == BB && c.forch == FF) return K<QQ, SS, BB, FF>::go(args...);
 #define GLBM_F(QQ, SS, BB) GLBM_CASE(QQ, SS, BB, false) GLBM_CASE(QQ, SS, BB, true)
-#define GLBM_B(QQ, SS) GLBM_F(QQ, SS, 0) GLBM_F(QQ, SS, 1) GLBM_F(QQ, SS, 2) GLBM_CASE(QQ, SS, 3, false)
+#define GLBM_B(QQ, SS)                                                                      \
+    GLBM_F(QQ, SS, 0) GLBM_F(QQ, SS, 1) GLBM_F(QQ, SS, 2) GLBM_CASE(QQ, SS, 3, false) GLBM_CASE(QQ, SS, 4, false)
 #define GLBM_S(QQ)                                                                                 \
     GLBM_B(QQ, GLBM_STORE_F64) GLBM_B(QQ, GLBM_STORE_F32) GLBM_B(QQ, GLBM_STORE_F16DEV)              \
     GLBM_B(QQ, GLBM_STORE_F16LOC) GLBM_B(QQ, GLBM_STORE_F32LOC)
@@ -1037,7 +1183,7 @@ hipError_t launch_stream_copy(const void* src, void* dst, size_t bytes, hipStrea
 {
     const size_t n = bytes / 16;
     if (n == 0) return hipSuccess;
-    const size_t blocks = std::min<size_t>((n + 255) / 256, 8192);
+    const size_t blocks = std::min<size_t>((n + 256 * kCopyUnroll - 1) / (256 * kCopyUnroll), 65536);
     hipLaunchKernelGGL(k_stream_copy, dim3((unsigned)blocks), dim3(256), 0, s, static_cast<const u32x4*>(src),
                        static_cast<u32x4*>(dst), n);
     return hipGetLastError();
@@ -1063,7 +1209,7 @@ hipError_t launch_set_fields(const Config& c, const Args& a, int inst, int ntile
                                                        static_cast<const double*>(u))                     \
                    : set_fields_go<QQ, SS, BB, float>(a, s, inst, ntiles, static_cast<const float*>(rho),   \
                                                       static_cast<const float*>(u));
-#define GLBM_SF_B(QQ, SS) GLBM_SF(QQ, SS, 0) GLBM_SF(QQ, SS, 1) GLBM_SF(QQ, SS, 2) GLBM_SF(QQ, SS, 3)
+#define GLBM_SF_B(QQ, SS) GLBM_SF(QQ, SS, 0) GLBM_SF(QQ, SS, 1) GLBM_SF(QQ, SS, 2) GLBM_SF(QQ, SS, 3) GLBM_SF(QQ, SS, 4)
 #define GLBM_SF_S(QQ)                                                                              \
     GLBM_SF_B(QQ, GLBM_STORE_F64) GLBM_SF_B(QQ, GLBM_STORE_F32) GLBM_SF_B(QQ, GLBM_STORE_F16DEV)     \
     GLBM_SF_B(QQ, GLBM_STORE_F16LOC) GLBM_SF_B(QQ, GLBM_STORE_F32LOC)

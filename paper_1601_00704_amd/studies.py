@@ -46,7 +46,7 @@ def gas_params(case, molar_mass=0.016043):
     return p
 
 
-def solve_study(cases, maps=None, store="f32", tol=1e-8, max_steps=3000000, tile=None):
+def solve_study(cases, maps=None, store="f64", tol=1e-8, max_steps=3000000, tile=None):
     """Solve every sample of a study in one batched context; returns per-sample records
     and the run's wall time, steps and lattice updates."""
     maps = maps if maps is not None else [c.classes() for c in cases]
@@ -82,7 +82,7 @@ def main(argv=None):
     import shale_inputs as si
     ap = argparse.ArgumentParser()
     ap.add_argument("study", choices=("layout", "toc", "iom", "om"))
-    ap.add_argument("--store", default="f32")
+    ap.add_argument("--store", default="f64")
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--realizations", type=int, default=4)
     ap.add_argument("--out", default=None)

@@ -233,6 +233,28 @@ def test_cache_policies_bitwise(gpu, q, store):
             assert r[0] == ref[1] and st[0] == ref[2], cache
 
 
+@pytest.mark.parametrize("store", ["f16loc", "f16dev"])
+@pytest.mark.parametrize("shape,tile", [((48, 64), (64, 4)), ((37, 200), (128, 2)), ((21, 256), (256, 1)),
+                                        ((9, 8), (64, 4))])
+def test_staged_fp16_sweep_bitwise(gpu, store, shape, tile):
+    """The D2Q9 FP16 sweep that stages population and density rows in LDS (periodic
+    instances, nx a multiple of 8) gives the same bits as the plain FP16 sweep (cache
+    policy bit 4), including tiles wider than the grid and ragged last rows."""
+    g = gpu
+    cls, eps, k, _ = random_case(shape, seed=77)
+    G = (2e-5, -1e-5, 0)
+    out = []
+    for cache in (13, 29, 15, 31):
+        print("case store=%s shape=%s tile=%s cache=%d" % (store, shape, tile, cache), flush=True)
+        s = gpu_solver(g, 9, cls, eps, k, G=G, store=store, tile=tile, cache=cache)
+        s.step(150)
+        out.append((s.populations(), s.residual()))
+        s.close()
+    for p, r in out[1:]:
+        assert np.array_equal(p, out[0][0])
+        assert r[0][0] == out[0][1][0][0]
+
+
 def test_batch_per_instance_convergence(gpu):
     """Instances stop individually at their own first check with r <= tol."""
     g = gpu

@@ -71,7 +71,7 @@ def test_layout_study_matches_oracle_and_orders_cases(gpu):
 def test_toc_study_trend_depends_on_surface_diffusivity(gpu):
     from paper_1601_00704_amd import studies
     cases = _small(si.toc_study((32, 64), tocs=(0.2, 0.8), d_s=(1e-9, 1e-5)))
-    res, run = studies.solve_study(cases, store="f32", tol=1e-8, max_steps=2000000)
+    res, run = studies.solve_study(cases, store="f64", tol=1e-8, max_steps=2000000)
     k = {(r["toc"], r["d_s"]): r["k_lattice"] for r in res}
     print("run: %s; k: %s" % (run, k))
     assert run["rc"] == gpu.GLBM_OK
