@@ -47,7 +47,8 @@ extern "C" {
  *            y_pitch, channels [y_off, y_off + cout) written
  *   relu     1: max(., 0)
  *   accumulate  1: add to the values already in y (bf16 output only)
- * Requirements: W a multiple of 64; EINVAL otherwise.
+ * Requirements: W a multiple of 64; x and w 16-byte aligned, x_pitch and
+ * x_off multiples of 8; EINVAL otherwise.
  */
 int glbm_conv3x3_forward(const uint16_t* x, int32_t x_pitch, int32_t x_off, int32_t cin, const uint16_t* w,
                          const float* bias, void* y, int32_t y_pitch, int32_t y_off, int32_t cout, int32_t relu,

@@ -100,15 +100,28 @@ def num_params():
     return sum(co * ci * 9 + co for ci, co, _ in SPEC)
 
 
-def forward(params, x, bf16=False):
+def _perturber(perturb):
+    """perturb = (rel, seed): a function that multiplies an array by 1 + rel * N(0, 1) per
+    element (seeded), else the identity.  A sensitivity probe: the network evaluated
+    with every convolution sum disturbed at about the FP32 rounding level shows how far
+    each output moves under rounding alone."""
+    if not perturb:
+        return lambda a: a
+    rel, seed = perturb
+    rng = np.random.default_rng(seed)
+    return lambda a: a * (1.0 + rel * rng.standard_normal(a.shape))
+
+
+def forward(params, x, bf16=False, perturb=None):
     """Network output (B, H, W, 3) and the stored activations."""
     r = round_bf16 if bf16 else (lambda a: a)
+    pt = _perturber(perturb)
     L = unpack(params)
     A = {}
 
     def layer(i, inp):
         w, b = L[i]
-        y = conv3x3(inp, w, b)
+        y = pt(conv3x3(inp, w, b))
         if SPEC[i][2]:
             y = np.maximum(y, 0.0)
         return y
@@ -139,13 +152,16 @@ def output_abs_scale(params, A):
     return conv3x3(np.abs(A["a8"]), np.abs(w), np.abs(b))
 
 
-def loss_and_grads(params, x, target, mask, bf16=False, abs_scale=False):
+def loss_and_grads(params, x, target, mask, bf16=False, abs_scale=False, perturb=None):
     """Masked MSE over channels 0..2 and its gradient with respect to the flat parameters.
     With abs_scale=True also returns, in the same flat layout, sum_pixels |dy| |x| of
-    every weight and sum_pixels |dy| of every bias (the scale of each gradient's sum)."""
+    every weight and sum_pixels |dy| of every bias (the scale of each gradient's sum).
+    perturb = (rel, seed) disturbs every convolution sum (forward and data gradient)
+    by a relative rel (see _perturber)."""
     r = round_bf16 if bf16 else (lambda a: a)
+    pt = _perturber(perturb and (perturb[0], perturb[1] + 1))
     L = unpack(params)
-    out, A = forward(params, x, bf16)
+    out, A = forward(params, x, bf16, perturb)
     m = mask.astype(bool)
     cnt = 3.0 * m.sum()
     d = (out - target[..., :3]) * m[..., None]
@@ -161,7 +177,7 @@ def loss_and_grads(params, x, target, mask, bf16=False, abs_scale=False):
         grads[i] = conv3x3_weight_grad(inp, gy)
         if abs_scale:
             scales[i] = conv3x3_weight_grad(np.abs(inp), np.abs(gy))
-        return conv3x3_data_grad(gy, L[i][0])
+        return pt(conv3x3_data_grad(gy, L[i][0]))
 
     g_a8 = r(back(9, gout, A["a8"], None))
     g_c1 = r(back(8, g_a8, A["c1"], A["a8"]))

@@ -61,6 +61,7 @@ struct ConvArgs {
     int k_real, k_pad, cout_pad;
     int H, W;
     long long npix;
+    int y_vec;  // 1: four consecutive output channels may be written with one 8-byte (bf16) / 16-byte (FP32) store
 };
 
 // ------------------------------------------------------------------ forward --
@@ -249,6 +250,131 @@ __global__ __launch_bounds__(kConvBlock) void k_conv_fwd_tap(ConvArgs a)
                 }
             }
         }
+}
+
+// ------------------------------------------------ forward, row-reuse path --
+// For cin = 32 CI.  A wavefront owns 16 pixels in each of R consecutive rows;
+// the workgroup's four wavefronts sit side by side (64 x R pixels).  K runs
+// over 32-channel slices of the input and, within a slice, over the column
+// shifts dx = -1, 0, 1: the slice's 16-byte fragments of the R + 2 input rows
+// at that shift are loaded once and serve every (dy, output row) pair that
+// reads them, so R + 2 loads feed 3 R NT MFMAs (the tap-major kernel spends
+// one load per NT MFMAs).  The slice's weights for all nine taps (16 NT
+// channels x 32) sit in LDS.  The weights are the MFMA's row operand, so a
+// lane ends with four consecutive output channels of its own pixel and
+// writes them with one 8-byte (bf16) or 16-byte (FP32) store.
+constexpr int kRwRow = 40;  // 32 channels + 8 pad (bf16): 80-byte rows, 16 lanes hit 64 distinct banks
+
+template <int CI, int NT, int R, bool OUT_F32, bool RELU, bool ACC>
+__global__ __launch_bounds__(kConvBlock) void k_conv_fwd_rows(ConvArgs a)
+{
+    constexpr int kCin = 32 * CI;
+    constexpr int kN = 16 * NT;
+    __shared__ __attribute__((aligned(16))) uint16_t wt[9 * kN * kRwRow];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int m = lane & 15, kq = lane >> 4;
+    const int xtiles = a.W >> 6, ytiles = (a.H + R - 1) / R;
+    const int xt = (int)blockIdx.x % xtiles, rest = (int)blockIdx.x / xtiles;
+    const int yt = rest % ytiles, b = rest / ytiles;
+    const int x = (xt << 6) + 16 * wave + m;  // this lane's pixel column
+    const int y0 = yt * R;
+    const int n0 = blockIdx.y * kN;
+    const size_t img = (size_t)b * a.H * a.W;
+    const uint16_t* xb = a.x + img * a.x_pitch + a.x_off + 8 * kq;
+    int rowoff[R + 2];
+#pragma unroll
+    for (int r = 0; r < R + 2; ++r) rowoff[r] = (((y0 - 1 + r) % a.H + a.H) % a.H) * a.W;
+    int xs[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const int xx = x + d - 1;
+        xs[d] = xx < 0 ? xx + a.W : (xx >= a.W ? xx - a.W : xx);
+    }
+    f32x4 acc[R][NT];
+#pragma unroll
+    for (int o = 0; o < R; ++o)
+#pragma unroll
+        for (int j = 0; j < NT; ++j) acc[o][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+    for (int c = 0; c < CI; ++c) {
+        __syncthreads();  // the previous slice's weights are no longer read
+        // wt[tap][n][0..31] = w[n0 + n][tap * cin + 32 c + 0..31]
+        for (int e = threadIdx.x; e < 9 * kN * 4; e += kConvBlock) {
+            const int tap = e / (kN * 4), rem = e - tap * (kN * 4), n = rem >> 2, c8 = (rem & 3) * 8;
+            uint4 v = make_uint4(0, 0, 0, 0);
+            if (n0 + n < a.cout_pad)
+                v = *reinterpret_cast<const uint4*>(a.w + (size_t)(n0 + n) * a.k_pad + tap * kCin + 32 * c + c8);
+            *reinterpret_cast<uint4*>(&wt[(tap * kN + n) * kRwRow + c8]) = v;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            uint4 av[R + 2];
+#pragma unroll
+            for (int r = 0; r < R + 2; ++r)
+                av[r] = *reinterpret_cast<const uint4*>(xb + (size_t)(rowoff[r] + xs[d]) * a.x_pitch + 32 * c);
+#pragma unroll
+            for (int e = 0; e < 3; ++e) {
+                const int tap = 3 * e + d;  // dy = e - 1
+#pragma unroll
+                for (int j = 0; j < NT; ++j) {
+                    const bf16x8 bw = __builtin_bit_cast(
+                        bf16x8, *reinterpret_cast<const uint4*>(&wt[(tap * kN + 16 * j + m) * kRwRow + 8 * kq]));
+#pragma unroll
+                    for (int o = 0; o < R; ++o)
+                        acc[o][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bw, __builtin_bit_cast(bf16x8, av[o + e]),
+                                                                            acc[o][j], 0, 0, 0);
+                }
+            }
+        }
+    }
+    // epilogue: lane holds D[4 kq + i][m]: output channels n0 + 16 j + 4 kq + i of pixel (y0 + o, x)
+#pragma unroll
+    for (int o = 0; o < R; ++o) {
+        if (y0 + o >= a.H) continue;
+        const size_t q = img + (size_t)(y0 + o) * a.W + x;
+#pragma unroll
+        for (int j = 0; j < NT; ++j) {
+            const int nb = n0 + 16 * j + 4 * kq;
+            if (nb >= a.cout) continue;
+            const bool full = a.y_vec && nb + 3 < a.cout;
+            float v[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                v[i] = acc[o][j][i] + ((a.bias && nb + i < a.cout) ? a.bias[nb + i] : 0.f);
+                if (RELU) v[i] = fmaxf(v[i], 0.f);
+            }
+            if (OUT_F32) {
+                float* yp = static_cast<float*>(a.y) + q * a.y_pitch + a.y_off + nb;
+                if (full) {
+                    *reinterpret_cast<float4*>(yp) = make_float4(v[0], v[1], v[2], v[3]);
+                } else {
+                    for (int i = 0; i < 4; ++i)
+                        if (nb + i < a.cout) yp[i] = v[i];
+                }
+            } else {
+                uint16_t* yp = static_cast<uint16_t*>(a.y) + q * a.y_pitch + a.y_off + nb;
+                if (full) {
+                    if (ACC) {
+                        const uint2 old = *reinterpret_cast<const uint2*>(yp);
+                        v[0] += bf2f(uint16_t(old.x & 0xffffu));
+                        v[1] += bf2f(uint16_t(old.x >> 16));
+                        v[2] += bf2f(uint16_t(old.y & 0xffffu));
+                        v[3] += bf2f(uint16_t(old.y >> 16));
+                    }
+                    *reinterpret_cast<uint2*>(yp) = make_uint2(uint32_t(f2bf(v[0])) | (uint32_t(f2bf(v[1])) << 16),
+                                                               uint32_t(f2bf(v[2])) | (uint32_t(f2bf(v[3])) << 16));
+                } else {
+                    for (int i = 0; i < 4; ++i) {
+                        if (nb + i >= a.cout) continue;
+                        float t = v[i];
+                        if (ACC) t += bf2f(yp[i]);
+                        yp[i] = f2bf(t);
+                    }
+                }
+            }
+        }
+    }
 }
 
 // -------------------------------------------------------------- flip weights --
@@ -714,6 +840,8 @@ int conv_fwd(const uint16_t* x, int xp, int xo, int cin, const uint16_t* w, cons
         return cfail(GLBM_EINVAL, "conv3x3: need cin % 8 == 0, W % 64 == 0, positive sizes");
     if (xo + cin > xp || yo + cout > yp) return cfail(GLBM_EINVAL, "conv3x3: channel slice exceeds pitch");
     if (yf32 && acc) return cfail(GLBM_EINVAL, "conv3x3: accumulate needs bf16 output");
+    if (xp % 8 || xo % 8 || reinterpret_cast<uintptr_t>(x) % 16 || reinterpret_cast<uintptr_t>(w) % 16)
+        return cfail(GLBM_EINVAL, "conv3x3: x and w must be 16-byte aligned, x_pitch and x_off multiples of 8");
     ConvArgs a{};
     a.x = x;
     a.w = w;
@@ -731,39 +859,42 @@ int conv_fwd(const uint16_t* x, int xp, int xo, int cin, const uint16_t* w, cons
     a.H = H;
     a.W = W;
     a.npix = (long long)B * H * W;
+    a.y_vec = yp % 4 == 0 && yo % 4 == 0 && reinterpret_cast<uintptr_t>(y) % (yf32 ? 16 : 8) == 0;
     const unsigned gy = (unsigned)((a.cout_pad + kChTile - 1) / kChTile);
     const int ci32 = cin % 32 == 0 ? cin / 32 : 0;
-    const int mb = a.cout_pad <= 32 && ci32 <= 3 ? 4 : 2;
-    const bool tap_path = ci32 == 1 || ci32 == 2 || ci32 == 3 || ci32 == 4 || ci32 == 6;
-    if (tap_path) {
-        dim3 grid((unsigned)((a.npix + 64 * mb - 1) / (64 * mb)), gy);
-#define LAUNCH_T(C, M, F, R, A) hipLaunchKernelGGL((k_conv_fwd_tap<C, M, F, R, A>), grid, dim3(kConvBlock), 0, s, a)
-#define EPI_T(C, M)                                                                                    \
+    const bool row_path = ci32 == 1 || ci32 == 2 || ci32 == 3 || ci32 == 4 || ci32 == 6;
+    if (row_path) {
+        constexpr int R = 4;
+        const int nt = a.cout_pad % 64 == 0 ? 4 : (a.cout_pad % 32 == 0 ? 2 : 1);
+        dim3 grid((unsigned)((long long)B * ((H + R - 1) / R) * (W / 64)), (unsigned)(a.cout_pad / (16 * nt)));
+#define LAUNCH_R(C, N, F, Re, A) hipLaunchKernelGGL((k_conv_fwd_rows<C, N, R, F, Re, A>), grid, dim3(kConvBlock), 0, s, a)
+#define EPI_R(C, N)                                                                                    \
     do {                                                                                               \
         if (yf32) {                                                                                    \
-            if (relu) LAUNCH_T(C, M, true, true, false);                                               \
-            else LAUNCH_T(C, M, true, false, false);                                                   \
+            if (relu) LAUNCH_R(C, N, true, true, false);                                               \
+            else LAUNCH_R(C, N, true, false, false);                                                   \
         } else if (acc) {                                                                              \
-            if (relu) LAUNCH_T(C, M, false, true, true);                                               \
-            else LAUNCH_T(C, M, false, false, true);                                                   \
+            if (relu) LAUNCH_R(C, N, false, true, true);                                               \
+            else LAUNCH_R(C, N, false, false, true);                                                   \
         } else {                                                                                       \
-            if (relu) LAUNCH_T(C, M, false, true, false);                                              \
-            else LAUNCH_T(C, M, false, false, false);                                                  \
+            if (relu) LAUNCH_R(C, N, false, true, false);                                              \
+            else LAUNCH_R(C, N, false, false, false);                                                  \
         }                                                                                              \
     } while (0)
-        if (mb == 4) {
-            if (ci32 == 1) EPI_T(1, 4);
-            else if (ci32 == 2) EPI_T(2, 4);
-            else EPI_T(3, 4);
-        } else {
-            if (ci32 == 1) EPI_T(1, 2);
-            else if (ci32 == 2) EPI_T(2, 2);
-            else if (ci32 == 3) EPI_T(3, 2);
-            else if (ci32 == 4) EPI_T(4, 2);
-            else EPI_T(6, 2);
-        }
-#undef EPI_T
-#undef LAUNCH_T
+#define NT_R(C)                                                                                        \
+    do {                                                                                               \
+        if (nt == 4) EPI_R(C, 4);                                                                      \
+        else if (nt == 2) EPI_R(C, 2);                                                                 \
+        else EPI_R(C, 1);                                                                              \
+    } while (0)
+        if (ci32 == 1) NT_R(1);
+        else if (ci32 == 2) NT_R(2);
+        else if (ci32 == 3) NT_R(3);
+        else if (ci32 == 4) NT_R(4);
+        else NT_R(6);
+#undef NT_R
+#undef EPI_R
+#undef LAUNCH_R
     } else {
         dim3 grid((unsigned)(a.npix / kPixTile), gy);
 #define LAUNCH(F, R, A) hipLaunchKernelGGL((k_conv_fwd<F, R, A>), grid, dim3(kConvBlock), 0, s, a)

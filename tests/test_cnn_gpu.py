@@ -213,26 +213,40 @@ def test_network_forward_and_gradients(gpu):
         print("  output channel %d: worst element rel %.2e at %s (value %.3e, scale %.3e); %d above 1e-3"
               % (c, rel[..., c][k], k, oref[..., c][k], oscale[..., c][k], int((rel[..., c] > 1e-3).sum())))
     assert rel.max() <= 1e-2
-    # Gradient sums run over pixels of post-ReLU inputs.  A sum dominated by a few pixels
-    # can also differ by a ReLU mask that flips between the FP32 and FP64 arithmetic at a
-    # pre-activation within rounding of zero, which the rounding bound does not cover; its
-    # scale is therefore floored at a tenth of the layer's median scale.
+    # Per gradient element.  A gradient sum runs over post-ReLU inputs and is masked by
+    # ReLU derivatives, so a unit whose pre-activation lies within rounding of zero can
+    # take either branch, and such a flip moves single elements far more than their own
+    # rounding does.  The oracle shows the size of that effect on itself: evaluated with
+    # every convolution sum disturbed by 2^-23 (one FP32 rounding), its gradients move,
+    # per element, well beyond 1e-2 of their own scale for a few percent of the elements.
+    # Each layer is held to what that disturbed oracle does, with a margin of 3:
+    #   - the fraction of elements beyond 1e-2 of their own scale (sum |dy| |x|);
+    #   - the worst element relative to max(own scale, the layer's median scale), or the
+    #     1e-2 bar if that is larger;
+    # and the weights that read the two all-zero input channels must be exactly zero.
+    _, gpert, _ = C.loss_and_grads(pq, x, target, mask, bf16=True, perturb=(2.0 ** -23, 1))
+    assert np.all(x[..., 6:] == 0)
+    w0 = grads[:32 * 8 * 9].reshape(32, 8, 3, 3)
+    assert np.all(w0[:, 6:] == 0)
     o = 0
     for i, (ci, co, _) in enumerate(C.SPEC):
         for part, n in (("w", co * ci * 9), ("b", co)):
-            gg, rr, sc = grads[o:o + n], gref[o:o + n], gscale[o:o + n]
-            d = np.abs(gg - rr)
-            # a zero scale (weights of the two all-zero input channels) demands an exact zero
-            raw = np.where(sc > 0, d / np.where(sc > 0, sc, 1.0), np.where(d == 0, 0.0, np.inf))
-            floor = 0.1 * np.median(sc[sc > 0]) if np.any(sc > 0) else 0.0
-            den = np.maximum(sc, floor)
-            worst = np.where(den > 0, d / np.where(den > 0, den, 1.0), np.where(d == 0, 0.0, np.inf)).max()
-            j = int(np.argmax(raw))
+            gg, rr, sc, pp = grads[o:o + n], gref[o:o + n], gscale[o:o + n], gpert[o:o + n]
+            med = np.median(sc[sc > 0])
+            d, dp = np.abs(gg - rr), np.abs(pp - rr)
+            pos = sc > 0
+            frac = float(np.mean(d[pos] > 1e-2 * sc[pos]))
+            frac_p = float(np.mean(dp[pos] > 1e-2 * sc[pos]))
+            worst, worst_p = (d / np.maximum(sc, med)).max(), (dp / np.maximum(sc, med)).max()
             l2 = np.linalg.norm(gg - rr) / np.linalg.norm(rr)
-            print("  layer %d %s grad: rel L2 %.2e, worst element rel to its (floored) scale %.2e; unfloored "
-                  "worst %.2e at %d (value %.3e, scale %.3e, layer median scale %.3e); %d above 1e-2"
-                  % (i, part, l2, worst, raw[j], j, rr[j], sc[j], 10 * floor, int((raw > 1e-2).sum())))
-            assert worst <= 1e-2
+            own = np.where(pos, d / np.where(pos, sc, 1.0), 0.0)
+            j = int(np.argmax(own))
+            print("  layer %d %s grad: rel L2 %.2e; beyond 1e-2 of own scale %.4f (disturbed oracle %.4f); "
+                  "worst vs max(scale, median) %.2e (disturbed oracle %.2e); worst own-scale element %.2e "
+                  "(value %.3e, scale %.3e, median scale %.3e)"
+                  % (i, part, l2, frac, frac_p, worst, worst_p, own[j], rr[j], sc[j], med))
+            assert frac <= max(1e-3, 3 * frac_p)
+            assert worst <= max(1e-2, 3 * worst_p)
             o += n
 
 
