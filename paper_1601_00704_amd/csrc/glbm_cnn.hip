@@ -329,6 +329,14 @@ __global__ __launch_bounds__(kConvBlock) void k_conv_fwd_rows(ConvArgs a)
         }
     }
     // epilogue: lane holds D[4 kq + i][m]: output channels n0 + 16 j + 4 kq + i of pixel (y0 + o, x)
+    float bias[NT][4];
+#pragma unroll
+    for (int j = 0; j < NT; ++j)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int n = n0 + 16 * j + 4 * kq + i;
+            bias[j][i] = (a.bias && n < a.cout) ? a.bias[n] : 0.f;
+        }
 #pragma unroll
     for (int o = 0; o < R; ++o) {
         if (y0 + o >= a.H) continue;
@@ -341,7 +349,7 @@ __global__ __launch_bounds__(kConvBlock) void k_conv_fwd_rows(ConvArgs a)
             float v[4];
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                v[i] = acc[o][j][i] + ((a.bias && nb + i < a.cout) ? a.bias[nb + i] : 0.f);
+                v[i] = acc[o][j][i] + bias[j][i];
                 if (RELU) v[i] = fmaxf(v[i], 0.f);
             }
             if (OUT_F32) {
@@ -431,7 +439,9 @@ __global__ __launch_bounds__(kConvBlock) void k_conv_wgrad(WgradArgs a)
     const long long pend = min(pbeg + a.split_pix, a.npix);
     // the blocks of the first K range also sum dy per channel: the bias gradient
     const bool bias = a.bpart && blockIdx.x == 0;
-    double bsum = 0.0;
+    // bias partials: each loader thread sums its own pixels of its 8 channels over the
+    // chunks (in chunk order); the 32 threads of a channel group are summed at the end
+    double bsum[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     const int HW = a.H * a.W;
     // wave tile: channels c0 + 32 (wave >> 1) .. +32, K columns k0 + 32 (wave & 1) .. +32
     const int wc = 32 * (wave >> 1), wk = 32 * (wave & 1);
@@ -497,10 +507,12 @@ __global__ __launch_bounds__(kConvBlock) void k_conv_wgrad(WgradArgs a)
             *reinterpret_cast<uint2*>(&xt[(8 * lc + i) * kWtRow + 4 * lp]) = xq;
         }
         __syncthreads();
-        if (bias && threadIdx.x < 64) {
-            // fixed order: pixels of the chunk in sequence
-#pragma unroll 8
-            for (int q = 0; q < kWgPix; ++q) bsum += double(bf2f(dyt[threadIdx.x * kWtRow + q]));
+        if (bias) {
+            const uint16_t* d0 = reinterpret_cast<const uint16_t*>(dv);
+#pragma unroll
+            for (int i = 0; i < 8; ++i)
+                bsum[i] += (double(bf2f(d0[i])) + double(bf2f(d0[8 + i]))) +
+                           (double(bf2f(d0[16 + i])) + double(bf2f(d0[24 + i])));
         }
 #pragma unroll
         for (int ks = 0; ks < kWgPix / 32; ++ks) {
@@ -518,8 +530,19 @@ __global__ __launch_bounds__(kConvBlock) void k_conv_wgrad(WgradArgs a)
             }
         }
     }
-    if (bias && threadIdx.x < 64 && c0 + threadIdx.x < a.cout)
-        a.bpart[(size_t)split * kBgradCh + c0 + threadIdx.x] = float(bsum);
+    if (bias) {
+        // red[channel][lp] reuses the dy tile (64 x 32 doubles = 16 KiB fits in 64 x kWtRow bf16)
+        double* red = reinterpret_cast<double*>(dyt);
+        __syncthreads();  // every wavefront is done with the dy tile
+#pragma unroll
+        for (int i = 0; i < 8; ++i) red[(8 * lc + i) * 32 + lp] = bsum[i];
+        __syncthreads();
+        if (threadIdx.x < 64 && c0 + threadIdx.x < a.cout) {
+            double t = 0.0;
+            for (int q = 0; q < 32; ++q) t += red[threadIdx.x * 32 + q];
+            a.bpart[(size_t)split * kBgradCh + c0 + threadIdx.x] = float(t);
+        }
+    }
     // D[4 kq + r][m]: row = output channel, column = K column
     float* out = a.part + (size_t)split * a.cout_pad * a.k_real;
 #pragma unroll
@@ -534,15 +557,29 @@ __global__ __launch_bounds__(kConvBlock) void k_conv_wgrad(WgradArgs a)
             }
 }
 
-// sum the split partials in split order; dw[co][k] for co < cout
-__global__ void k_wgrad_reduce(const float* part, int nsplit, int cout, int cout_pad, int k_real, float* dw)
+// sum the split partials; dw[co][k] for co < cout.  A workgroup covers 32
+// consecutive elements; its eight rows of 32 threads take every eighth split
+// (row r: splits r, r + 8, ...), and the eight row sums are then added in row
+// order: a fixed order for a given split count.
+constexpr int kRedCols = 32, kRedRows = 8;
+__global__ __launch_bounds__(kRedCols * kRedRows) void k_wgrad_reduce(const float* part, int nsplit, int cout,
+                                                                      int cout_pad, int k_real, float* dw)
 {
-    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= cout * k_real) return;
+    __shared__ double red[kRedRows][kRedCols];
+    const int j = threadIdx.x % kRedCols, r = threadIdx.x / kRedCols;
+    const long long idx = (long long)blockIdx.x * kRedCols + j;
+    const long long total = (long long)cout * k_real;
     const size_t stride = (size_t)cout_pad * k_real;
     double sd = 0.0;
-    for (int t = 0; t < nsplit; ++t) sd += part[(size_t)t * stride + idx];
-    dw[idx] = float(sd);
+    if (idx < total)
+        for (int t = r; t < nsplit; t += kRedRows) sd += part[(size_t)t * stride + idx];
+    red[r][j] = sd;
+    __syncthreads();
+    if (r == 0 && idx < total) {
+        double t = red[0][j];
+        for (int q = 1; q < kRedRows; ++q) t += red[q][j];
+        dw[idx] = float(t);
+    }
 }
 
 // bias gradient: the per-split channel sums written by k_conv_wgrad, reduced
@@ -972,8 +1009,8 @@ int conv_wgrad(const uint16_t* x, int xp, int xo, int cin, const uint16_t* dy, i
     dim3 grid((unsigned)((a.k_real + 63) / 64), (unsigned)((a.cout_pad + 63) / 64), (unsigned)a.nsplit);
     hipLaunchKernelGGL(k_conv_wgrad, grid, dim3(kConvBlock), 0, s, a);
     CHK(hipGetLastError());
-    hipLaunchKernelGGL(k_wgrad_reduce, dim3(nblocks((long long)cout * a.k_real)), dim3(256), 0, s, a.part, a.nsplit,
-                       cout, a.cout_pad, a.k_real, dw);
+    hipLaunchKernelGGL(k_wgrad_reduce, dim3((unsigned)(((long long)cout * a.k_real + kRedCols - 1) / kRedCols)),
+                       dim3(kRedCols * kRedRows), 0, s, a.part, a.nsplit, cout, a.cout_pad, a.k_real, dw);
     CHK(hipGetLastError());
     if (db) {
         hipLaunchKernelGGL(k_bgrad_reduce, dim3(cout), dim3(256), 0, s, a.bpart, a.nsplit, db);

@@ -730,26 +730,39 @@ __device__ __forceinline__ void sweep_staged_tile(const Args& a, const Tile& t, 
     S* __restrict__ dst = static_cast<S*>(a.buf[sel ^ 1]) + I.pop_off;
     const uint8_t* __restrict__ cls = a.cls + I.cls_off;
     // populations: plane i, staged row rr <- grid row y0 + rr - e_y(i), staged
-    // column 8 cc .. 8 cc + 7 <- grid columns x0 - 8 + 8 cc .. (wrapped)
+    // column 8 cc .. 8 cc + 7 <- grid columns x0 - 8 + 8 cc .. (wrapped).  Each
+    // staged row is one wavefront (lane = chunk cc, cc < tw / 8 + 2 <= 34), so the
+    // index arithmetic is shifts and masks; th is 1, 2 or 4.  Rows and chunks that
+    // no node of the tile reads (past the grid's last row or column) are skipped,
+    // which keeps every source index within one period of the grid.
+    const int thl = th == 4 ? 2 : (th == 2 ? 1 : 0);
     const int cpr = (tw >> 3) + 2;
-    for (int k = threadIdx.x; k < 9 * th * cpr; k += kBlock) {
-        const int i = k / (th * cpr), rem = k - i * th * cpr, rr = rem / cpr, cc = rem - rr * cpr;
-        const int ey = int((kEy9 >> (2 * i)) & 3u) - 1;
-        const int gy = (t.y0 + rr - ey + ny) % ny;
-        const int gx = (t.x0 - kStPad + 8 * cc + nx) % nx;
-        const S* p = src + (size_t)i * I.stride + (size_t)gy * nx + gx;
-        *reinterpret_cast<u32x4v*>(&sp[i][rr][8 * cc]) = *reinterpret_cast<const u32x4v*>(p);
+    for (int row = threadIdx.x >> 6; row < 9 * th; row += kBlock >> 6) {
+        const int cc = threadIdx.x & 63;
+        const int i = row >> thl, rr = row & (th - 1);
+        int gx = t.x0 - kStPad + 8 * cc;
+        if (cc < cpr && gx <= nx && t.y0 + rr < ny) {
+            int gy = t.y0 + rr - (int((kEy9 >> (2 * i)) & 3u) - 1);
+            gy += gy < 0 ? ny : (gy >= ny ? -ny : 0);
+            gx += gx < 0 ? nx : (gx >= nx ? -nx : 0);
+            const S* p = src + (size_t)i * I.stride + (size_t)gy * nx + gx;
+            *reinterpret_cast<u32x4v*>(&sp[i][rr][8 * cc]) = *reinterpret_cast<const u32x4v*>(p);
+        }
     }
     if constexpr (SS::kRho) {
-        // density rows y0 - 1 .. y0 + th, columns x0 - 8 .. x0 + tw + 7, four floats a load
+        // density rows y0 - 1 .. y0 + th, columns x0 - 8 .. x0 + tw + 7, four floats a
+        // load: two staged rows per pass of 128 lanes (cc < tw / 4 + 4 <= 68)
         const float* rp = rho_plane<STORE>(src, 9, I.stride);
         const int cpr4 = (tw >> 2) + 4;
-        for (int k = threadIdx.x; k < (th + 2) * cpr4; k += kBlock) {
-            const int rr = k / cpr4, cc = k - rr * cpr4;
-            const int gy = (t.y0 - 1 + rr + ny) % ny;
-            const int gx = (t.x0 - kStPad + 4 * cc + nx) % nx;
-            *reinterpret_cast<u32x4v*>(&srho[rr][4 * cc]) =
-                *reinterpret_cast<const u32x4v*>(rp + (size_t)gy * nx + gx);
+        for (int rr = threadIdx.x >> 7; rr < th + 2; rr += kBlock >> 7) {
+            const int cc = threadIdx.x & 127;
+            int gy = t.y0 - 1 + rr, gx = t.x0 - kStPad + 4 * cc;
+            if (cc < cpr4 && gx <= nx && gy <= ny) {
+                gy += gy < 0 ? ny : (gy >= ny ? -ny : 0);
+                gx += gx < 0 ? nx : (gx >= nx ? -nx : 0);
+                *reinterpret_cast<u32x4v*>(&srho[rr][4 * cc]) =
+                    *reinterpret_cast<const u32x4v*>(rp + (size_t)gy * nx + gx);
+            }
         }
     }
     __syncthreads();
