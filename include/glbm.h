@@ -257,10 +257,11 @@ int glbm_load_state(glbm_ctx ctx, const void* host, size_t bytes);
  *                            1 nontemporal loads of the planes without an x shift;
  *                            2 workgroups in launch order (clear: grouped per XCD);
  *                            3 per-class constants read through L1 (clear: staged
- *                            in LDS); 4 no LDS staging of the population rows in
- *                            the D2Q9 FP16 sweep (which otherwise stages them for
- *                            periodic instances with nx a multiple of 8 and tiles
- *                            of at most 256 x 4 nodes)
+ *                            in LDS); 4 LDS staging of the population and density
+ *                            rows in the D2Q9 FP16 sweep (periodic instances with
+ *                            nx a multiple of 8, tiles at most 256 nodes wide with
+ *                            1, 2 or 4 rows; ignored elsewhere).  Same results
+ *                            bit for bit under every policy.
  * Errors: GLBM_EINVAL for unknown options or values.
  */
 enum { GLBM_OPT_GRAPH = 1, GLBM_OPT_TIMING = 2, GLBM_OPT_TILE_ROWS = 3, GLBM_OPT_TILE_WIDTH = 4,

@@ -246,7 +246,7 @@ struct glbm_ctx_s {
         a.tw_log2 = tw_log2;
         a.nslot = ((1 << tw_log2) * th) / kBlock;
         a.cache = cache;
-        a.staged = (staged_ok && !(cache & 16) && tw_log2 <= 8 && (th == 1 || th == 2 || th == 4)) ? 1 : 0;
+        a.staged = (staged_ok && (cache & 16) && tw_log2 <= 8 && (th == 1 || th == 2 || th == 4)) ? 1 : 0;
         return a;
     }
 };
@@ -1163,7 +1163,7 @@ int glbm_autotune(glbm_ctx c, int32_t steps, int32_t* chosen)
         for (int th : {1, 2, 4, 8, 16}) {
             if (!tile_ok(twl, th)) continue;
             // policies with and without nontemporal stores (bit 0), and (bit 4) the
-            // plain FP16 sweep where the LDS-staged one would apply
+            // LDS-staged FP16 sweep where it applies
             for (int cache : {1, 3, 4, 5, 9, 12, 13, 15, 29, 31}) {
                 if ((cache & 16) && !(c->staged_ok && twl <= 8 && (th == 1 || th == 2 || th == 4))) continue;
                 c->cache = cache;

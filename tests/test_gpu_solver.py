@@ -237,9 +237,9 @@ def test_cache_policies_bitwise(gpu, q, store):
 @pytest.mark.parametrize("shape,tile", [((48, 64), (64, 4)), ((37, 200), (128, 2)), ((21, 256), (256, 1)),
                                         ((9, 8), (64, 4))])
 def test_staged_fp16_sweep_bitwise(gpu, store, shape, tile):
-    """The D2Q9 FP16 sweep that stages population and density rows in LDS (periodic
-    instances, nx a multiple of 8) gives the same bits as the plain FP16 sweep (cache
-    policy bit 4), including tiles wider than the grid and ragged last rows."""
+    """The D2Q9 FP16 sweep that stages population and density rows in LDS (cache policy
+    bit 4; periodic instances, nx a multiple of 8) gives the same bits as the plain FP16
+    sweep, including tiles wider than the grid and ragged last rows."""
     g = gpu
     cls, eps, k, _ = random_case(shape, seed=77)
     G = (2e-5, -1e-5, 0)
