@@ -424,7 +424,20 @@ struct WgradArgs {
     long long npix;
     int nsplit;
     long long split_pix;  // pixels per split (a multiple of kWgPix)
+    int kblocks, cblocks;  // 64-wide K and channel blocks
 };
+
+// Workgroup order of the weight gradient: the hardware deals consecutive
+// workgroups round-robin to the eight XCDs, each with its own L2.  Workgroup b
+// takes logical index xcd_order(b): XCD x gets one contiguous run of logical
+// indices, and the K blocks of one (split, channel block) are consecutive in
+// it, so the workgroups that read the same dy rows and the same input rows run
+// side by side on one XCD and share its L2.
+__device__ __forceinline__ int xcd_order(int b, int G)
+{
+    const int q = G >> 3, r = G & 7, x = b & 7, k = b >> 3;
+    return x * q + min(x, r) + k;
+}
 
 __global__ __launch_bounds__(kConvBlock) void k_conv_wgrad(WgradArgs a)
 {
@@ -432,13 +445,15 @@ __global__ __launch_bounds__(kConvBlock) void k_conv_wgrad(WgradArgs a)
     __shared__ __attribute__((aligned(16))) uint16_t xt[64 * kWtRow];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int m = lane & 15, kq = lane >> 4;
-    const int k0 = blockIdx.x * 64;   // K columns
-    const int c0 = blockIdx.y * 64;   // output channels
-    const int split = blockIdx.z;
+    const int L = xcd_order((int)blockIdx.x, (int)gridDim.x);
+    const int kb = L % a.kblocks, rest = L / a.kblocks;
+    const int k0 = kb * 64;                    // K columns
+    const int c0 = (rest % a.cblocks) * 64;    // output channels
+    const int split = rest / a.cblocks;
     const long long pbeg = (long long)split * a.split_pix;
     const long long pend = min(pbeg + a.split_pix, a.npix);
     // the blocks of the first K range also sum dy per channel: the bias gradient
-    const bool bias = a.bpart && blockIdx.x == 0;
+    const bool bias = a.bpart && kb == 0;
     // bias partials: each loader thread sums its own pixels of its 8 channels over the
     // chunks (in chunk order); the 32 threads of a channel group are summed at the end
     double bsum[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
@@ -1006,7 +1021,9 @@ int conv_wgrad(const uint16_t* x, int xp, int xo, int cin, const uint16_t* dy, i
     wgrad_split(cin, cout, a.npix, &a.nsplit, &a.split_pix);
     a.part = static_cast<float*>(ws);
     a.bpart = db ? a.part + (size_t)a.nsplit * a.cout_pad * a.k_real : nullptr;
-    dim3 grid((unsigned)((a.k_real + 63) / 64), (unsigned)((a.cout_pad + 63) / 64), (unsigned)a.nsplit);
+    a.kblocks = (a.k_real + 63) / 64;
+    a.cblocks = (a.cout_pad + 63) / 64;
+    dim3 grid((unsigned)(a.kblocks * a.cblocks * a.nsplit));
     hipLaunchKernelGGL(k_conv_wgrad, grid, dim3(kConvBlock), 0, s, a);
     CHK(hipGetLastError());
     hipLaunchKernelGGL(k_wgrad_reduce, dim3((unsigned)(((long long)cout * a.k_real + kRedCols - 1) / kRedCols)),

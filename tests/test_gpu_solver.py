@@ -142,8 +142,9 @@ def _crop_solver(g, name, store):
 
 
 @pytest.mark.parametrize("name,store,tol,must_converge", [
-    ("shale4096_crop512_oracle", "f32loc", 1e-5, True),
-    ("shale4096_crop512_oracle", "f32", 1e-5, False),
+    ("shale4096_crop512_oracle", "f64", 1e-10, True),
+    ("shale4096_crop512_oracle", "f32loc", 3e-4, True),
+    ("shale4096_crop512_oracle", "f32", 3e-4, True),
     ("shale4096_crop512_oracle", "f16loc", 1e-3, False),
     ("shale3d_crop64_oracle", "f32", 1e-5, True),
     ("shale3d_crop64_oracle", "f32loc", 1e-5, True),
@@ -153,9 +154,14 @@ def test_crop_converged_permeability(gpu, name, store, tol, must_converge):
     """Converged k on crops of the benchmark maps against the oracle's converged k
     (512^2 crop of the 4096^2 map to r <= 1e-8; 64^3 crop of the 256^3 map, walls on
     the x/y faces and drive along z, to r <= 1e-7).  The solve runs with the oracle's
-    tolerance and a budget of three times the oracle's steps; stores whose rounding
-    floor lies above the tolerance (FP16 storage; plain F32 on the 2-D map) end at the
-    budget, and their k is still compared."""
+    tolerance and a budget of three times the oracle's steps; FP16 storage, whose
+    residual floor lies above the tolerance, ends at the budget and its k is still
+    compared.  FP64 stops at the oracle's step with the oracle's k.  On the 512^2 crop
+    the FP32 stores are held to 3e-4: there r <= 1e-8 is not yet the fixed point (the
+    FP64 k still moves by 1.3e-4 on the way to r <= 1e-10, so a solve stopping a few
+    checks earlier or later lands elsewhere on that path), and FP32 storage of the
+    populations shifts the fixed point itself by about 1.6e-4 (F32LOC), through the
+    rounding of parts dominated by the density gradient in the tight matrix."""
     if not os.path.exists(os.path.join(GOLDEN, name + ".json")):
         pytest.skip("golden %s not written" % name)
     print("case %s store %s" % (name, store), flush=True)
