@@ -478,34 +478,58 @@ __global__ __launch_bounds__(kConvBlock) void k_conv_wgrad(WgradArgs a)
         ci = k - tap * a.cin;
     }
     const int ty = tap / 3 - 1, tx = tap % 3 - 1;
+    // this loader's first pixel of the chunk and its image coordinates, advanced by
+    // one chunk per iteration (W is a multiple of 64, so the four pixels 4 lp ..
+    // 4 lp + 3 never straddle a row)
+    int b, py, px;
+    {
+        const long long p0 = pbeg + 4 * lp;
+        const long long pc = p0 < a.npix ? p0 : 0;
+        b = int(pc / HW);
+        const int rem = int(pc - (long long)b * HW);
+        py = rem / a.W;
+        px = rem - py * a.W;
+    }
     for (long long pb = pbeg; pb < pend; pb += kWgPix) {
         uint4 dv[4], xv[4];
+        const long long p = pb + 4 * lp;
+        int yy = py + ty;
+        yy += yy < 0 ? a.H : (yy >= a.H ? -a.H : 0);
+        const size_t row = (size_t)b * HW + (size_t)yy * a.W;
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-            const long long p = pb + 4 * lp + u;
             dv[u] = make_uint4(0, 0, 0, 0);
             xv[u] = make_uint4(0, 0, 0, 0);
-            if (p < pend) {
+            if (p + u < pend) {
                 if (co < a.cout) {
-                    const uint16_t* src = a.dy + (size_t)p * a.dy_pitch + a.dy_off + co;
+                    const uint16_t* src = a.dy + (size_t)(p + u) * a.dy_pitch + a.dy_off + co;
                     if (co + 8 <= a.cout) {
                         dv[u] = *reinterpret_cast<const uint4*>(src);
                     } else {
-                        uint16_t t[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-                        for (int i = 0; i < a.cout - co; ++i) t[i] = src[i];
-                        memcpy(&dv[u], t, 16);
+                        // the last group of a channel count that is not a multiple of 8
+                        const int nv = a.cout - co;
+                        uint32_t w[4];
+#pragma unroll
+                        for (int h = 0; h < 4; ++h) {
+                            const uint32_t lo = 2 * h < nv ? src[2 * h] : 0u, hi = 2 * h + 1 < nv ? src[2 * h + 1] : 0u;
+                            w[h] = lo | (hi << 16);
+                        }
+                        dv[u] = make_uint4(w[0], w[1], w[2], w[3]);
                     }
                 }
                 if (k < a.k_real) {
-                    const int b = int(p / HW);
-                    const int rem = int(p - (long long)b * HW);
-                    const int py = rem / a.W, px = rem - py * a.W;
-                    int yy = py + ty, xx = px + tx;
-                    yy += yy < 0 ? a.H : (yy >= a.H ? -a.H : 0);
+                    int xx = px + u + tx;
                     xx += xx < 0 ? a.W : (xx >= a.W ? -a.W : 0);
-                    xv[u] = *reinterpret_cast<const uint4*>(a.x + ((size_t)b * HW + yy * a.W + xx) * a.x_pitch +
-                                                            a.x_off + ci);
+                    xv[u] = *reinterpret_cast<const uint4*>(a.x + (row + xx) * a.x_pitch + a.x_off + ci);
                 }
+            }
+        }
+        px += kWgPix;
+        while (px >= a.W) {
+            px -= a.W;
+            if (++py == a.H) {
+                py = 0;
+                ++b;
             }
         }
         __syncthreads();
