@@ -127,13 +127,15 @@ size_t glbm_required_bytes(int32_t n_inst, const glbm_instance_desc* desc);
  *               (x fastest); class 255 is a wall node, every other class
  *               must be given a table entry by glbm_set_local_perm
  *   pop_dev     device buffer of at least glbm_required_bytes() bytes owned
- *               by the caller, or NULL to let the library allocate it
+ *               by the caller (256-byte aligned), or NULL to let the library
+ *               allocate it
  *   pop_bytes   size of pop_dev (ignored when pop_dev is NULL)
  *   hip_stream  hipStream_t for all work of the context (NULL: null stream)
  * The populations start at rest, f_i = w_i (rho = 1, u = 0) — the paper
  * leaves the initial state open.
  * Errors: GLBM_EINVAL (n_inst < 1, empty grid, tau <= 1/2, mixed lattice /
- * store / check_every, nz != 1 for D2Q9, odd check_every, scale outside
+ * store / check_every, nz != 1 for D2Q9, odd check_every, pop_dev not
+ * 256-byte aligned, scale outside
  * [0, 30], a wall face without its opposite face, unknown flag bits,
  * GLBM_STORE_F16DEV without GLBM_FLAG_F16DEV_OPT_IN); GLBM_ENOMEM; GLBM_EDEVICE.
  */
@@ -260,8 +262,12 @@ int glbm_load_state(glbm_ctx ctx, const void* host, size_t bytes);
  *                            in LDS); 4 LDS staging of the population and density
  *                            rows in the D2Q9 FP16 sweep (periodic instances with
  *                            nx a multiple of 8, tiles at most 256 nodes wide with
- *                            1, 2 or 4 rows; ignored elsewhere).  Same results
- *                            bit for bit under every policy.
+ *                            1, 2 or 4 rows; ignored elsewhere); 5 two x-adjacent
+ *                            nodes per lane in the D2Q9 FP16 sweep (periodic
+ *                            instances with nx even, tiles at least 128 nodes
+ *                            wide and an even number of nodes per thread;
+ *                            ignored elsewhere and when bit 4 applies).  Same
+ *                            results bit for bit under every policy.
  * Errors: GLBM_EINVAL for unknown options or values.
  */
 enum { GLBM_OPT_GRAPH = 1, GLBM_OPT_TIMING = 2, GLBM_OPT_TILE_ROWS = 3, GLBM_OPT_TILE_WIDTH = 4,
@@ -273,7 +279,8 @@ int glbm_sweep_time(glbm_ctx ctx, double* ms_total, int64_t* launches);
  * Autotuner: time every (tile width, tile rows, cache policy) candidate for
  * `steps` sweeps and keep the fastest.  Widths 64 .. 1024 (up to twice the
  * widest instance), rows 1 .. 16, cache policies 1, 3, 4, 5, 9, 12, 13, 15
- * (and 29, 31 where the LDS-staged FP16 sweep applies).
+ * (and 29, 31 where the LDS-staged FP16 sweep applies, 37, 45, 47 where the
+ * paired-node FP16 sweep does).
  * The state advances by those sweeps (an even number per candidate); the
  * residual snapshot is reset.  If chosen is not NULL it receives {width,
  * rows, cache}.  Errors: GLBM_EINVAL for a null context or odd or < 2 steps;

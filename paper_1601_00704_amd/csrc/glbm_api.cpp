@@ -215,6 +215,7 @@ struct glbm_ctx_s {
     int th = 4;        // tile height
     int cache = 13;    // memory policy, see Args::cache (nontemporal stores, plain order, L1 table)
     bool staged_ok = false;  // D2Q9 FP16 store, periodic, every nx a multiple of 8: k_sweep9h applies
+    bool paired_ok = false;  // D2Q9 FP16 store, periodic, every nx even: k_sweep9p applies
     int ntiles = 0;
     bool use_graph = true;
     hipGraphExec_t graph = nullptr;
@@ -247,6 +248,7 @@ struct glbm_ctx_s {
         a.nslot = ((1 << tw_log2) * th) / kBlock;
         a.cache = cache;
         a.staged = (staged_ok && (cache & 16) && tw_log2 <= 8 && (th == 1 || th == 2 || th == 4)) ? 1 : 0;
+        a.paired = (paired_ok && !a.staged && (cache & 32) && tw_log2 >= 7 && a.nslot % 2 == 0) ? 1 : 0;
         return a;
     }
 };
@@ -487,6 +489,8 @@ int glbm_init_geometry(glbm_ctx* out, int32_t n_inst, const glbm_instance_desc* 
     const size_t need = glbm_required_bytes(n_inst, desc);
     if (pop_dev && pop_bytes < need)
         return fail(GLBM_ENOMEM, "population buffer too small: %zu < %zu bytes", pop_bytes, need);
+    if (pop_dev && reinterpret_cast<uintptr_t>(pop_dev) % 256)
+        return fail(GLBM_EINVAL, "population buffer must be 256-byte aligned");
 
     glbm_ctx c = new (std::nothrow) glbm_ctx_s();
     if (!c) return fail(GLBM_ENOMEM, "host allocation failed");
@@ -578,6 +582,10 @@ int glbm_init_geometry(glbm_ctx* out, int32_t n_inst, const glbm_instance_desc* 
                    (c->cfg.store == GLBM_STORE_F16DEV || c->cfg.store == GLBM_STORE_F16LOC);
     for (int i = 0; i < n_inst; ++i)
         if (desc[i].nx % 8) c->staged_ok = false;
+    c->paired_ok = c->cfg.q == GLBM_D2Q9 && c->cfg.bc == 0 &&
+                   (c->cfg.store == GLBM_STORE_F16DEV || c->cfg.store == GLBM_STORE_F16LOC);
+    for (int i = 0; i < n_inst; ++i)
+        if (desc[i].nx % 2) c->paired_ok = false;
     c->steps.assign(n_inst, 0);
     c->snap_step.assign(n_inst, 0);
     c->active_h.assign(n_inst, 1);
@@ -1126,7 +1134,7 @@ int glbm_set_option(glbm_ctx c, int32_t option, int64_t value)
         return build_tiles(c);
     }
     case GLBM_OPT_CACHE:
-        if (value < 0 || value > 31) return fail(GLBM_EINVAL, "memory policy must be in [0, 31]");
+        if (value < 0 || value > 63) return fail(GLBM_EINVAL, "memory policy must be in [0, 63]");
         c->cache = (int)value;
         free_graph(c);
         return GLBM_OK;
@@ -1162,10 +1170,12 @@ int glbm_autotune(glbm_ctx c, int32_t steps, int32_t* chosen)
         if (twl > 6 && (1 << twl) > 2 * max_nx) break;
         for (int th : {1, 2, 4, 8, 16}) {
             if (!tile_ok(twl, th)) continue;
-            // policies with and without nontemporal stores (bit 0), and (bit 4) the
-            // LDS-staged FP16 sweep where it applies
-            for (int cache : {1, 3, 4, 5, 9, 12, 13, 15, 29, 31}) {
+            // policies with and without nontemporal stores (bit 0), and the FP16
+            // sweeps with LDS-staged rows (bit 4) and with node pairs (bit 5)
+            // where they apply
+            for (int cache : {1, 3, 4, 5, 9, 12, 13, 15, 29, 31, 37, 45, 47}) {
                 if ((cache & 16) && !(c->staged_ok && twl <= 8 && (th == 1 || th == 2 || th == 4))) continue;
+                if ((cache & 32) && !(c->paired_ok && twl >= 7 && (((1 << twl) * th / kBlock) % 2) == 0)) continue;
                 c->cache = cache;
                 rc = glbm_set_option(c, GLBM_OPT_TILE_WIDTH, 1 << twl);
                 if (!rc) rc = glbm_set_option(c, GLBM_OPT_TILE_ROWS, th);

@@ -103,6 +103,7 @@ struct Args {
     int32_t nslot;         // tile nodes / kBlock: nodes each thread visits
     int32_t cache;         // bit 0: nontemporal population stores; bit 1: nontemporal loads of x-aligned planes
     int32_t staged;        // D2Q9 FP16 sweep with LDS-staged rows (k_sweep9h)
+    int32_t paired;        // D2Q9 FP16 sweep with two x-adjacent nodes per lane (k_sweep9p)
 };
 
 // Kernel configuration of a context.

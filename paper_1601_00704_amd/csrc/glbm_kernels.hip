@@ -518,25 +518,27 @@ __device__ __forceinline__ void load_table(T* lds, const Args& a, int inst)
 // forcing of Eq. 31) and write its q post-collision values (and, for a kRho
 // store, its density) to the other buffer.  d and r hold what gather()
 // returned for the node; ct is its row of the class table.
-template <int Q, int STORE, int BC, bool FORCH, bool NTS>
-__device__ __forceinline__ void collide_store(typename St<STORE>::T (&d)[Q], typename St<STORE>::T (&r)[Q], int n,
-                                              const typename St<STORE>::T* ct, const InstDev& I,
-                                              const typename St<STORE>::T (&g)[3], typename St<STORE>::T omega,
-                                              typename St<STORE>::T cforce, typename St<STORE>::S* __restrict__ dst)
+// The collision of one node: d (and r) as gather() returned them become the
+// node's q post-collision values in the store's form; for a kRho store the
+// return value is the node's density deviation (what its density plane
+// receives), otherwise 0.
+template <int Q, int STORE, int BC, bool FORCH>
+__device__ __forceinline__ typename St<STORE>::T collide_node(typename St<STORE>::T (&d)[Q],
+                                                              typename St<STORE>::T (&r)[Q],
+                                                              const typename St<STORE>::T* ct, const InstDev& I,
+                                                              const typename St<STORE>::T (&g)[3],
+                                                              typename St<STORE>::T omega, typename St<STORE>::T cforce)
 {
     using SS = St<STORE>;
     using T = typename SS::T;
     Node<Q, T, FORCH, pressure_faces(BC)> s;
+    T dr = T(0);
     if constexpr (SS::kRho) {
         // local form; collision conserves mass, so the node writes its
         // density and the parts relative to it
-        const T dr = localize<Q, T>(d, r);
+        dr = localize<Q, T>(d, r);
         s.moments_with(d, dr, ct, g, I);
         relax<Q, T, true>(d, s, ct, omega, cforce);
-        if constexpr (node_blocks(STORE))
-            rho_plane<STORE>(dst, Q, I.stride)[n] = dr;
-        else
-            *elem(rho_plane<STORE>(dst, Q, I.stride), uint32_t(n)) = dr;
     } else if constexpr (STORE == GLBM_STORE_F32) {
         // FP32 deviations d_i = f_i - w_i collide in the local form: the
         // node's own density part w_i drho is split off with a fused
@@ -558,6 +560,23 @@ __device__ __forceinline__ void collide_store(typename St<STORE>::T (&d)[Q], typ
     } else {
         s.moments(d, ct, g, I);
         relax<Q, T, false>(d, s, ct, omega, cforce);
+    }
+    return dr;
+}
+
+template <int Q, int STORE, int BC, bool FORCH, bool NTS>
+__device__ __forceinline__ void collide_store(typename St<STORE>::T (&d)[Q], typename St<STORE>::T (&r)[Q], int n,
+                                              const typename St<STORE>::T* ct, const InstDev& I,
+                                              const typename St<STORE>::T (&g)[3], typename St<STORE>::T omega,
+                                              typename St<STORE>::T cforce, typename St<STORE>::S* __restrict__ dst)
+{
+    using SS = St<STORE>;
+    const typename SS::T dr = collide_node<Q, STORE, BC, FORCH>(d, r, ct, I, g, omega, cforce);
+    if constexpr (SS::kRho) {
+        if constexpr (node_blocks(STORE))
+            rho_plane<STORE>(dst, Q, I.stride)[n] = dr;
+        else
+            *elem(rho_plane<STORE>(dst, Q, I.stride), uint32_t(n)) = dr;
     }
     if constexpr (node_blocks(STORE)) {
         if constexpr (NTS) {
@@ -808,6 +827,155 @@ __global__ __launch_bounds__(kBlock) void k_sweep9h(Args a)
     }
     if (a.cache & 1) sweep_staged_tile<STORE, FORCH, true>(a, t, I, tb, tcols, sp, srho);
     else sweep_staged_tile<STORE, FORCH, false>(a, t, I, tb, tcols, sp, srho);
+}
+
+// ------------------------------------------------ paired-node FP16 sweep --
+// D2Q9 with an FP16 store on periodic instances whose nx is even, tiles at
+// least 128 nodes wide and a whole number of 512-node groups.  Each lane owns
+// two x-adjacent nodes (x even), so a wavefront covers 128 consecutive nodes
+// of one row.  Per plane the lane reads the pair's source values as one
+// 4-byte word; for the planes shifted along x, the value that falls outside
+// the pair (x - 1 or x + 2) is the neighbouring lane's word, fetched with a
+// DPP wavefront shift, and read from memory only at the wavefront's ends and
+// at the grid's periodic seam.  For F16LOC the three density rows a pair
+// pulls from are read as 8-byte pairs the same way (three loads serve all
+// nine directions of both nodes).  The two nodes collide exactly as in
+// k_sweep and are written back as 4-byte words (plus one 8-byte density
+// pair), so the results are bitwise equal to the plain sweep's.
+__device__ __forceinline__ uint32_t from_lane_below(uint32_t v)
+{
+    // lane l receives lane l - 1's value (lane 0 receives 0)
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x138, 0xf, 0xf, false);
+}
+__device__ __forceinline__ uint32_t from_lane_above(uint32_t v)
+{
+    // lane l receives lane l + 1's value (lane 63 receives 0)
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x130, 0xf, 0xf, false);
+}
+
+template <int STORE, bool FORCH, bool NTS>
+__device__ __forceinline__ void sweep_pair_tile(const Args& a, const Tile& t, const InstDev& I, const float* tb,
+                                                int tcols)
+{
+    using SS = St<STORE>;
+    using S = typename SS::S;
+    using T = typename SS::T;
+    using L = Lat<9>;
+    const int twl = a.tw_log2, hwl = twl - 1;  // pairs per tile row: 2^hwl
+    const int nx = I.nx, ny = I.ny;
+    const int lane = threadIdx.x & 63;
+    const int sel = (a.parity + I.par) & 1;
+    const S* __restrict__ src = static_cast<const S*>(a.buf[sel]) + I.pop_off;
+    S* __restrict__ dst = static_cast<S*>(a.buf[sel ^ 1]) + I.pop_off;
+    const uint8_t* __restrict__ cls = a.cls + I.cls_off;
+    const T g[3] = {inst_g<T>(I, 0), inst_g<T>(I, 1), inst_g<T>(I, 2)};
+    const T omega = inst_omega<T>(I), cforce = inst_cforce<T>(I);
+    for (int it = 0; it < (a.nslot >> 1); ++it) {
+        const int s = it * kBlock + threadIdx.x;
+        const int x = t.x0 + 2 * (s & ((1 << hwl) - 1)), y = t.y0 + (s >> hwl);
+        if (y >= ny) continue;  // whole wavefronts: a wavefront covers one tile row
+        const bool on = x < nx;
+        // every lane reads at a valid address (lanes past the grid's last
+        // column read its first pair and store nothing), so that the
+        // wavefront shifts below see defined values in every lane
+        const int xc = on ? x : 0;
+        const bool left_ok = lane != 0 && xc != 0;        // lane l - 1 holds x - 2, x - 1
+        const bool right_ok = lane != 63 && xc + 2 < nx;  // lane l + 1 holds x + 2, x + 3
+        const int xl = xc == 0 ? nx - 1 : xc - 1, xr = xc + 2 == nx ? 0 : xc + 2;
+        const int ym = y == 0 ? ny - 1 : y - 1, yp = y == ny - 1 ? 0 : y + 1;
+        T da[9], db[9], ra[9], rb[9];
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+            const int ex = L::ex(i), ey = L::ey(i);
+            const int sy = ey > 0 ? ym : (ey < 0 ? yp : y);
+            const S* plane = src + (size_t)i * I.stride + (size_t)sy * nx;
+            const uint32_t w = *reinterpret_cast<const uint32_t*>(plane + xc);
+            uint32_t lo = w & 0xffffu, hi = w >> 16;  // source values at xc, xc + 1
+            if (ex > 0) {
+                // node x pulls x - 1: the high half of the word below
+                uint32_t v = from_lane_below(w) >> 16;
+                if (!left_ok) v = plane[xl];
+                hi = lo;
+                lo = v;
+            } else if (ex < 0) {
+                // node x + 1 pulls x + 2: the low half of the word above
+                uint32_t v = from_lane_above(w) & 0xffffu;
+                if (!right_ok) v = plane[xr];
+                lo = hi;
+                hi = v;
+            }
+            da[i] = SS::dec(S(lo), I.inv_scale);
+            db[i] = SS::dec(S(hi), I.inv_scale);
+        }
+        if constexpr (SS::kRho) {
+            const float* rp = rho_plane<STORE>(src, 9, I.stride);
+            float rl[3], r0[3], r1[3], rr[3];  // per source row: x - 1, x, x + 1, x + 2
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                const int sy = k == 0 ? ym : (k == 1 ? y : yp);
+                const float* row = rp + (size_t)sy * nx;
+                const float2 v = *reinterpret_cast<const float2*>(row + xc);
+                uint32_t below = from_lane_below(__float_as_uint(v.y));
+                uint32_t above = from_lane_above(__float_as_uint(v.x));
+                float fl = __uint_as_float(below), fr = __uint_as_float(above);
+                if (!left_ok) fl = row[xl];
+                if (!right_ok) fr = row[xr];
+                rl[k] = fl;
+                r0[k] = v.x;
+                r1[k] = v.y;
+                rr[k] = fr;
+            }
+#pragma unroll
+            for (int i = 0; i < 9; ++i) {
+                const int ex = L::ex(i), ey = L::ey(i);
+                const int k = ey > 0 ? 0 : (ey < 0 ? 2 : 1);
+                ra[i] = ex > 0 ? rl[k] : (ex < 0 ? r1[k] : r0[k]);
+                rb[i] = ex > 0 ? r0[k] : (ex < 0 ? rr[k] : r1[k]);
+            }
+        }
+        if (!on) continue;
+        const int n = y * nx + x;
+        const uint32_t cc = *reinterpret_cast<const uint16_t*>(cls + n);
+        const T dra = collide_node<9, STORE, 0, FORCH>(da, ra, tb + (cc & 0xffu) * tcols, I, g, omega, cforce);
+        const T drb = collide_node<9, STORE, 0, FORCH>(db, rb, tb + (cc >> 8) * tcols, I, g, omega, cforce);
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+            const uint32_t v = uint32_t(SS::enc(da[i], I.scale)) | (uint32_t(SS::enc(db[i], I.scale)) << 16);
+            uint32_t* at = reinterpret_cast<uint32_t*>(dst + (size_t)i * I.stride + n);
+            if constexpr (NTS) __builtin_nontemporal_store(v, at);
+            else *at = v;
+        }
+        if constexpr (SS::kRho) {
+            typedef float f32x2 __attribute__((ext_vector_type(2)));
+            f32x2* at = reinterpret_cast<f32x2*>(rho_plane<STORE>(dst, 9, I.stride) + n);
+            const f32x2 v = {dra, drb};
+            if constexpr (NTS) __builtin_nontemporal_store(v, at);
+            else *at = v;
+        }
+    }
+}
+
+template <int STORE, bool FORCH>
+__global__ __launch_bounds__(kBlock) void k_sweep9p(Args a)
+{
+    constexpr int NT = tab_cols<0, FORCH>();
+    __shared__ float tab[kClasses * NT];
+    const int tid = (a.cache & 4) ? (int)blockIdx.x : xcd_tile(blockIdx.x, gridDim.x);
+    const Tile t = a.tiles[tid];
+    if (!a.active[t.inst]) return;
+    const InstDev& I = a.inst[t.inst];
+    const float* tb;
+    int tcols;
+    if (a.cache & 8) {
+        tb = static_cast<const float*>(a.tab) + (size_t)t.inst * kClasses * kTabW;
+        tcols = kTabW;
+    } else {
+        load_table<9, float, NT>(tab, a, t.inst);   // ends with a barrier before tab is read
+        tb = tab;
+        tcols = NT;
+    }
+    if (a.cache & 1) sweep_pair_tile<STORE, FORCH, true>(a, t, I, tb, tcols);
+    else sweep_pair_tile<STORE, FORCH, false>(a, t, I, tb, tcols);
 }
 
 // ------------------------------------------------------------ observations --
@@ -1111,6 +1279,10 @@ template <int Q, int STORE, int BC, bool FORCH> struct SweepK {
         if constexpr (Q == 9 && !node_blocks(STORE) && BC == 0) {
             if (a.staged) {
                 hipLaunchKernelGGL((k_sweep9h<STORE, FORCH>), dim3(a.ntiles), dim3(kBlock), 0, s, a);
+                return hipGetLastError();
+            }
+            if (a.paired) {
+                hipLaunchKernelGGL((k_sweep9p<STORE, FORCH>), dim3(a.ntiles), dim3(kBlock), 0, s, a);
                 return hipGetLastError();
             }
         }

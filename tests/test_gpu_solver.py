@@ -261,6 +261,30 @@ def test_staged_fp16_sweep_bitwise(gpu, store, shape, tile):
         assert r[0][0] == out[0][1][0][0]
 
 
+@pytest.mark.parametrize("store", ["f16loc", "f16dev"])
+@pytest.mark.parametrize("shape,tile,forch", [((20, 130), (128, 4), False), ((7, 512), (256, 2), True),
+                                              ((5, 258), (512, 1), False), ((3, 2), (128, 4), False),
+                                              ((64, 64), (128, 4), True), ((33, 1000), (256, 2), False)])
+def test_paired_fp16_sweep_bitwise(gpu, store, shape, tile, forch):
+    """The D2Q9 FP16 sweep with two x-adjacent nodes per lane (cache policy bit 5;
+    periodic instances with nx even) gives the same bits as the plain FP16 sweep: pairs
+    at the grid's periodic seam, at wavefront ends, in tiles wider than the grid and in
+    ragged last rows, with and without Forchheimer classes."""
+    g = gpu
+    cls, eps, k, fe = random_case(shape, seed=91)
+    G = (2e-5, -1e-5, 0)
+    out = []
+    for cache in (13, 45, 47, 37):
+        print("case store=%s shape=%s tile=%s forch=%d cache=%d" % (store, shape, tile, forch, cache), flush=True)
+        s = gpu_solver(g, 9, cls, eps, k, f_eps=fe if forch else None, G=G, store=store, tile=tile, cache=cache)
+        s.step(150)
+        out.append((s.populations(), s.residual()))
+        s.close()
+    for p, r in out[1:]:
+        assert np.array_equal(p, out[0][0])
+        assert r[0][0] == out[0][1][0][0]
+
+
 def test_batch_per_instance_convergence(gpu):
     """Instances stop individually at their own first check with r <= tol."""
     g = gpu
