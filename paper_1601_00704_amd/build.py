@@ -17,11 +17,14 @@ ARCH = "gfx950"
 SOURCES = ["glbm_kernels.hip", "glbm_api.cpp", "glbm_physics.cpp", "glbm_cnn.hip", "glbm_gmm.hip"]
 
 # Packed-FP32 instructions are kept out of every code object; plain float code
-# otherwise compiles to them at -O3.
+# otherwise compiles to them at -O3.  Multiply-adds are fused only within one
+# expression (-ffp-contract=on, not the default "fast"), so that the same
+# arithmetic inlined into different kernels (the sweep variants that the cache
+# policy selects) rounds the same way and gives the same bits.
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-I" + os.path.join(ROOT, "include"), "-I" + CSRC,
           "-Wall", "-Wno-unused-function"]
 DEVICE = ["-x", "hip", "--offload-arch=" + ARCH, "-Xclang", "-target-feature", "-Xclang",
-          "-packed-fp32-ops"]
+          "-packed-fp32-ops", "-ffp-contract=on"]
 
 
 def _compile(src: str, obj: str) -> None:

@@ -883,47 +883,79 @@ __device__ __forceinline__ void sweep_pair_tile(const Args& a, const Tile& t, co
         const bool right_ok = lane != 63 && xc + 2 < nx;  // lane l + 1 holds x + 2, x + 3
         const int xl = xc == 0 ? nx - 1 : xc - 1, xr = xc + 2 == nx ? 0 : xc + 2;
         const int ym = y == 0 ? ny - 1 : y - 1, yp = y == ny - 1 ? 0 : y + 1;
+        // all loads first (the class bytes, the words, the density pairs, and
+        // the few values past the wavefront's ends), then the wavefront
+        // shifts: no load waits on another
+        const uint32_t cc = *reinterpret_cast<const uint16_t*>(cls + (y * nx + xc));
+        const S* plane[9];
+        uint32_t w[9], el[9], er[9];
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+            const int ey = L::ey(i);
+            const int sy = ey > 0 ? ym : (ey < 0 ? yp : y);
+            plane[i] = src + (size_t)i * I.stride + (size_t)sy * nx;
+            w[i] = *reinterpret_cast<const uint32_t*>(plane[i] + xc);  // source values at xc, xc + 1
+            el[i] = 0u;
+            er[i] = 0u;
+        }
+        const float* rrow[3];
+        float2 rv[3];
+        float fl[3] = {0.f, 0.f, 0.f}, fr[3] = {0.f, 0.f, 0.f};
+        if constexpr (SS::kRho) {
+            const float* rp = rho_plane<STORE>(src, 9, I.stride);
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                rrow[k] = rp + (size_t)(k == 0 ? ym : (k == 1 ? y : yp)) * nx;
+                rv[k] = *reinterpret_cast<const float2*>(rrow[k] + xc);
+            }
+        }
+        if (!left_ok) {
+#pragma unroll
+            for (int i = 0; i < 9; ++i)
+                if (L::ex(i) > 0) el[i] = plane[i][xl];
+            if constexpr (SS::kRho) {
+#pragma unroll
+                for (int k = 0; k < 3; ++k) fl[k] = rrow[k][xl];
+            }
+        }
+        if (!right_ok) {
+#pragma unroll
+            for (int i = 0; i < 9; ++i)
+                if (L::ex(i) < 0) er[i] = plane[i][xr];
+            if constexpr (SS::kRho) {
+#pragma unroll
+                for (int k = 0; k < 3; ++k) fr[k] = rrow[k][xr];
+            }
+        }
         T da[9], db[9], ra[9], rb[9];
 #pragma unroll
         for (int i = 0; i < 9; ++i) {
-            const int ex = L::ex(i), ey = L::ey(i);
-            const int sy = ey > 0 ? ym : (ey < 0 ? yp : y);
-            const S* plane = src + (size_t)i * I.stride + (size_t)sy * nx;
-            const uint32_t w = *reinterpret_cast<const uint32_t*>(plane + xc);
-            uint32_t lo = w & 0xffffu, hi = w >> 16;  // source values at xc, xc + 1
+            const int ex = L::ex(i);
+            uint32_t lo = w[i] & 0xffffu, hi = w[i] >> 16;
             if (ex > 0) {
                 // node x pulls x - 1: the high half of the word below
-                uint32_t v = from_lane_below(w) >> 16;
-                if (!left_ok) v = plane[xl];
+                const uint32_t v = from_lane_below(w[i]) >> 16;
                 hi = lo;
-                lo = v;
+                lo = left_ok ? v : el[i];
             } else if (ex < 0) {
                 // node x + 1 pulls x + 2: the low half of the word above
-                uint32_t v = from_lane_above(w) & 0xffffu;
-                if (!right_ok) v = plane[xr];
+                const uint32_t v = from_lane_above(w[i]) & 0xffffu;
                 lo = hi;
-                hi = v;
+                hi = right_ok ? v : er[i];
             }
             da[i] = SS::dec(S(lo), I.inv_scale);
             db[i] = SS::dec(S(hi), I.inv_scale);
         }
         if constexpr (SS::kRho) {
-            const float* rp = rho_plane<STORE>(src, 9, I.stride);
             float rl[3], r0[3], r1[3], rr[3];  // per source row: x - 1, x, x + 1, x + 2
 #pragma unroll
             for (int k = 0; k < 3; ++k) {
-                const int sy = k == 0 ? ym : (k == 1 ? y : yp);
-                const float* row = rp + (size_t)sy * nx;
-                const float2 v = *reinterpret_cast<const float2*>(row + xc);
-                uint32_t below = from_lane_below(__float_as_uint(v.y));
-                uint32_t above = from_lane_above(__float_as_uint(v.x));
-                float fl = __uint_as_float(below), fr = __uint_as_float(above);
-                if (!left_ok) fl = row[xl];
-                if (!right_ok) fr = row[xr];
-                rl[k] = fl;
-                r0[k] = v.x;
-                r1[k] = v.y;
-                rr[k] = fr;
+                const float below = __uint_as_float(from_lane_below(__float_as_uint(rv[k].y)));
+                const float above = __uint_as_float(from_lane_above(__float_as_uint(rv[k].x)));
+                rl[k] = left_ok ? below : fl[k];
+                r0[k] = rv[k].x;
+                r1[k] = rv[k].y;
+                rr[k] = right_ok ? above : fr[k];
             }
 #pragma unroll
             for (int i = 0; i < 9; ++i) {
@@ -935,7 +967,6 @@ __device__ __forceinline__ void sweep_pair_tile(const Args& a, const Tile& t, co
         }
         if (!on) continue;
         const int n = y * nx + x;
-        const uint32_t cc = *reinterpret_cast<const uint16_t*>(cls + n);
         const T dra = collide_node<9, STORE, 0, FORCH>(da, ra, tb + (cc & 0xffu) * tcols, I, g, omega, cforce);
         const T drb = collide_node<9, STORE, 0, FORCH>(db, rb, tb + (cc >> 8) * tcols, I, g, omega, cforce);
 #pragma unroll
