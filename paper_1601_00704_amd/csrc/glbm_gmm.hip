@@ -14,7 +14,8 @@
 //     Phi = S0 / m,  mu' = mu + S1 / S0,  var' = S2 / S0 - (S1 / S0)^2.
 // Results are deterministic and independent of the batch composition.
 // The kernel reads 8 bytes per sample and iteration and evaluates k
-// exponentials and one logarithm in FP64 per sample.
+// exponentials (k - 1 for k = 2, whose larger term is 1) and one logarithm in
+// FP64 per sample: it is bound by those, not by memory.
 #include "glbm.h"
 #include "glbm_internal.h"
 
@@ -95,12 +96,27 @@ __global__ __launch_bounds__(kGmmBlock) void k_gmm_pass(const double* __restrict
             t[j] = la[j] + nb[j] * d[j] * d[j];   // log(Phi_j g_j(x)), Eq. (21)
             mx = fmax(mx, t[j]);
         }
-        double e[K], sum = 0.0;
+        double e[K], lse;
+        if constexpr (K == 2) {
+            // the larger term is exp(0) = 1: one exponential, and the sum lies in
+            // (1, 2], where log has no cancellation to guard against
+            const double o = exp(-fabs(t[1] - t[0]));
+            const bool first = t[0] >= t[1];
+            e[0] = first ? 1.0 : o;
+            e[1] = first ? o : 1.0;
+            lse = log(1.0 + o);
+        } else {
+            double sum = 0.0;
 #pragma unroll
-        for (int j = 0; j < K; ++j) {
-            e[j] = exp(t[j] - mx);
-            sum += e[j];
+            for (int j = 0; j < K; ++j) {
+                e[j] = exp(t[j] - mx);
+                sum += e[j];
+            }
+            lse = log(sum);
         }
+        double sum = e[0];
+#pragma unroll
+        for (int j = 1; j < K; ++j) sum += e[j];
         const double inv = 1.0 / sum;
 #pragma unroll
         for (int j = 0; j < K; ++j) {
@@ -109,7 +125,7 @@ __global__ __launch_bounds__(kGmmBlock) void k_gmm_pass(const double* __restrict
             acc[3 * j + 1] += w * d[j];
             acc[3 * j + 2] += w * d[j] * d[j];
         }
-        acc[3 * K] += mx + log(sum);
+        acc[3 * K] += mx + lse;
     }
     // wavefront trees, then the four wavefronts in a fixed order
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
