@@ -383,7 +383,8 @@ int glbm_class_table_pressure(const glbm_gas_params* p, int32_t n_iom, const dou
  *   iters_done  host, n_sets (may be NULL): iterations each set ran
  * FP64 throughout; the sums are reduced in a fixed order, so results are
  * deterministic and do not depend on the other sets of the batch.  A
- * component whose responsibilities all vanish keeps its parameters.  Work is
+ * component whose responsibilities all vanish gets Phi = 0 (Eq. 22) and keeps
+ * its mean and variance (Eq. 23-24 are then 0/0).  Work is
  * queued on hip_stream (NULL: null stream) and the call synchronises it.
  * Errors: GLBM_EINVAL (bad sizes or starting point), GLBM_ENOMEM, GLBM_EDEVICE.
  */

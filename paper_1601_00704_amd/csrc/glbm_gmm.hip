@@ -173,7 +173,12 @@ __global__ __launch_bounds__(kGmmBlock) void k_gmm_update(GmmSet* sets, const do
     if (!with_update) return;
     for (int j = 0; j < k; ++j) {
         const double s0 = red[3 * j], s1 = red[3 * j + 1], s2 = red[3 * j + 2];
-        if (!(s0 > 0.0)) continue;  // an empty component keeps its parameters
+        if (!(s0 > 0.0)) {
+            // an empty component: Eq. (22) gives Phi = 0; Eq. (23)-(24) are 0/0,
+            // so its mean and variance are kept
+            if (s0 == 0.0) S.phi[j] = 0.0;
+            continue;
+        }
         const double dm = s1 / s0;
         S.phi[j] = s0 / (double)S.n;          // Eq. (22)
         S.mu[j] += dm;                        // Eq. (23)

@@ -26,6 +26,7 @@ GLBM_WALL_CLASS = 255
 GLBM_SCALE_AUTO = -2147483648
 GLBM_OPT_GRAPH, GLBM_OPT_TIMING, GLBM_OPT_TILE_ROWS, GLBM_OPT_TILE_WIDTH, GLBM_OPT_CACHE = 1, 2, 3, 4, 5
 GLBM_FLAG_F16DEV_OPT_IN = 1
+GLBM_GMM_MAX_COMPONENTS = 8
 STORE_NAMES = {"f64": GLBM_STORE_F64, "f32": GLBM_STORE_F32, "f16dev": GLBM_STORE_F16DEV,
                "f16loc": GLBM_STORE_F16LOC, "f32loc": GLBM_STORE_F32LOC}
 STORE_BYTES = {GLBM_STORE_F64: 8, GLBM_STORE_F32: 4, GLBM_STORE_F16DEV: 2, GLBM_STORE_F16LOC: 2,

@@ -97,3 +97,50 @@ def test_class_table_from_measured_pore_sizes(gpu):
         math.exp(mu[0][om]), math.exp(mu[0][iom]), math.sqrt(var[0][om]), math.sqrt(var[0][iom]), rel.max()))
     assert rel.max() < 0.08
     assert np.array_equal(eps_fit, eps_true)
+
+
+def test_gmm_vanishing_component_keeps_its_parameters(gpu):
+    """Degenerate case: a component so far from every sample that its responsibilities
+    underflow to zero.  After one iteration the other component is the plain sample
+    mean and (population) variance with Phi = 1, and the vanished one keeps its mean and
+    variance with Phi = 0; further iterations leave both unchanged."""
+    g = gpu
+    x = np.random.default_rng(5).standard_normal(10000) * 0.7 + 2.0
+    st = ([0.5, 0.5], [0.0, 1e6], [1.0, 1.0])
+    for iters in (1, 5):
+        print("case iters=%d" % iters, flush=True)
+        phi, mu, var, ll, it = _fit_gpu(g, [x], [st], iters)
+        assert it[0] == iters
+        assert phi[0][0] == 1.0 and phi[0][1] == 0.0
+        assert abs(mu[0][0] - x.mean()) <= 1e-12 * abs(x.mean())
+        assert abs(var[0][0] - x.var()) <= 1e-12 * x.var()
+        assert mu[0][1] == 1e6 and var[0][1] == 1.0
+
+
+def test_gmm_argument_errors(gpu):
+    """Empty sets, k outside 1 .. GLBM_GMM_MAX_COMPONENTS and non-positive starting
+    variances or weights are rejected before any work."""
+    import torch
+    g = gpu
+    xd = torch.zeros(16, dtype=torch.float64, device="cuda")
+    one = ([1.0], [0.0], [1.0])
+    good = np.array([0, 16], np.int64)
+    g.glbm_gmm_fit(good, xd.data_ptr(), *(np.array([v]) for v in one), 1, 0.0)
+    cases = [
+        (np.array([0, 0], np.int64), one),                                  # empty set
+        (np.array([0, 8, 8], np.int64), None),                              # empty second set
+        (good, ([1.0], [0.0], [0.0])),                                      # zero variance
+        (good, ([1.0], [0.0], [-1.0])),                                     # negative variance
+        (good, ([0.0], [0.0], [1.0])),                                      # zero weight
+    ]
+    for offs, st in cases:
+        print("case offsets=%s start=%s" % (offs.tolist(), st), flush=True)
+        n_sets = len(offs) - 1
+        st = st or one
+        arrs = [np.tile(np.array(v, np.float64), (n_sets, 1)) for v in st]
+        with pytest.raises(g.GlbmError):
+            g.glbm_gmm_fit(offs, xd.data_ptr(), *arrs, 1, 0.0)
+    k_bad = g.GLBM_GMM_MAX_COMPONENTS + 1
+    arrs = [np.full((1, k_bad), v) for v in (1.0 / k_bad, 0.0, 1.0)]
+    with pytest.raises(g.GlbmError):
+        g.glbm_gmm_fit(good, xd.data_ptr(), *arrs, 1, 0.0)
