@@ -250,7 +250,8 @@ int glbm_load_state(glbm_ctx ctx, const void* host, size_t bytes);
  *   GLBM_OPT_GRAPH (1)       replay full n_c-step chunks from a captured HIP graph
  *   GLBM_OPT_TIMING (0)      bracket every sweep launch with HIP events on the
  *                            context's stream; glbm_sweep_time reports the summed
- *                            time and the launch count since the option was set
+ *                            time and the number of sweeps since the option was
+ *                            set (a two-step launch, policy bit 6, counts as two)
  *   GLBM_OPT_TILE_WIDTH      nodes along x per workgroup tile: 64 .. 1024, a power
  *                            of two (default: 256, or the largest <= max nx)
  *   GLBM_OPT_TILE_ROWS       rows per tile, 1 .. 256; width x rows must be a
@@ -266,8 +267,13 @@ int glbm_load_state(glbm_ctx ctx, const void* host, size_t bytes);
  *                            nodes per lane in the D2Q9 FP16 sweep (periodic
  *                            instances with nx even, tiles at least 128 nodes
  *                            wide and an even number of nodes per thread;
- *                            ignored elsewhere and when bit 4 applies).  Same
- *                            results bit for bit under every policy.
+ *                            ignored elsewhere and when bit 4 applies); 6 two
+ *                            time steps per launch, the intermediate state kept
+ *                            in LDS (D2Q9, FP32 store, periodic instances, tiles
+ *                            64 x 4/8/16, 128 x 4/8 or 256 x 4, check_every a
+ *                            multiple of 4; used for whole check intervals,
+ *                            ignored elsewhere).  Same results bit for bit under
+ *                            every policy.
  * Errors: GLBM_EINVAL for unknown options or values.
  */
 enum { GLBM_OPT_GRAPH = 1, GLBM_OPT_TIMING = 2, GLBM_OPT_TILE_ROWS = 3, GLBM_OPT_TILE_WIDTH = 4,
@@ -280,7 +286,8 @@ int glbm_sweep_time(glbm_ctx ctx, double* ms_total, int64_t* launches);
  * `steps` sweeps and keep the fastest.  Widths 64 .. 1024 (up to twice the
  * widest instance), rows 1 .. 16, cache policies 1, 3, 4, 5, 9, 12, 13, 15
  * (and 29, 31 where the LDS-staged FP16 sweep applies, 37, 45, 47 where the
- * paired-node FP16 sweep does).
+ * paired-node FP16 sweep does, 77, 79 where two steps per launch do and
+ * `steps` is a multiple of 4).
  * The state advances by those sweeps (an even number per candidate); the
  * residual snapshot is reset.  If chosen is not NULL it receives {width,
  * rows, cache}.  Errors: GLBM_EINVAL for a null context or odd or < 2 steps;

@@ -224,9 +224,13 @@ struct glbm_ctx_s {
     // timing
     bool timing = false;
     std::vector<hipEvent_t> ev_pool;
+    std::vector<int> ev_steps;  // sweeps covered by each recorded event pair
     size_t ev_used = 0;
     double time_ms = 0.0;
     int64_t launches = 0;
+
+    // two steps per launch (cache policy bit 6) for whole chunks of n_c steps
+    bool tb_on() const { return (cache & 64) && n_c % 4 == 0 && tb_applies(cfg, tw_log2, th); }
 
     Args args(int parity) const
     {
@@ -352,13 +356,17 @@ int resolve_timing(glbm_ctx c)
         float ms = 0.f;
         HIPCHK(hipEventElapsedTime(&ms, c->ev_pool[k], c->ev_pool[k + 1]));
         c->time_ms += ms;
-        c->launches += 1;
+        c->launches += c->ev_steps[k / 2];
     }
     c->ev_used = 0;
+    c->ev_steps.clear();
     return GLBM_OK;
 }
 
-int sweep_once(glbm_ctx c, int parity)
+// One sweep, or with two = true one two-step launch (the caller keeps such
+// launches in pairs within a chunk, so the state returns to the buffer of its
+// step parity).
+int sweep_once(glbm_ctx c, int parity, bool two = false)
 {
     if (c->timing) {
         if (c->ev_used + 2 > c->ev_pool.size()) {
@@ -371,8 +379,10 @@ int sweep_once(glbm_ctx c, int parity)
             }
         }
         HIPCHK(hipEventRecord(c->ev_pool[c->ev_used++], c->work));
+        c->ev_steps.push_back(two ? 2 : 1);
     }
-    HIPCHK(launch_sweep(c->cfg, c->args(parity), c->work));
+    if (two) HIPCHK(launch_sweep_tb(c->cfg, c->args(parity), c->work));
+    else HIPCHK(launch_sweep(c->cfg, c->args(parity), c->work));
     if (c->timing) HIPCHK(hipEventRecord(c->ev_pool[c->ev_used++], c->work));
     return GLBM_OK;
 }
@@ -405,7 +415,11 @@ int capture_chunk(glbm_ctx c, double tol)
     hipGraph_t g = nullptr;
     HIPCHK(hipStreamBeginCapture(c->work, hipStreamCaptureModeRelaxed));
     hipError_t err = hipSuccess;
-    for (int k = 0; k < c->n_c && err == hipSuccess; ++k) err = launch_sweep(c->cfg, c->args(k), c->work);
+    if (c->tb_on()) {
+        for (int j = 0; j < c->n_c / 2 && err == hipSuccess; ++j) err = launch_sweep_tb(c->cfg, c->args(j), c->work);
+    } else {
+        for (int k = 0; k < c->n_c && err == hipSuccess; ++k) err = launch_sweep(c->cfg, c->args(k), c->work);
+    }
     if (err == hipSuccess) err = launch_observe(c->cfg, c->args(0), 3, c->work);
     if (err == hipSuccess) err = launch_finalize(c->args(0), c->n_inst, tol, 1, 1, c->work);
     hipError_t e2 = hipStreamEndCapture(c->work, &g);
@@ -836,9 +850,16 @@ int glbm_step_n(glbm_ctx c, int64_t n, double tol)
             }
             HIPCHK(hipGraphLaunch(c->graph, c->work));
         } else {
-            for (int64_t k = 0; k < len; ++k) {
-                rc = sweep_once(c, (int)((c->gstep + k) & 1));
-                if (rc) return rc;
+            if (check && len == c->n_c && c->tb_on() && (c->gstep & 1) == 0) {
+                for (int64_t j = 0; j < len / 2; ++j) {
+                    rc = sweep_once(c, (int)((c->gstep + j) & 1), true);
+                    if (rc) return rc;
+                }
+            } else {
+                for (int64_t k = 0; k < len; ++k) {
+                    rc = sweep_once(c, (int)((c->gstep + k) & 1));
+                    if (rc) return rc;
+                }
             }
             if (check) {
                 HIPCHK(launch_observe(c->cfg, c->args(c->gstep + len), 3, c->work));
@@ -1134,7 +1155,7 @@ int glbm_set_option(glbm_ctx c, int32_t option, int64_t value)
         return build_tiles(c);
     }
     case GLBM_OPT_CACHE:
-        if (value < 0 || value > 63) return fail(GLBM_EINVAL, "memory policy must be in [0, 63]");
+        if (value < 0 || value > 127) return fail(GLBM_EINVAL, "memory policy must be in [0, 127]");
         c->cache = (int)value;
         free_graph(c);
         return GLBM_OK;
@@ -1173,9 +1194,12 @@ int glbm_autotune(glbm_ctx c, int32_t steps, int32_t* chosen)
             // policies with and without nontemporal stores (bit 0), and the FP16
             // sweeps with LDS-staged rows (bit 4) and with node pairs (bit 5)
             // where they apply
-            for (int cache : {1, 3, 4, 5, 9, 12, 13, 15, 29, 31, 37, 45, 47}) {
+            for (int cache : {1, 3, 4, 5, 9, 12, 13, 15, 29, 31, 37, 45, 47, 77, 79}) {
                 if ((cache & 16) && !(c->staged_ok && twl <= 8 && (th == 1 || th == 2 || th == 4))) continue;
                 if ((cache & 32) && !(c->paired_ok && twl >= 7 && (((1 << twl) * th / kBlock) % 2) == 0)) continue;
+                // two steps per launch: whole chunks only, in launch pairs
+                const bool two = (cache & 64) != 0;
+                if (two && !(tb_applies(c->cfg, twl, th) && c->n_c % 4 == 0 && steps % 4 == 0)) continue;
                 c->cache = cache;
                 rc = glbm_set_option(c, GLBM_OPT_TILE_WIDTH, 1 << twl);
                 if (!rc) rc = glbm_set_option(c, GLBM_OPT_TILE_ROWS, th);
@@ -1184,7 +1208,12 @@ int glbm_autotune(glbm_ctx c, int32_t steps, int32_t* chosen)
                 rc = enter(c);
                 if (rc) return rc;
                 int k = 0;
-                for (; k < steps && rc == GLBM_OK; ++k) rc = sweep_once(c, (int)((c->gstep + k) & 1));
+                if (two) {
+                    for (int j = 0; j < steps / 2 && rc == GLBM_OK; ++j, k += 2)
+                        rc = sweep_once(c, (int)((c->gstep + j) & 1), true);
+                } else {
+                    for (; k < steps && rc == GLBM_OK; ++k) rc = sweep_once(c, (int)((c->gstep + k) & 1));
+                }
                 double ms = 0.0;
                 int64_t nl = 0;
                 if (!rc) rc = glbm_sweep_time(c, &ms, &nl);

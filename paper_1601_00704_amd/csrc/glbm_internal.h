@@ -116,6 +116,10 @@ struct Config {
 
 // Host launchers (glbm_kernels.hip).
 hipError_t launch_sweep(const Config& c, const Args& a, hipStream_t s);
+// two time steps per launch (D2Q9, FP32 node blocks, periodic; tiles 64 x 4/8/16,
+// 128 x 4/8, 256 x 4): reads the buffer of a.parity, writes the other one
+bool tb_applies(const Config& c, int tw_log2, int th);
+hipError_t launch_sweep_tb(const Config& c, const Args& a, hipStream_t s);
 // mode bit 0: update snapshot; bit 1: accumulate residual terms
 hipError_t launch_observe(const Config& c, const Args& a, int mode, hipStream_t s);
 // tol > 0: deactivate converged instances; with_r: compute r from S_d, S_u

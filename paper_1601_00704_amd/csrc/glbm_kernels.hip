@@ -1009,6 +1009,109 @@ __global__ __launch_bounds__(kBlock) void k_sweep9p(Args a)
     else sweep_pair_tile<STORE, FORCH, false>(a, t, I, tb, tcols);
 }
 
+// --------------------------------------------- two steps per launch (D2Q9) --
+// Temporal blocking for the node-block stores on periodic D2Q9 instances.  A
+// workgroup owns a TW x TH tile and advances it two time steps in one launch:
+//   1. every node of the tile grown by one node on each side is swept from the
+//      source buffer as in k_sweep9 (pull, collide), and its q post-collision
+//      values are kept in LDS, not written back;
+//   2. every node of the tile pulls those values from LDS, collides again and
+//      writes the result to the other buffer.
+// The nodes of the one-node rim are computed by the neighbouring tiles as
+// well (redundantly: (TW + 2)(TH + 2) / (TW TH) - 1 of the collisions), but the
+// intermediate state never travels through HBM, so one launch moves about the
+// bytes of one plain sweep for two steps.  The arithmetic is that of
+// collide_node, so the result is bitwise equal to two k_sweep9 launches.  The
+// state then sits in the buffer a single step would have written, so the
+// host issues these launches in pairs (four steps between state reads).
+template <int TW, int TH> struct TbShape {
+    static constexpr int kRW = TW + 2, kRH = TH + 2, kRegion = kRW * kRH;
+};
+
+template <int STORE, bool FORCH, bool NTS, int TW, int TH>
+__device__ __forceinline__ void sweep_tb_tile(const Args& a, const Tile& t, const InstDev& I,
+                                              const typename St<STORE>::T* __restrict__ tb, int tcols,
+                                              typename St<STORE>::T (*f1)[TbShape<TW, TH>::kRegion])
+{
+    using SS = St<STORE>;
+    using S = typename SS::S;
+    using T = typename SS::T;
+    using L = Lat<9>;
+    using Sh = TbShape<TW, TH>;
+    const int nx = I.nx, ny = I.ny;
+    const int sel = (a.parity + I.par) & 1;
+    const S* __restrict__ src = static_cast<const S*>(a.buf[sel]) + I.pop_off;
+    S* __restrict__ dst = static_cast<S*>(a.buf[sel ^ 1]) + I.pop_off;
+    const uint8_t* __restrict__ cls = a.cls + I.cls_off;
+    const T g[3] = {inst_g<T>(I, 0), inst_g<T>(I, 1), inst_g<T>(I, 2)};
+    const T omega = inst_omega<T>(I), cforce = inst_cforce<T>(I);
+    const bool nt_load = (a.cache & 2) != 0;
+    // step 1 over the grown tile (coordinates wrapped onto the periodic grid)
+    for (int e = threadIdx.x; e < Sh::kRegion; e += kBlock) {
+        const int ry = e / Sh::kRW, rx = e - ry * Sh::kRW;
+        int x = t.x0 - 1 + rx, y = t.y0 - 1 + ry;
+        x += x < 0 ? nx : 0;
+        y += y < 0 ? ny : 0;
+        if (x >= nx) x -= nx;
+        if (x >= nx) x %= nx;  // grids narrower than the tile
+        if (y >= ny) y -= ny;
+        if (y >= ny) y %= ny;
+        const int n = y * nx + x;
+        T d[9], r[9];
+        gather<9, STORE, 0>(d, r, src, cls, I, x, y, 0, n, nt_load);
+        collide_node<9, STORE, 0, FORCH>(d, r, tb + cls[n] * tcols, I, g, omega, cforce);
+#pragma unroll
+        for (int i = 0; i < 9; ++i) f1[i][e] = d[i];
+    }
+    __syncthreads();
+    // step 2 over the tile, pulling from the grown tile in LDS
+    for (int s = threadIdx.x; s < TW * TH; s += kBlock) {
+        const int ly = s / TW, lx = s - ly * TW;
+        const int x = t.x0 + lx, y = t.y0 + ly;
+        if (x >= nx || y >= ny) continue;
+        const int n = y * nx + x;
+        T d[9], r[9];
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+            d[i] = f1[i][(ly + 1 - L::ey(i)) * Sh::kRW + (lx + 1 - L::ex(i))];
+            r[i] = T(0);
+        }
+        collide_node<9, STORE, 0, FORCH>(d, r, tb + cls[n] * tcols, I, g, omega, cforce);
+        if constexpr (NTS) {
+#pragma unroll
+            for (int i = 0; i < 9; ++i) __builtin_nontemporal_store(SS::enc(d[i], I.scale), dst + pidx<9, STORE>(i, n, 0));
+        } else {
+#pragma unroll
+            for (int i = 0; i < 9; ++i) dst[pidx<9, STORE>(i, n, 0)] = SS::enc(d[i], I.scale);
+        }
+    }
+}
+
+template <int STORE, bool FORCH, int TW, int TH>
+__global__ __launch_bounds__(kBlock) void k_sweep9tb(Args a)
+{
+    using T = typename St<STORE>::T;
+    constexpr int NT = tab_cols<0, FORCH>();
+    __shared__ T tab[kClasses * NT];
+    __shared__ T f1[9][TbShape<TW, TH>::kRegion];
+    const int tid = (a.cache & 4) ? (int)blockIdx.x : xcd_tile(blockIdx.x, gridDim.x);
+    const Tile t = a.tiles[tid];
+    if (!a.active[t.inst]) return;
+    const InstDev& I = a.inst[t.inst];
+    const T* tb;
+    int tcols;
+    if (a.cache & 8) {
+        tb = static_cast<const T*>(a.tab) + (size_t)t.inst * kClasses * kTabW;
+        tcols = kTabW;
+    } else {
+        load_table<9, T, NT>(tab, a, t.inst);   // ends with a barrier before tab is read
+        tb = tab;
+        tcols = NT;
+    }
+    if (a.cache & 1) sweep_tb_tile<STORE, FORCH, true, TW, TH>(a, t, I, tb, tcols, f1);
+    else sweep_tb_tile<STORE, FORCH, false, TW, TH>(a, t, I, tb, tcols, f1);
+}
+
 // ------------------------------------------------------------ observations --
 __device__ __forceinline__ double wave_sum(double v)
 {
@@ -1375,6 +1478,32 @@ hipError_t launch_sweep(const Config& c, const Args& a, hipStream_t s)
 {
     if (a.ntiles <= 0) return hipSuccess;
     return dispatch<SweepK>(c, a, s);
+}
+
+bool tb_applies(const Config& c, int tw_log2, int th)
+{
+    if (c.q != 9 || c.bc != 0 || c.store != GLBM_STORE_F32) return false;
+    const int tw = 1 << tw_log2;
+    return (tw == 64 && (th == 4 || th == 8 || th == 16)) || (tw == 128 && (th == 4 || th == 8)) ||
+           (tw == 256 && th == 4);
+}
+
+hipError_t launch_sweep_tb(const Config& c, const Args& a, hipStream_t s)
+{
+    if (a.ntiles <= 0) return hipSuccess;
+    const int tw = 1 << a.tw_log2, th = (a.nslot * kBlock) >> a.tw_log2;
+    if (!tb_applies(c, a.tw_log2, th)) return hipErrorInvalidValue;
+#define GLBM_TB(W, H)                                                                                          \
+    if (tw == W && th == H) {                                                                                  \
+        if (c.forch)                                                                                           \
+            hipLaunchKernelGGL((k_sweep9tb<GLBM_STORE_F32, true, W, H>), dim3(a.ntiles), dim3(kBlock), 0, s, a); \
+        else                                                                                                   \
+            hipLaunchKernelGGL((k_sweep9tb<GLBM_STORE_F32, false, W, H>), dim3(a.ntiles), dim3(kBlock), 0, s, a); \
+        return hipGetLastError();                                                                              \
+    }
+    GLBM_TB(64, 4) GLBM_TB(64, 8) GLBM_TB(64, 16) GLBM_TB(128, 4) GLBM_TB(128, 8) GLBM_TB(256, 4)
+#undef GLBM_TB
+    return hipErrorInvalidValue;
 }
 
 hipError_t launch_observe(const Config& c, const Args& a, int mode, hipStream_t s)

@@ -285,6 +285,40 @@ def test_paired_fp16_sweep_bitwise(gpu, store, shape, tile, forch):
         assert r[0][0] == out[0][1][0][0]
 
 
+@pytest.mark.parametrize("timing", [False, True])
+@pytest.mark.parametrize("shape,tile,forch", [((48, 200), (64, 4), False), ((40, 130), (128, 8), True),
+                                              ((21, 256), (256, 4), False), ((20, 50), (64, 16), False),
+                                              ((3, 130), (128, 4), True), ((64, 64), (64, 8), False)])
+def test_two_step_sweep_bitwise(gpu, shape, tile, forch, timing):
+    """Two time steps per launch with the intermediate state in LDS (cache policy bit
+    6; D2Q9 FP32, periodic) gives the same bits as one step per launch, over whole
+    check intervals (graph replay, or eager launches with timing on), including tiles
+    wider or taller than the grid; a check interval that is not a multiple of 4 falls
+    back to single steps."""
+    g = gpu
+    cls, eps, k, fe = random_case(shape, seed=123)
+    G = (2e-5, -1e-5, 0)
+    out = []
+    for cache, every in ((13, 100), (77, 100), (79, 100), (13, 102), (77, 102)):
+        print("case shape=%s tile=%s forch=%d timing=%d cache=%d every=%d" % (shape, tile, forch, timing, cache,
+                                                                           every), flush=True)
+        s = gpu_solver(g, 9, cls, eps, k, f_eps=fe if forch else None, G=G, store="f32", tile=tile, cache=cache,
+                       check_every=every)
+        if timing:
+            s.set_option(g.GLBM_OPT_TIMING, 1)
+        s.step(2 * every)
+        p = s.populations()
+        r, st = s.residual()
+        if timing:
+            ms, nl = g.glbm_sweep_time(s.ctx)
+            assert nl == 2 * every
+        s.close()
+        out.append((p, r[0], st[0], every))
+    for a, b in ((0, 1), (0, 2), (3, 4)):
+        assert np.array_equal(out[a][0], out[b][0])
+        assert out[a][1] == out[b][1] and out[a][2] == out[b][2]
+
+
 def test_batch_per_instance_convergence(gpu):
     """Instances stop individually at their own first check with r <= tol."""
     g = gpu
