@@ -154,7 +154,11 @@ def pmc_summary(fetch_dir, write_dir, cfetch_dir, cwrite_dir, args):
     import paper_1601_00704_amd.glbm as g
     key, q, n = workload_key(args)
     bpl = g.bytes_per_update(q, g.STORE_NAMES[args.store])
-    rec = {"kernel": "%s, %s, %d nodes" % (sweep_kernel(q, args.store), args.workload, n),
+    cache = args.tile[2] if args.tile else None
+    per = 2 if two_step(q, args.store, cache) else 1
+    bpl = bpl * per  # algorithmic bytes of the sweeps one launch performs, per node
+    rec = {"kernel": "%s, %s, %d nodes" % (sweep_kernel(q, args.store, cache), args.workload, n),
+           "sweeps_per_launch": per,
            "kernel_source_hash": kernel_source_hash(),
            "fetch_kib_per_launch": sf, "write_kib_per_launch": sw, "launches": [nf, nw],
            "copy_fetch_kib": cf, "copy_write_kib": cw, "fetch_scale": f_scale, "write_scale": w_scale,
@@ -168,10 +172,17 @@ def pmc_summary(fetch_dir, write_dir, cfetch_dir, cwrite_dir, args):
     print(json.dumps(rec))
 
 
-def sweep_kernel(q, store):
-    """Name of the sweep kernel that runs for a lattice and store."""
+def two_step(q, store, cache):
+    """True when the cache policy runs two time steps per launch (D2Q9 FP32, bit 6)."""
+    return q == 9 and store == "f32" and cache is not None and (int(cache) & 64) != 0
+
+
+def sweep_kernel(q, store, cache=None):
+    """Name of the sweep kernel that runs for a lattice, store and cache policy."""
     if q == 19:
         return "k_sweep19<%s>" % store
+    if two_step(q, store, cache):
+        return "k_sweep9tb<f32> (two time steps per launch)"
     return ("k_sweep9<%s>" if store in ("f64", "f32", "f32loc") else "k_sweep<9,%s>") % store
 
 
@@ -334,11 +345,13 @@ def run_batch(args):
           file=sys.stderr, flush=True)
     tile = _choose_tile(s, g, args)
     wall = _timed_chunks(s, g, args.steps, args.warmup, graph=True)
-    per_launch, launches = _sweep_mean_ms(s, g)
+    per_sweep, launches = _sweep_mean_ms(s, g)
     r, st = s.residual()
     s.close()
     bpl = g.bytes_per_update(9, store)
-    achieved = bpl * N / (per_launch * 1e-3) / 1e9
+    per = 2 if tile and two_step(9, args.store, tile["cache_policy"]) else 1
+    per_launch = per_sweep * per
+    achieved = bpl * N * per / (per_launch * 1e-3) / 1e9
     sides = sorted(set(int(m.shape[0]) for m in maps))
     cfg = {"workload": "batched D2Q9 GLBM: %d QSGS instances, sides %s, TOC U(0.05,0.30), P log-U(1,30) MPa, "
                        "P_L U(2,8) MPa, V_L U(0.002,0.008) m3/kg; %s populations; one HIP graph per "
@@ -348,8 +361,9 @@ def run_batch(args):
            "median_residual": float(np.median(r)), "steps_total": int(st.max())}
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
             "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic_from_profile(workload_key(args)[0]),
-            "kernel": "%s over the flat tile list" % sweep_kernel(9, args.store), "bytes_per_lu": bpl,
-            "mean_launch_ms": round(per_launch, 5), "launches": launches}
+            "kernel": "%s over the flat tile list" % sweep_kernel(9, args.store, tile["cache_policy"] if tile else None),
+            "bytes_per_lu": bpl, "sweeps_per_launch": per,
+            "mean_launch_ms": round(per_launch, 5), "launches": launches // per}
     return _json_line(N * N_C * args.steps / wall / 1e6, args.steps, args.warmup, wall / args.steps * 1e3,
                       DTYPE[args.store], cfg, roof)
 
@@ -703,8 +717,12 @@ def main():
     lups = N * N_C * args.steps
     mlups = lups / wall / 1e6
     bytes_per_lu = g.bytes_per_update(9, store)
-    per_launch = sweep_ms / max(launches, 1)
-    achieved = bytes_per_lu * N / (per_launch * 1e-3) / 1e9
+    # the library counts sweeps (a two-step launch counts as two); a launch of the
+    # chosen kernel performs `per` sweeps
+    per = 2 if tile and two_step(9, args.store, tile["cache_policy"]) else 1
+    per_sweep = sweep_ms / max(launches, 1)
+    per_launch = per_sweep * per
+    achieved = bytes_per_lu * N * per / (per_launch * 1e-3) / 1e9
     traffic = traffic_from_profile(workload_key(args)[0])
     out = {
         "metric": METRIC,
@@ -727,10 +745,15 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": round(achieved / PEAK_HBM_GBS, 4),
                      "traffic": traffic,
-                     "kernel": sweep_kernel(9, args.store), "bytes_per_lu": bytes_per_lu,
-                     "mean_launch_ms": round(per_launch, 5), "launches": launches,
+                     "kernel": sweep_kernel(9, args.store, tile["cache_policy"] if tile else None),
+                     "bytes_per_lu": bytes_per_lu, "sweeps_per_launch": per,
+                     "mean_launch_ms": round(per_launch, 5), "launches": launches // per,
                      "measured_copy_gbs": copy_bandwidth()},
     }
+    if per == 2:
+        out["roofline"]["note"] = ("two time steps per launch with the intermediate state in LDS: the algorithmic "
+                                   "bytes of two plain sweeps over the launch time exceed the HBM peak; traffic is "
+                                   "what HBM moved")
     if not args.no_converge:
         out["time_to_converge"] = time_to_converge(args.store if args.store in ("f32", "f32loc", "f64") else "f32",
                                                    n=args.converge_problems)
