@@ -270,10 +270,10 @@ int glbm_load_state(glbm_ctx ctx, const void* host, size_t bytes);
  *                            ignored elsewhere and when bit 4 applies); 6 two
  *                            time steps per launch, the intermediate state kept
  *                            in LDS (D2Q9, FP32 store, periodic instances, tiles
- *                            64 x 4/8/16, 128 x 4/8 or 256 x 4, check_every a
- *                            multiple of 4; used for whole check intervals,
- *                            ignored elsewhere).  Same results bit for bit under
- *                            every policy.
+ *                            64 x 4/8/16, 128 x 4/8 or 256 x 4; runs of 4k steps
+ *                            go as 2k such launches, the rest of a run as single
+ *                            steps; ignored elsewhere).  Same results bit for
+ *                            bit under every policy.
  * Errors: GLBM_EINVAL for unknown options or values.
  */
 enum { GLBM_OPT_GRAPH = 1, GLBM_OPT_TIMING = 2, GLBM_OPT_TILE_ROWS = 3, GLBM_OPT_TILE_WIDTH = 4,

@@ -229,8 +229,10 @@ struct glbm_ctx_s {
     double time_ms = 0.0;
     int64_t launches = 0;
 
-    // two steps per launch (cache policy bit 6) for whole chunks of n_c steps
-    bool tb_on() const { return (cache & 64) && n_c % 4 == 0 && tb_applies(cfg, tw_log2, th); }
+    // two steps per launch (cache policy bit 6): runs of 4k steps that start at
+    // an even global step go as 2k two-step launches (an even count, so the state
+    // ends in the buffer of its step parity), the rest as single steps
+    bool tb_on() const { return (cache & 64) && tb_applies(cfg, tw_log2, th); }
 
     Args args(int parity) const
     {
@@ -415,11 +417,10 @@ int capture_chunk(glbm_ctx c, double tol)
     hipGraph_t g = nullptr;
     HIPCHK(hipStreamBeginCapture(c->work, hipStreamCaptureModeRelaxed));
     hipError_t err = hipSuccess;
-    if (c->tb_on()) {
-        for (int j = 0; j < c->n_c / 2 && err == hipSuccess; ++j) err = launch_sweep_tb(c->cfg, c->args(j), c->work);
-    } else {
-        for (int k = 0; k < c->n_c && err == hipSuccess; ++k) err = launch_sweep(c->cfg, c->args(k), c->work);
-    }
+    // chunks start at an even global step (n_c is even)
+    const int two = c->tb_on() ? c->n_c / 4 * 2 : 0;
+    for (int j = 0; j < two && err == hipSuccess; ++j) err = launch_sweep_tb(c->cfg, c->args(j), c->work);
+    for (int k = 2 * two; k < c->n_c && err == hipSuccess; ++k) err = launch_sweep(c->cfg, c->args(k), c->work);
     if (err == hipSuccess) err = launch_observe(c->cfg, c->args(0), 3, c->work);
     if (err == hipSuccess) err = launch_finalize(c->args(0), c->n_inst, tol, 1, 1, c->work);
     hipError_t e2 = hipStreamEndCapture(c->work, &g);
@@ -850,16 +851,18 @@ int glbm_step_n(glbm_ctx c, int64_t n, double tol)
             }
             HIPCHK(hipGraphLaunch(c->graph, c->work));
         } else {
-            if (check && len == c->n_c && c->tb_on() && (c->gstep & 1) == 0) {
-                for (int64_t j = 0; j < len / 2; ++j) {
+            int64_t k = 0;
+            if (c->tb_on() && (c->gstep & 1) == 0) {
+                const int64_t two = len / 4 * 2;
+                for (int64_t j = 0; j < two; ++j) {
                     rc = sweep_once(c, (int)((c->gstep + j) & 1), true);
                     if (rc) return rc;
                 }
-            } else {
-                for (int64_t k = 0; k < len; ++k) {
-                    rc = sweep_once(c, (int)((c->gstep + k) & 1));
-                    if (rc) return rc;
-                }
+                k = 2 * two;
+            }
+            for (; k < len; ++k) {
+                rc = sweep_once(c, (int)((c->gstep + k) & 1));
+                if (rc) return rc;
             }
             if (check) {
                 HIPCHK(launch_observe(c->cfg, c->args(c->gstep + len), 3, c->work));
@@ -1199,7 +1202,7 @@ int glbm_autotune(glbm_ctx c, int32_t steps, int32_t* chosen)
                 if ((cache & 32) && !(c->paired_ok && twl >= 7 && (((1 << twl) * th / kBlock) % 2) == 0)) continue;
                 // two steps per launch: whole chunks only, in launch pairs
                 const bool two = (cache & 64) != 0;
-                if (two && !(tb_applies(c->cfg, twl, th) && c->n_c % 4 == 0 && steps % 4 == 0)) continue;
+                if (two && !(tb_applies(c->cfg, twl, th) && steps % 4 == 0 && (c->gstep & 1) == 0)) continue;
                 c->cache = cache;
                 rc = glbm_set_option(c, GLBM_OPT_TILE_WIDTH, 1 << twl);
                 if (!rc) rc = glbm_set_option(c, GLBM_OPT_TILE_ROWS, th);

@@ -291,10 +291,10 @@ def test_paired_fp16_sweep_bitwise(gpu, store, shape, tile, forch):
                                               ((3, 130), (128, 4), True), ((64, 64), (64, 8), False)])
 def test_two_step_sweep_bitwise(gpu, shape, tile, forch, timing):
     """Two time steps per launch with the intermediate state in LDS (cache policy bit
-    6; D2Q9 FP32, periodic) gives the same bits as one step per launch, over whole
-    check intervals (graph replay, or eager launches with timing on), including tiles
-    wider or taller than the grid; a check interval that is not a multiple of 4 falls
-    back to single steps."""
+    6; D2Q9 FP32, periodic) gives the same bits as one step per launch (graph replay,
+    or eager launches with timing on), including tiles wider or taller than the grid,
+    check intervals that are not a multiple of 4 (the remainder runs as single steps)
+    and runs that start off a check boundary."""
     g = gpu
     cls, eps, k, fe = random_case(shape, seed=123)
     G = (2e-5, -1e-5, 0)
@@ -307,11 +307,13 @@ def test_two_step_sweep_bitwise(gpu, shape, tile, forch, timing):
         if timing:
             s.set_option(g.GLBM_OPT_TIMING, 1)
         s.step(2 * every)
+        s.step(6)        # off the check boundary: 4 in two launches, 2 single
+        s.step(every)    # realigns in two pieces
         p = s.populations()
         r, st = s.residual()
         if timing:
             ms, nl = g.glbm_sweep_time(s.ctx)
-            assert nl == 2 * every
+            assert nl == 3 * every + 6
         s.close()
         out.append((p, r[0], st[0], every))
     for a, b in ((0, 1), (0, 2), (3, 4)):
