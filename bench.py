@@ -147,17 +147,20 @@ def pmc_summary(fetch_dir, write_dir, cfetch_dir, cwrite_dir, args):
     cw, _ = pick(_pmc_per_kernel(cwrite_dir), "neg")
     f_scale = nbytes / (cf * 1024.0)
     w_scale = nbytes / (cw * 1024.0)
-    sf, nf = pick(_pmc_per_kernel(fetch_dir), "k_sweep")
-    sw, nw = pick(_pmc_per_kernel(write_dir), "k_sweep")
+    # the sweep kernel with the most dispatches in the run
+    fd = _pmc_per_kernel(fetch_dir)
+    main = max((k for k in fd if "k_sweep" in k), key=lambda k: len(fd[k]))
+    sf, nf = pick(fd, main)
+    sw, nw = pick(_pmc_per_kernel(write_dir), main)
     read = sf * 1024.0 * f_scale
     write = sw * 1024.0 * w_scale
     import paper_1601_00704_amd.glbm as g
     key, q, n = workload_key(args)
     bpl = g.bytes_per_update(q, g.STORE_NAMES[args.store])
-    cache = args.tile[2] if args.tile else None
-    per = 2 if two_step(q, args.store, cache) else 1
+    per = 2 if "k_sweep9tb" in main else 1
     bpl = bpl * per  # algorithmic bytes of the sweeps one launch performs, per node
-    rec = {"kernel": "%s, %s, %d nodes" % (sweep_kernel(q, args.store, cache), args.workload, n),
+    rec = {"kernel": "%s, %s, %d nodes" % (sweep_kernel(q, args.store, per), args.workload, n),
+           "kernel_symbol": main,
            "sweeps_per_launch": per,
            "kernel_source_hash": kernel_source_hash(),
            "fetch_kib_per_launch": sf, "write_kib_per_launch": sw, "launches": [nf, nw],
@@ -172,17 +175,17 @@ def pmc_summary(fetch_dir, write_dir, cfetch_dir, cwrite_dir, args):
     print(json.dumps(rec))
 
 
-def two_step(q, store, cache):
-    """True when the cache policy runs two time steps per launch (D2Q9 FP32, bit 6)."""
-    return q == 9 and store == "f32" and cache is not None and (int(cache) & 64) != 0
+TWO_STEP_NOTE = ("two time steps per launch with the intermediate state in LDS: the algorithmic bytes of two "
+                 "plain sweeps over the launch time can exceed the HBM peak; traffic is what HBM moved")
 
 
-def sweep_kernel(q, store, cache=None):
-    """Name of the sweep kernel that runs for a lattice, store and cache policy."""
+def sweep_kernel(q, store, per=1):
+    """Name of the sweep kernel that runs for a lattice and store, `per` time
+    steps per launch (glbm_sweeps_per_launch)."""
     if q == 19:
         return "k_sweep19<%s>" % store
-    if two_step(q, store, cache):
-        return "k_sweep9tb<f32> (two time steps per launch)"
+    if per == 2:
+        return "k_sweep9tb<%s> (two time steps per launch)" % store
     return ("k_sweep9<%s>" if store in ("f64", "f32", "f32loc") else "k_sweep<9,%s>") % store
 
 
@@ -346,10 +349,10 @@ def run_batch(args):
     tile = _choose_tile(s, g, args)
     wall = _timed_chunks(s, g, args.steps, args.warmup, graph=True)
     per_sweep, launches = _sweep_mean_ms(s, g)
+    per = g.glbm_sweeps_per_launch(s.ctx)
     r, st = s.residual()
     s.close()
     bpl = g.bytes_per_update(9, store)
-    per = 2 if tile and two_step(9, args.store, tile["cache_policy"]) else 1
     per_launch = per_sweep * per
     achieved = bpl * N * per / (per_launch * 1e-3) / 1e9
     sides = sorted(set(int(m.shape[0]) for m in maps))
@@ -361,9 +364,11 @@ def run_batch(args):
            "median_residual": float(np.median(r)), "steps_total": int(st.max())}
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
             "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic_from_profile(workload_key(args)[0]),
-            "kernel": "%s over the flat tile list" % sweep_kernel(9, args.store, tile["cache_policy"] if tile else None),
+            "kernel": "%s over the flat tile list" % sweep_kernel(9, args.store, per),
             "bytes_per_lu": bpl, "sweeps_per_launch": per,
             "mean_launch_ms": round(per_launch, 5), "launches": launches // per}
+    if per == 2:
+        roof["note"] = TWO_STEP_NOTE
     return _json_line(N * N_C * args.steps / wall / 1e6, args.steps, args.warmup, wall / args.steps * 1e3,
                       DTYPE[args.store], cfg, roof)
 
@@ -710,6 +715,7 @@ def main():
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     sweep_ms, launches = g.glbm_sweep_time(s.ctx)
+    per = g.glbm_sweeps_per_launch(s.ctx)
     r, st = s.residual()
     kk = s.permeability()[0]
     s.close()
@@ -719,7 +725,6 @@ def main():
     bytes_per_lu = g.bytes_per_update(9, store)
     # the library counts sweeps (a two-step launch counts as two); a launch of the
     # chosen kernel performs `per` sweeps
-    per = 2 if tile and two_step(9, args.store, tile["cache_policy"]) else 1
     per_sweep = sweep_ms / max(launches, 1)
     per_launch = per_sweep * per
     achieved = bytes_per_lu * N * per / (per_launch * 1e-3) / 1e9
@@ -745,15 +750,13 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": round(achieved / PEAK_HBM_GBS, 4),
                      "traffic": traffic,
-                     "kernel": sweep_kernel(9, args.store, tile["cache_policy"] if tile else None),
+                     "kernel": sweep_kernel(9, args.store, per),
                      "bytes_per_lu": bytes_per_lu, "sweeps_per_launch": per,
                      "mean_launch_ms": round(per_launch, 5), "launches": launches // per,
                      "measured_copy_gbs": copy_bandwidth()},
     }
     if per == 2:
-        out["roofline"]["note"] = ("two time steps per launch with the intermediate state in LDS: the algorithmic "
-                                   "bytes of two plain sweeps over the launch time exceed the HBM peak; traffic is "
-                                   "what HBM moved")
+        out["roofline"]["note"] = TWO_STEP_NOTE
     if not args.no_converge:
         out["time_to_converge"] = time_to_converge(args.store if args.store in ("f32", "f32loc", "f64") else "f32",
                                                    n=args.converge_problems)

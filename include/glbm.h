@@ -269,17 +269,28 @@ int glbm_load_state(glbm_ctx ctx, const void* host, size_t bytes);
  *                            wide and an even number of nodes per thread;
  *                            ignored elsewhere and when bit 4 applies); 6 two
  *                            time steps per launch, the intermediate state kept
- *                            in LDS (D2Q9, FP32 store, periodic instances, tiles
- *                            64 x 4/8/16, 128 x 4/8 or 256 x 4; runs of 4k steps
- *                            go as 2k such launches, the rest of a run as single
- *                            steps; ignored elsewhere).  Same results bit for
- *                            bit under every policy.
+ *                            in LDS (D2Q9, periodic instances; the F32, F32LOC
+ *                            and F16LOC stores with tiles 64 x 4/8/16, 128 x 4/8
+ *                            or 256 x 4, the F64 store with tiles 64 x 4/8 or
+ *                            128 x 4; runs of 4k steps that start at an even
+ *                            step go as 2k such launches, the rest of a run as
+ *                            single steps; ignored elsewhere, see
+ *                            glbm_sweeps_per_launch).  Same results bit for bit
+ *                            under every policy.
  * Errors: GLBM_EINVAL for unknown options or values.
  */
 enum { GLBM_OPT_GRAPH = 1, GLBM_OPT_TIMING = 2, GLBM_OPT_TILE_ROWS = 3, GLBM_OPT_TILE_WIDTH = 4,
        GLBM_OPT_CACHE = 5 };
 int glbm_set_option(glbm_ctx ctx, int32_t option, int64_t value);
 int glbm_sweep_time(glbm_ctx ctx, double* ms_total, int64_t* launches);
+
+/*
+ * Time steps that one sweep launch performs under the context's current
+ * tile shape and cache policy: 2 where policy bit 6 (two time steps per
+ * launch) applies to the context, else 1.  Host only, no device work.
+ * Errors: GLBM_EINVAL for a null context or output pointer.
+ */
+int glbm_sweeps_per_launch(glbm_ctx ctx, int32_t* sweeps);
 
 /*
  * Autotuner: time every (tile width, tile rows, cache policy) candidate for

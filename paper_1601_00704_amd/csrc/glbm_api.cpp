@@ -1178,6 +1178,14 @@ int glbm_sweep_time(glbm_ctx c, double* ms_total, int64_t* launches)
     return GLBM_OK;
 }
 
+int glbm_sweeps_per_launch(glbm_ctx c, int32_t* sweeps)
+{
+    g_err.clear();
+    if (!c || !sweeps) return fail(GLBM_EINVAL, "null context or output");
+    *sweeps = c->tb_on() ? 2 : 1;
+    return GLBM_OK;
+}
+
 int glbm_autotune(glbm_ctx c, int32_t steps, int32_t* chosen)
 {
     g_err.clear();

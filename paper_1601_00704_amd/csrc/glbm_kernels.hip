@@ -1010,18 +1010,21 @@ __global__ __launch_bounds__(kBlock) void k_sweep9p(Args a)
 }
 
 // --------------------------------------------- two steps per launch (D2Q9) --
-// Temporal blocking for the node-block stores on periodic D2Q9 instances.  A
-// workgroup owns a TW x TH tile and advances it two time steps in one launch:
+// Temporal blocking on periodic D2Q9 instances.  A workgroup owns a TW x TH
+// tile and advances it two time steps in one launch:
 //   1. every node of the tile grown by one node on each side is swept from the
-//      source buffer as in k_sweep9 (pull, collide), and its q post-collision
-//      values are kept in LDS, not written back;
-//   2. every node of the tile pulls those values from LDS, collides again and
-//      writes the result to the other buffer.
+//      source buffer as in a single-step sweep (pull, collide); its q values,
+//      encoded as the store would hold them, and for a kRho store its density
+//      deviation, are kept in LDS, not written back;
+//   2. every node of the tile pulls those values from LDS, decodes them as a
+//      load from the store would, collides again and writes the result to the
+//      other buffer.
 // The nodes of the one-node rim are computed by the neighbouring tiles as
 // well (redundantly: (TW + 2)(TH + 2) / (TW TH) - 1 of the collisions), but the
 // intermediate state never travels through HBM, so one launch moves about the
 // bytes of one plain sweep for two steps.  The arithmetic is that of
-// collide_node, so the result is bitwise equal to two k_sweep9 launches.  The
+// collide_node, and step 2 sees exactly the values a load of the store would
+// return, so the result is bitwise equal to two single-step launches.  The
 // state then sits in the buffer a single step would have written, so the
 // host issues these launches in pairs (four steps between state reads).
 template <int TW, int TH> struct TbShape {
@@ -1031,7 +1034,8 @@ template <int TW, int TH> struct TbShape {
 template <int STORE, bool FORCH, bool NTS, int TW, int TH>
 __device__ __forceinline__ void sweep_tb_tile(const Args& a, const Tile& t, const InstDev& I,
                                               const typename St<STORE>::T* __restrict__ tb, int tcols,
-                                              typename St<STORE>::T (*f1)[TbShape<TW, TH>::kRegion])
+                                              typename St<STORE>::S (*f1)[TbShape<TW, TH>::kRegion],
+                                              float* __restrict__ rho1)
 {
     using SS = St<STORE>;
     using S = typename SS::S;
@@ -1059,9 +1063,10 @@ __device__ __forceinline__ void sweep_tb_tile(const Args& a, const Tile& t, cons
         const int n = y * nx + x;
         T d[9], r[9];
         gather<9, STORE, 0>(d, r, src, cls, I, x, y, 0, n, nt_load);
-        collide_node<9, STORE, 0, FORCH>(d, r, tb + cls[n] * tcols, I, g, omega, cforce);
+        const T dr = collide_node<9, STORE, 0, FORCH>(d, r, tb + cls[n] * tcols, I, g, omega, cforce);
 #pragma unroll
-        for (int i = 0; i < 9; ++i) f1[i][e] = d[i];
+        for (int i = 0; i < 9; ++i) f1[i][e] = SS::enc(d[i], I.scale);
+        if constexpr (SS::kRho) rho1[e] = dr;
     }
     __syncthreads();
     // step 2 over the tile, pulling from the grown tile in LDS
@@ -1073,27 +1078,25 @@ __device__ __forceinline__ void sweep_tb_tile(const Args& a, const Tile& t, cons
         T d[9], r[9];
 #pragma unroll
         for (int i = 0; i < 9; ++i) {
-            d[i] = f1[i][(ly + 1 - L::ey(i)) * Sh::kRW + (lx + 1 - L::ex(i))];
-            r[i] = T(0);
+            const int e = (ly + 1 - L::ey(i)) * Sh::kRW + (lx + 1 - L::ex(i));
+            d[i] = SS::dec(f1[i][e], I.inv_scale);
+            if constexpr (SS::kRho) r[i] = rho1[e];
+            else r[i] = T(0);
         }
-        collide_node<9, STORE, 0, FORCH>(d, r, tb + cls[n] * tcols, I, g, omega, cforce);
-        if constexpr (NTS) {
-#pragma unroll
-            for (int i = 0; i < 9; ++i) __builtin_nontemporal_store(SS::enc(d[i], I.scale), dst + pidx<9, STORE>(i, n, 0));
-        } else {
-#pragma unroll
-            for (int i = 0; i < 9; ++i) dst[pidx<9, STORE>(i, n, 0)] = SS::enc(d[i], I.scale);
-        }
+        collide_store<9, STORE, 0, FORCH, NTS>(d, r, n, tb + cls[n] * tcols, I, g, omega, cforce, dst);
     }
 }
 
 template <int STORE, bool FORCH, int TW, int TH>
 __global__ __launch_bounds__(kBlock) void k_sweep9tb(Args a)
 {
-    using T = typename St<STORE>::T;
+    using SS = St<STORE>;
+    using T = typename SS::T;
+    using Sh = TbShape<TW, TH>;
     constexpr int NT = tab_cols<0, FORCH>();
     __shared__ T tab[kClasses * NT];
-    __shared__ T f1[9][TbShape<TW, TH>::kRegion];
+    __shared__ typename SS::S f1[9][Sh::kRegion];
+    __shared__ float rho1[SS::kRho ? Sh::kRegion : 1];
     const int tid = (a.cache & 4) ? (int)blockIdx.x : xcd_tile(blockIdx.x, gridDim.x);
     const Tile t = a.tiles[tid];
     if (!a.active[t.inst]) return;
@@ -1108,8 +1111,8 @@ __global__ __launch_bounds__(kBlock) void k_sweep9tb(Args a)
         tb = tab;
         tcols = NT;
     }
-    if (a.cache & 1) sweep_tb_tile<STORE, FORCH, true, TW, TH>(a, t, I, tb, tcols, f1);
-    else sweep_tb_tile<STORE, FORCH, false, TW, TH>(a, t, I, tb, tcols, f1);
+    if (a.cache & 1) sweep_tb_tile<STORE, FORCH, true, TW, TH>(a, t, I, tb, tcols, f1, rho1);
+    else sweep_tb_tile<STORE, FORCH, false, TW, TH>(a, t, I, tb, tcols, f1, rho1);
 }
 
 // ------------------------------------------------------------ observations --
@@ -1482,10 +1485,17 @@ hipError_t launch_sweep(const Config& c, const Args& a, hipStream_t s)
 
 bool tb_applies(const Config& c, int tw_log2, int th)
 {
-    if (c.q != 9 || c.bc != 0 || c.store != GLBM_STORE_F32) return false;
+    if (c.q != 9 || c.bc != 0) return false;
     const int tw = 1 << tw_log2;
-    return (tw == 64 && (th == 4 || th == 8 || th == 16)) || (tw == 128 && (th == 4 || th == 8)) ||
-           (tw == 256 && th == 4);
+    const bool small = (tw == 64 && (th == 4 || th == 8)) || (tw == 128 && th == 4);
+    const bool large = (tw == 64 && th == 16) || (tw == 128 && th == 8) || (tw == 256 && th == 4);
+    switch (c.store) {
+    case GLBM_STORE_F32:
+    case GLBM_STORE_F32LOC:
+    case GLBM_STORE_F16LOC: return small || large;
+    case GLBM_STORE_F64: return small;  // 72 bytes of LDS per grown-tile node
+    default: return false;
+    }
 }
 
 hipError_t launch_sweep_tb(const Config& c, const Args& a, hipStream_t s)
@@ -1493,15 +1503,32 @@ hipError_t launch_sweep_tb(const Config& c, const Args& a, hipStream_t s)
     if (a.ntiles <= 0) return hipSuccess;
     const int tw = 1 << a.tw_log2, th = (a.nslot * kBlock) >> a.tw_log2;
     if (!tb_applies(c, a.tw_log2, th)) return hipErrorInvalidValue;
-#define GLBM_TB(W, H)                                                                                          \
-    if (tw == W && th == H) {                                                                                  \
-        if (c.forch)                                                                                           \
-            hipLaunchKernelGGL((k_sweep9tb<GLBM_STORE_F32, true, W, H>), dim3(a.ntiles), dim3(kBlock), 0, s, a); \
-        else                                                                                                   \
-            hipLaunchKernelGGL((k_sweep9tb<GLBM_STORE_F32, false, W, H>), dim3(a.ntiles), dim3(kBlock), 0, s, a); \
-        return hipGetLastError();                                                                              \
+#define GLBM_TB_ST(ST, W, H)                                                                      \
+    if (c.store == ST) {                                                                          \
+        if (c.forch)                                                                              \
+            hipLaunchKernelGGL((k_sweep9tb<ST, true, W, H>), dim3(a.ntiles), dim3(kBlock), 0, s, a);  \
+        else                                                                                      \
+            hipLaunchKernelGGL((k_sweep9tb<ST, false, W, H>), dim3(a.ntiles), dim3(kBlock), 0, s, a); \
+        return hipGetLastError();                                                                 \
     }
-    GLBM_TB(64, 4) GLBM_TB(64, 8) GLBM_TB(64, 16) GLBM_TB(128, 4) GLBM_TB(128, 8) GLBM_TB(256, 4)
+#define GLBM_TB(W, H)                                                                             \
+    if (tw == W && th == H) {                                                                     \
+        GLBM_TB_ST(GLBM_STORE_F32, W, H)                                                          \
+        GLBM_TB_ST(GLBM_STORE_F32LOC, W, H)                                                       \
+        GLBM_TB_ST(GLBM_STORE_F16LOC, W, H)                                                       \
+        return hipErrorInvalidValue;                                                              \
+    }
+#define GLBM_TB64(W, H)                                                                           \
+    if (tw == W && th == H) {                                                                     \
+        GLBM_TB_ST(GLBM_STORE_F32, W, H)                                                          \
+        GLBM_TB_ST(GLBM_STORE_F32LOC, W, H)                                                       \
+        GLBM_TB_ST(GLBM_STORE_F16LOC, W, H)                                                       \
+        GLBM_TB_ST(GLBM_STORE_F64, W, H)                                                          \
+        return hipErrorInvalidValue;                                                              \
+    }
+    GLBM_TB64(64, 4) GLBM_TB64(64, 8) GLBM_TB64(128, 4) GLBM_TB(64, 16) GLBM_TB(128, 8) GLBM_TB(256, 4)
+#undef GLBM_TB64
+#undef GLBM_TB_ST
 #undef GLBM_TB
     return hipErrorInvalidValue;
 }

@@ -41,7 +41,7 @@ def bytes_per_update(q: int, store: int) -> int:
 EXPORTS = ("glbm_required_bytes", "glbm_init_geometry", "glbm_set_local_perm", "glbm_step_n",
            "glbm_residual", "glbm_permeability", "glbm_set_fields", "glbm_set_fields_device",
            "glbm_get_fields", "glbm_get_populations", "glbm_state_bytes", "glbm_save_state",
-           "glbm_load_state", "glbm_set_option", "glbm_sweep_time", "glbm_autotune",
+           "glbm_load_state", "glbm_set_option", "glbm_sweep_time", "glbm_sweeps_per_launch", "glbm_autotune",
            "glbm_velocity_set", "glbm_destroy", "glbm_last_error", "glbm_class_table",
            "glbm_conv3x3_forward", "glbm_conv3x3_flip_weights", "glbm_conv3x3_wgrad_workspace",
            "glbm_conv3x3_backward_weight", "glbm_cnn_create", "glbm_cnn_destroy", "glbm_cnn_num_params",
@@ -100,6 +100,7 @@ def _load():
         "glbm_load_state": (i32, [vp, vp, sz]),
         "glbm_set_option": (i32, [vp, i32, i64]),
         "glbm_sweep_time": (i32, [vp, vp, vp]),
+        "glbm_sweeps_per_launch": (i32, [vp, vp]),
         "glbm_autotune": (i32, [vp, i32, vp]),
         "glbm_velocity_set": (i32, [i32, vp, vp]),
         "glbm_destroy": (i32, [vp]),
@@ -269,6 +270,12 @@ def glbm_sweep_time(ctx):
     n = ctypes.c_int64()
     _check(_lib.glbm_sweep_time(ctx, ctypes.byref(ms), ctypes.byref(n)))
     return ms.value, n.value
+
+
+def glbm_sweeps_per_launch(ctx) -> int:
+    n = ctypes.c_int32()
+    _check(_lib.glbm_sweeps_per_launch(ctx, ctypes.byref(n)))
+    return n.value
 
 
 def glbm_autotune(ctx, steps: int = 20):

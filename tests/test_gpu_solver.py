@@ -285,25 +285,36 @@ def test_paired_fp16_sweep_bitwise(gpu, store, shape, tile, forch):
         assert r[0][0] == out[0][1][0][0]
 
 
+# tile shapes the two-step kernel is built for, per store
+TWO_STEP_TILES = {"f32": {(64, 4), (64, 8), (64, 16), (128, 4), (128, 8), (256, 4)},
+                  "f32loc": {(64, 4), (64, 8), (64, 16), (128, 4), (128, 8), (256, 4)},
+                  "f16loc": {(64, 4), (64, 8), (64, 16), (128, 4), (128, 8), (256, 4)},
+                  "f64": {(64, 4), (64, 8), (128, 4)}}
+
+
+@pytest.mark.parametrize("store", ["f32", "f32loc", "f16loc", "f64"])
 @pytest.mark.parametrize("timing", [False, True])
 @pytest.mark.parametrize("shape,tile,forch", [((48, 200), (64, 4), False), ((40, 130), (128, 8), True),
                                               ((21, 256), (256, 4), False), ((20, 50), (64, 16), False),
                                               ((3, 130), (128, 4), True), ((64, 64), (64, 8), False)])
-def test_two_step_sweep_bitwise(gpu, shape, tile, forch, timing):
+def test_two_step_sweep_bitwise(gpu, store, shape, tile, forch, timing):
     """Two time steps per launch with the intermediate state in LDS (cache policy bit
-    6; D2Q9 FP32, periodic) gives the same bits as one step per launch (graph replay,
-    or eager launches with timing on), including tiles wider or taller than the grid,
-    check intervals that are not a multiple of 4 (the remainder runs as single steps)
-    and runs that start off a check boundary."""
+    6; D2Q9, periodic) gives the same bits as one step per launch (graph replay, or
+    eager launches with timing on) for every store it is built for, including tiles
+    wider or taller than the grid, check intervals that are not a multiple of 4 (the
+    remainder runs as single steps) and runs that start off a check boundary.  Where
+    the kernel is not built for the tile, the policy bit is ignored."""
     g = gpu
     cls, eps, k, fe = random_case(shape, seed=123)
     G = (2e-5, -1e-5, 0)
+    applies = tile in TWO_STEP_TILES[store]
     out = []
     for cache, every in ((13, 100), (77, 100), (79, 100), (13, 102), (77, 102)):
-        print("case shape=%s tile=%s forch=%d timing=%d cache=%d every=%d" % (shape, tile, forch, timing, cache,
-                                                                           every), flush=True)
-        s = gpu_solver(g, 9, cls, eps, k, f_eps=fe if forch else None, G=G, store="f32", tile=tile, cache=cache,
+        print("case store=%s shape=%s tile=%s forch=%d timing=%d cache=%d every=%d"
+              % (store, shape, tile, forch, timing, cache, every), flush=True)
+        s = gpu_solver(g, 9, cls, eps, k, f_eps=fe if forch else None, G=G, store=store, tile=tile, cache=cache,
                        check_every=every)
+        assert g.glbm_sweeps_per_launch(s.ctx) == (2 if (cache & 64) and applies else 1)
         if timing:
             s.set_option(g.GLBM_OPT_TIMING, 1)
         s.step(2 * every)
