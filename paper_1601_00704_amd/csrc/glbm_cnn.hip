@@ -401,16 +401,23 @@ __global__ void k_flip(const uint16_t* w, int cin, int cout, int k_pad_w, int co
 }
 
 // ---------------------------------------------------------- weight gradient --
-// Workgroup: 64 output channels x 64 columns of K, reducing over a range of
-// pixels 128 at a time.  dy and the shifted x are staged transposed in LDS
+// Workgroup: CT output channels x KT columns of K (CT KT = 4096; 64 x 64, or
+// 32 x 128 and 16 x 128 for the layers with few output channels, so that the
+// MFMAs do not multiply padding channels), reducing over a range of pixels
+// 128 at a time.  dy and the shifted x are staged transposed in LDS
 // ([channel][pixel]) so that each lane reads 8 consecutive pixels: a thread
-// loads 8 channels of 4 pixels and writes each channel's 4 values with one
-// 8-byte store.  Each wavefront then issues 16 MFMAs per staged chunk.
+// loads 8 channels (or K columns) of 4 pixels and writes each one's 4 values
+// with one 8-byte store.  The four wavefronts sit WC x WK over the tile, each
+// owning 16 MI channels x 32 K columns, and issue 8 MI MFMAs per staged chunk.
 constexpr int kWgPix = 128;
 constexpr int kBgradCh = 128;        // channel slots per split of the bias partials
 constexpr int kWgMinSplit = 512;     // fewest pixels per split
 constexpr int kWgTargetBlocks = 2048;  // workgroups the split count aims for
 constexpr int kWtRow = kWgPix + 8;
+
+// channel tile of the weight gradient for cout_pad output channels (K tile: 4096 / it, at most 128)
+__host__ __device__ constexpr int wg_ct(int cout_pad) { return cout_pad <= 16 ? 16 : (cout_pad <= 32 ? 32 : 64); }
+__host__ __device__ constexpr int wg_kt(int ct) { return ct == 64 ? 64 : 128; }
 
 struct WgradArgs {
     const uint16_t* x;
@@ -424,7 +431,7 @@ struct WgradArgs {
     long long npix;
     int nsplit;
     long long split_pix;  // pixels per split (a multiple of kWgPix)
-    int kblocks, cblocks;  // 64-wide K and channel blocks
+    int kblocks, cblocks;  // K and channel blocks of the tile
 };
 
 // Workgroup order of the weight gradient: the hardware deals consecutive
@@ -439,16 +446,23 @@ __device__ __forceinline__ int xcd_order(int b, int G)
     return x * q + min(x, r) + k;
 }
 
+template <int CT>
 __global__ __launch_bounds__(kConvBlock) void k_conv_wgrad(WgradArgs a)
 {
-    __shared__ __attribute__((aligned(16))) uint16_t dyt[64 * kWtRow];
-    __shared__ __attribute__((aligned(16))) uint16_t xt[64 * kWtRow];
+    constexpr int KT = wg_kt(CT);
+    constexpr int WC = CT >= 32 ? CT / 32 : 1;  // wavefronts along channels
+    constexpr int WK = 4 / WC;                   // and along K (32 columns each)
+    constexpr int MI = CT / (16 * WC);           // 16-channel MFMA rows per wavefront
+    constexpr int NX = KT / 64;                  // K-column groups each loader thread stages
+    static_assert(WK * 32 == KT && MI >= 1 && MI <= 2, "weight-gradient tile");
+    __shared__ __attribute__((aligned(16))) uint16_t dyt[CT * kWtRow];
+    __shared__ __attribute__((aligned(16))) uint16_t xt[KT * kWtRow];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int m = lane & 15, kq = lane >> 4;
     const int L = xcd_order((int)blockIdx.x, (int)gridDim.x);
     const int kb = L % a.kblocks, rest = L / a.kblocks;
-    const int k0 = kb * 64;                    // K columns
-    const int c0 = (rest % a.cblocks) * 64;    // output channels
+    const int k0 = kb * KT;                    // K columns
+    const int c0 = (rest % a.cblocks) * CT;    // output channels
     const int split = rest / a.cblocks;
     const long long pbeg = (long long)split * a.split_pix;
     const long long pend = min(pbeg + a.split_pix, a.npix);
@@ -458,26 +472,34 @@ __global__ __launch_bounds__(kConvBlock) void k_conv_wgrad(WgradArgs a)
     // chunks (in chunk order); the 32 threads of a channel group are summed at the end
     double bsum[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     const int HW = a.H * a.W;
-    // wave tile: channels c0 + 32 (wave >> 1) .. +32, K columns k0 + 32 (wave & 1) .. +32
-    const int wc = 32 * (wave >> 1), wk = 32 * (wave & 1);
-    f32x4 acc[2][2];
+    // wave tile: channels c0 + wc .. + 16 MI, K columns k0 + wk .. + 32
+    const int wc = 16 * MI * (wave / WK), wk = 32 * (wave % WK);
+    f32x4 acc[MI][2];
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < MI; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
 
-    // loader role: pixels 4 lp .. 4 lp + 3 of the chunk, 8-wide channel / K group lc.
-    // lp runs fastest, so that the 8-byte transposed LDS writes of a wavefront
-    // fill consecutive slots of two rows (no bank conflicts beyond the minimum).
+    // loader role: pixels 4 lp .. 4 lp + 3 of the chunk; 8-wide channel group lc
+    // (threads with lc < CT / 8) and K-column groups lc + 8 h, h < NX.  lp runs
+    // fastest, so that the 8-byte transposed LDS writes of a wavefront fill
+    // consecutive slots of two rows (no bank conflicts beyond the minimum).
     const int lp = threadIdx.x & 31, lc = threadIdx.x >> 5;
+    const bool dy_loader = lc < CT / 8;
     const int co = c0 + 8 * lc;
-    const int k = k0 + 8 * lc;
-    int tap = 0, ci = 0;
-    if (k < a.k_real) {
-        tap = k / a.cin;
-        ci = k - tap * a.cin;
+    int kk[NX], ci[NX], ty[NX], tx[NX];
+#pragma unroll
+    for (int h = 0; h < NX; ++h) {
+        kk[h] = k0 + 8 * (lc + 8 * h);
+        int tap = 0;
+        ci[h] = 0;
+        if (kk[h] < a.k_real) {
+            tap = kk[h] / a.cin;
+            ci[h] = kk[h] - tap * a.cin;
+        }
+        ty[h] = tap / 3 - 1;
+        tx[h] = tap % 3 - 1;
     }
-    const int ty = tap / 3 - 1, tx = tap % 3 - 1;
     // this loader's first pixel of the chunk and its image coordinates, advanced by
     // one chunk per iteration (W is a multiple of 64, so the four pixels 4 lp ..
     // 4 lp + 3 never straddle a row)
@@ -491,36 +513,40 @@ __global__ __launch_bounds__(kConvBlock) void k_conv_wgrad(WgradArgs a)
         px = rem - py * a.W;
     }
     for (long long pb = pbeg; pb < pend; pb += kWgPix) {
-        uint4 dv[4], xv[4];
+        uint4 dv[4], xv[NX][4];
         const long long p = pb + 4 * lp;
-        int yy = py + ty;
-        yy += yy < 0 ? a.H : (yy >= a.H ? -a.H : 0);
-        const size_t row = (size_t)b * HW + (size_t)yy * a.W;
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             dv[u] = make_uint4(0, 0, 0, 0);
-            xv[u] = make_uint4(0, 0, 0, 0);
-            if (p + u < pend) {
-                if (co < a.cout) {
-                    const uint16_t* src = a.dy + (size_t)(p + u) * a.dy_pitch + a.dy_off + co;
-                    if (co + 8 <= a.cout) {
-                        dv[u] = *reinterpret_cast<const uint4*>(src);
-                    } else {
-                        // the last group of a channel count that is not a multiple of 8
-                        const int nv = a.cout - co;
-                        uint32_t w[4];
+            if (dy_loader && p + u < pend && co < a.cout) {
+                const uint16_t* src = a.dy + (size_t)(p + u) * a.dy_pitch + a.dy_off + co;
+                if (co + 8 <= a.cout) {
+                    dv[u] = *reinterpret_cast<const uint4*>(src);
+                } else {
+                    // the last group of a channel count that is not a multiple of 8
+                    const int nv = a.cout - co;
+                    uint32_t w[4];
 #pragma unroll
-                        for (int h = 0; h < 4; ++h) {
-                            const uint32_t lo = 2 * h < nv ? src[2 * h] : 0u, hi = 2 * h + 1 < nv ? src[2 * h + 1] : 0u;
-                            w[h] = lo | (hi << 16);
-                        }
-                        dv[u] = make_uint4(w[0], w[1], w[2], w[3]);
+                    for (int q = 0; q < 4; ++q) {
+                        const uint32_t lo = 2 * q < nv ? src[2 * q] : 0u, hi = 2 * q + 1 < nv ? src[2 * q + 1] : 0u;
+                        w[q] = lo | (hi << 16);
                     }
+                    dv[u] = make_uint4(w[0], w[1], w[2], w[3]);
                 }
-                if (k < a.k_real) {
-                    int xx = px + u + tx;
+            }
+        }
+#pragma unroll
+        for (int h = 0; h < NX; ++h) {
+            int yy = py + ty[h];
+            yy += yy < 0 ? a.H : (yy >= a.H ? -a.H : 0);
+            const size_t row = (size_t)b * HW + (size_t)yy * a.W;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                xv[h][u] = make_uint4(0, 0, 0, 0);
+                if (p + u < pend && kk[h] < a.k_real) {
+                    int xx = px + u + tx[h];
                     xx += xx < 0 ? a.W : (xx >= a.W ? -a.W : 0);
-                    xv[u] = *reinterpret_cast<const uint4*>(a.x + (row + xx) * a.x_pitch + a.x_off + ci);
+                    xv[h][u] = *reinterpret_cast<const uint4*>(a.x + (row + xx) * a.x_pitch + a.x_off + ci[h]);
                 }
             }
         }
@@ -536,17 +562,22 @@ __global__ __launch_bounds__(kConvBlock) void k_conv_wgrad(WgradArgs a)
         // transposed: row = channel (or K column), 4 consecutive pixels per 8-byte write
 #pragma unroll
         for (int i = 0; i < 8; ++i) {
-            const uint16_t* d0 = reinterpret_cast<const uint16_t*>(dv);
-            const uint16_t* x0 = reinterpret_cast<const uint16_t*>(xv);
-            const uint2 dq = make_uint2(uint32_t(d0[i]) | (uint32_t(d0[8 + i]) << 16),
-                                        uint32_t(d0[16 + i]) | (uint32_t(d0[24 + i]) << 16));
-            const uint2 xq = make_uint2(uint32_t(x0[i]) | (uint32_t(x0[8 + i]) << 16),
-                                        uint32_t(x0[16 + i]) | (uint32_t(x0[24 + i]) << 16));
-            *reinterpret_cast<uint2*>(&dyt[(8 * lc + i) * kWtRow + 4 * lp]) = dq;
-            *reinterpret_cast<uint2*>(&xt[(8 * lc + i) * kWtRow + 4 * lp]) = xq;
+            if (dy_loader) {
+                const uint16_t* d0 = reinterpret_cast<const uint16_t*>(dv);
+                const uint2 dq = make_uint2(uint32_t(d0[i]) | (uint32_t(d0[8 + i]) << 16),
+                                            uint32_t(d0[16 + i]) | (uint32_t(d0[24 + i]) << 16));
+                *reinterpret_cast<uint2*>(&dyt[(8 * lc + i) * kWtRow + 4 * lp]) = dq;
+            }
+#pragma unroll
+            for (int h = 0; h < NX; ++h) {
+                const uint16_t* x0 = reinterpret_cast<const uint16_t*>(xv[h]);
+                const uint2 xq = make_uint2(uint32_t(x0[i]) | (uint32_t(x0[8 + i]) << 16),
+                                            uint32_t(x0[16 + i]) | (uint32_t(x0[24 + i]) << 16));
+                *reinterpret_cast<uint2*>(&xt[(8 * (lc + 8 * h) + i) * kWtRow + 4 * lp]) = xq;
+            }
         }
         __syncthreads();
-        if (bias) {
+        if (bias && dy_loader) {
             const uint16_t* d0 = reinterpret_cast<const uint16_t*>(dv);
 #pragma unroll
             for (int i = 0; i < 8; ++i)
@@ -556,7 +587,7 @@ __global__ __launch_bounds__(kConvBlock) void k_conv_wgrad(WgradArgs a)
 #pragma unroll
         for (int ks = 0; ks < kWgPix / 32; ++ks) {
 #pragma unroll
-            for (int i = 0; i < 2; ++i) {
+            for (int i = 0; i < MI; ++i) {
                 const uint4 av = *reinterpret_cast<const uint4*>(&dyt[(wc + 16 * i + m) * kWtRow + 32 * ks + 8 * kq]);
 #pragma unroll
                 for (int j = 0; j < 2; ++j) {
@@ -570,13 +601,15 @@ __global__ __launch_bounds__(kConvBlock) void k_conv_wgrad(WgradArgs a)
         }
     }
     if (bias) {
-        // red[channel][lp] reuses the dy tile (64 x 32 doubles = 16 KiB fits in 64 x kWtRow bf16)
+        // red[channel][lp] reuses the dy tile (CT x 32 doubles fit in CT x kWtRow bf16)
         double* red = reinterpret_cast<double*>(dyt);
         __syncthreads();  // every wavefront is done with the dy tile
+        if (dy_loader) {
 #pragma unroll
-        for (int i = 0; i < 8; ++i) red[(8 * lc + i) * 32 + lp] = bsum[i];
+            for (int i = 0; i < 8; ++i) red[(8 * lc + i) * 32 + lp] = bsum[i];
+        }
         __syncthreads();
-        if (threadIdx.x < 64 && c0 + threadIdx.x < a.cout) {
+        if (threadIdx.x < CT && c0 + threadIdx.x < a.cout) {
             double t = 0.0;
             for (int q = 0; q < 32; ++q) t += red[threadIdx.x * 32 + q];
             a.bpart[(size_t)split * kBgradCh + c0 + threadIdx.x] = float(t);
@@ -585,7 +618,7 @@ __global__ __launch_bounds__(kConvBlock) void k_conv_wgrad(WgradArgs a)
     // D[4 kq + r][m]: row = output channel, column = K column
     float* out = a.part + (size_t)split * a.cout_pad * a.k_real;
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < MI; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j)
 #pragma unroll
@@ -1006,7 +1039,8 @@ int flip_weights(const uint16_t* w, int cin, int cout, uint16_t* wt, hipStream_t
 // only on the shapes, so the reduction order (and the result) is fixed.
 void wgrad_split(int cin, int cout, long long npix, int* nsplit, long long* split_pix)
 {
-    const long long blocks = (long long)((9 * cin + 63) / 64) * ((rup(cout, 16) + 63) / 64);
+    const int ct = wg_ct(rup(cout, 16)), kt = wg_kt(ct);
+    const long long blocks = (long long)((9 * cin + kt - 1) / kt) * ((rup(cout, 16) + ct - 1) / ct);
     long long ns = std::max(1LL, std::min((npix + kWgMinSplit - 1) / kWgMinSplit,
                                           (kWgTargetBlocks + blocks - 1) / blocks));
     long long sp = (npix + ns - 1) / ns;
@@ -1045,10 +1079,16 @@ int conv_wgrad(const uint16_t* x, int xp, int xo, int cin, const uint16_t* dy, i
     wgrad_split(cin, cout, a.npix, &a.nsplit, &a.split_pix);
     a.part = static_cast<float*>(ws);
     a.bpart = db ? a.part + (size_t)a.nsplit * a.cout_pad * a.k_real : nullptr;
-    a.kblocks = (a.k_real + 63) / 64;
-    a.cblocks = (a.cout_pad + 63) / 64;
+    const int ct = wg_ct(a.cout_pad), kt = wg_kt(ct);
+    a.kblocks = (a.k_real + kt - 1) / kt;
+    a.cblocks = (a.cout_pad + ct - 1) / ct;
     dim3 grid((unsigned)(a.kblocks * a.cblocks * a.nsplit));
-    hipLaunchKernelGGL(k_conv_wgrad, grid, dim3(kConvBlock), 0, s, a);
+    if (ct == 16)
+        hipLaunchKernelGGL(k_conv_wgrad<16>, grid, dim3(kConvBlock), 0, s, a);
+    else if (ct == 32)
+        hipLaunchKernelGGL(k_conv_wgrad<32>, grid, dim3(kConvBlock), 0, s, a);
+    else
+        hipLaunchKernelGGL(k_conv_wgrad<64>, grid, dim3(kConvBlock), 0, s, a);
     CHK(hipGetLastError());
     hipLaunchKernelGGL(k_wgrad_reduce, dim3((unsigned)(((long long)cout * a.k_real + kRedCols - 1) / kRedCols)),
                        dim3(kRedCols * kRedRows), 0, s, a.part, a.nsplit, cout, a.cout_pad, a.k_real, dw);

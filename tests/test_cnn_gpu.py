@@ -132,8 +132,12 @@ def test_conv_data_gradient(gpu, cin, cout, W):
 
 
 @pytest.mark.parametrize("cin,cout,B,H,W", [(8, 32, 2, 6, 64), (32, 3, 1, 40, 128), (192, 64, 1, 8, 64),
-                                             (128, 128, 2, 64, 64)])
+                                             (128, 128, 2, 64, 64), (96, 32, 2, 16, 128), (64, 16, 1, 8, 64),
+                                             (32, 48, 1, 8, 64), (24, 20, 1, 6, 64)])
 def test_conv_weight_gradient(gpu, cin, cout, B, H, W):
+    """Weight and bias gradients against the FP64 oracle, element by element, over the
+    channel tiles (16, 32 and 64 output channels), ragged channel and K blocks and
+    pixel ranges split across workgroups."""
     import torch
     g = gpu
     rng = np.random.default_rng(cin + 3 * cout)
