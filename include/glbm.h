@@ -269,12 +269,14 @@ int glbm_load_state(glbm_ctx ctx, const void* host, size_t bytes);
  *                            wide and an even number of nodes per thread;
  *                            ignored elsewhere and when bit 4 applies); 6 two
  *                            time steps per launch, the intermediate state kept
- *                            in LDS (D2Q9, periodic instances; the F32, F32LOC
- *                            and F16LOC stores with tiles 64 x 4/8/16, 128 x 4/8
- *                            or 256 x 4, the F64 store with tiles 64 x 4/8 or
- *                            128 x 4; runs of 4k steps that start at an even
- *                            step go as 2k such launches, the rest of a run as
- *                            single steps; ignored elsewhere, see
+ *                            in LDS (D2Q9; periodic instances with the F32,
+ *                            F32LOC and F16LOC stores and tiles 64 x 4/8/16,
+ *                            128 x 4/8 or 256 x 4, or the F64 store and tiles
+ *                            64 x 4/8 or 128 x 4; pressure faces, with or
+ *                            without wall nodes, with the F64 and F32 stores and
+ *                            tiles 64 x 4/8 or 128 x 4; runs of 4k steps that
+ *                            start at an even step go as 2k such launches, the
+ *                            rest of a run as single steps; ignored elsewhere, see
  *                            glbm_sweeps_per_launch).  Same results bit for bit
  *                            under every policy.
  * Errors: GLBM_EINVAL for unknown options or values.

@@ -1031,17 +1031,74 @@ template <int TW, int TH> struct TbShape {
     static constexpr int kRW = TW + 2, kRH = TH + 2, kRegion = kRW * kRH;
 };
 
-template <int STORE, bool FORCH, bool NTS, int TW, int TH>
+// Step 2's pull of node (x, y), at (lx, ly) in the tile, from the grown tile in
+// LDS, with the boundary rules of gather(): directions entering through a
+// pressure face are left to fill_face, and a pull that a face wall or a wall
+// node blocks takes the node's own opposite value.  c1 holds the classes of
+// the grown tile.
+template <int STORE, int BC, int TW, int TH>
+__device__ __forceinline__ void pull_tb(typename St<STORE>::T (&d)[9], typename St<STORE>::T (&r)[9],
+                                        const typename St<STORE>::S (*f1)[TbShape<TW, TH>::kRegion],
+                                        const float* __restrict__ rho1, const uint8_t* __restrict__ c1,
+                                        const InstDev& I, int x, int y, int lx, int ly)
+{
+    using SS = St<STORE>;
+    using T = typename SS::T;
+    using L = Lat<9>;
+    using Sh = TbShape<TW, TH>;
+    const int own = (ly + 1) * Sh::kRW + (lx + 1);
+    int side = 0;
+    if constexpr (pressure_faces(BC)) {
+        const int ca = I.paxis == 0 ? x : y, na = I.paxis == 0 ? I.nx : I.ny;
+        side = ca == 0 ? 1 : (ca == na - 1 ? -1 : 0);
+    }
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        const int ex = L::ex(i), ey = L::ey(i);
+        if constexpr (pressure_faces(BC)) {
+            const int ea = I.paxis == 0 ? ex : (I.paxis == 1 ? ey : 0);
+            if (side * ea > 0) {
+                d[i] = T(0);
+                r[i] = T(0);
+                continue;
+            }
+        }
+        int e = (ly + 1 - ey) * Sh::kRW + (lx + 1 - ex);
+        int j = i;
+        if constexpr (face_walls(BC) || wall_nodes(BC)) {
+            const uint32_t w = I.walls;
+            bool blocked = false;
+            if constexpr (face_walls(BC)) {
+                if (ex > 0) blocked |= (x == 0) && (w & 1u);
+                if (ex < 0) blocked |= (x == I.nx - 1) && (w & 2u);
+                if (ey > 0) blocked |= (y == 0) && (w & 4u);
+                if (ey < 0) blocked |= (y == I.ny - 1) && (w & 8u);
+            }
+            if (wall_nodes(BC) && i != 0) blocked |= c1[e] == kWallClass;
+            if (blocked) {
+                e = own;
+                j = L::opp(i);
+            }
+        }
+        d[i] = SS::dec(f1[j][e], I.inv_scale);
+        if constexpr (SS::kRho) r[i] = rho1[e];
+        else r[i] = T(0);
+    }
+    if constexpr (pressure_faces(BC))
+        if (side != 0) fill_face<9, SS::kRho>(d, r, I, side);
+}
+
+template <int STORE, int BC, bool FORCH, bool NTS, int TW, int TH>
 __device__ __forceinline__ void sweep_tb_tile(const Args& a, const Tile& t, const InstDev& I,
                                               const typename St<STORE>::T* __restrict__ tb, int tcols,
                                               typename St<STORE>::S (*f1)[TbShape<TW, TH>::kRegion],
-                                              float* __restrict__ rho1)
+                                              float* __restrict__ rho1, uint8_t* __restrict__ c1)
 {
     using SS = St<STORE>;
     using S = typename SS::S;
     using T = typename SS::T;
-    using L = Lat<9>;
     using Sh = TbShape<TW, TH>;
+    constexpr bool kC1 = face_walls(BC) || wall_nodes(BC) || pressure_faces(BC);
     const int nx = I.nx, ny = I.ny;
     const int sel = (a.parity + I.par) & 1;
     const S* __restrict__ src = static_cast<const S*>(a.buf[sel]) + I.pop_off;
@@ -1050,7 +1107,9 @@ __device__ __forceinline__ void sweep_tb_tile(const Args& a, const Tile& t, cons
     const T g[3] = {inst_g<T>(I, 0), inst_g<T>(I, 1), inst_g<T>(I, 2)};
     const T omega = inst_omega<T>(I), cforce = inst_cforce<T>(I);
     const bool nt_load = (a.cache & 2) != 0;
-    // step 1 over the grown tile (coordinates wrapped onto the periodic grid)
+    // step 1 over the grown tile (coordinates wrapped onto the grid; beyond a
+    // face wall or a pressure face the wrapped rim nodes are computed but never
+    // pulled, since those pulls are blocked or rebuilt)
     for (int e = threadIdx.x; e < Sh::kRegion; e += kBlock) {
         const int ry = e / Sh::kRW, rx = e - ry * Sh::kRW;
         int x = t.x0 - 1 + rx, y = t.y0 - 1 + ry;
@@ -1061,9 +1120,12 @@ __device__ __forceinline__ void sweep_tb_tile(const Args& a, const Tile& t, cons
         if (y >= ny) y -= ny;
         if (y >= ny) y %= ny;
         const int n = y * nx + x;
+        const int c = cls[n];
+        if constexpr (kC1) c1[e] = uint8_t(c);
+        if (wall_nodes(BC) && c == kWallClass) continue;  // never swept, never pulled from
         T d[9], r[9];
-        gather<9, STORE, 0>(d, r, src, cls, I, x, y, 0, n, nt_load);
-        const T dr = collide_node<9, STORE, 0, FORCH>(d, r, tb + cls[n] * tcols, I, g, omega, cforce);
+        gather<9, STORE, BC>(d, r, src, cls, I, x, y, 0, n, nt_load);
+        const T dr = collide_node<9, STORE, BC, FORCH>(d, r, tb + c * tcols, I, g, omega, cforce);
 #pragma unroll
         for (int i = 0; i < 9; ++i) f1[i][e] = SS::enc(d[i], I.scale);
         if constexpr (SS::kRho) rho1[e] = dr;
@@ -1075,28 +1137,36 @@ __device__ __forceinline__ void sweep_tb_tile(const Args& a, const Tile& t, cons
         const int x = t.x0 + lx, y = t.y0 + ly;
         if (x >= nx || y >= ny) continue;
         const int n = y * nx + x;
+        const int c = kC1 ? int(c1[(ly + 1) * Sh::kRW + lx + 1]) : int(cls[n]);
+        if (wall_nodes(BC) && c == kWallClass) continue;
         T d[9], r[9];
+        if constexpr (kC1) {
+            pull_tb<STORE, BC, TW, TH>(d, r, f1, rho1, c1, I, x, y, lx, ly);
+        } else {
 #pragma unroll
-        for (int i = 0; i < 9; ++i) {
-            const int e = (ly + 1 - L::ey(i)) * Sh::kRW + (lx + 1 - L::ex(i));
-            d[i] = SS::dec(f1[i][e], I.inv_scale);
-            if constexpr (SS::kRho) r[i] = rho1[e];
-            else r[i] = T(0);
+            for (int i = 0; i < 9; ++i) {
+                const int e = (ly + 1 - Lat<9>::ey(i)) * Sh::kRW + (lx + 1 - Lat<9>::ex(i));
+                d[i] = SS::dec(f1[i][e], I.inv_scale);
+                if constexpr (SS::kRho) r[i] = rho1[e];
+                else r[i] = T(0);
+            }
         }
-        collide_store<9, STORE, 0, FORCH, NTS>(d, r, n, tb + cls[n] * tcols, I, g, omega, cforce, dst);
+        collide_store<9, STORE, BC, FORCH, NTS>(d, r, n, tb + c * tcols, I, g, omega, cforce, dst);
     }
 }
 
-template <int STORE, bool FORCH, int TW, int TH>
+template <int STORE, int BC, bool FORCH, int TW, int TH>
 __global__ __launch_bounds__(kBlock) void k_sweep9tb(Args a)
 {
     using SS = St<STORE>;
     using T = typename SS::T;
     using Sh = TbShape<TW, TH>;
-    constexpr int NT = tab_cols<0, FORCH>();
+    constexpr int NT = tab_cols<BC, FORCH>();
+    constexpr bool kC1 = face_walls(BC) || wall_nodes(BC) || pressure_faces(BC);
     __shared__ T tab[kClasses * NT];
     __shared__ typename SS::S f1[9][Sh::kRegion];
     __shared__ float rho1[SS::kRho ? Sh::kRegion : 1];
+    __shared__ uint8_t c1[kC1 ? Sh::kRegion : 1];
     const int tid = (a.cache & 4) ? (int)blockIdx.x : xcd_tile(blockIdx.x, gridDim.x);
     const Tile t = a.tiles[tid];
     if (!a.active[t.inst]) return;
@@ -1111,8 +1181,8 @@ __global__ __launch_bounds__(kBlock) void k_sweep9tb(Args a)
         tb = tab;
         tcols = NT;
     }
-    if (a.cache & 1) sweep_tb_tile<STORE, FORCH, true, TW, TH>(a, t, I, tb, tcols, f1, rho1);
-    else sweep_tb_tile<STORE, FORCH, false, TW, TH>(a, t, I, tb, tcols, f1, rho1);
+    if (a.cache & 1) sweep_tb_tile<STORE, BC, FORCH, true, TW, TH>(a, t, I, tb, tcols, f1, rho1, c1);
+    else sweep_tb_tile<STORE, BC, FORCH, false, TW, TH>(a, t, I, tb, tcols, f1, rho1, c1);
 }
 
 // ------------------------------------------------------------ observations --
@@ -1485,10 +1555,13 @@ hipError_t launch_sweep(const Config& c, const Args& a, hipStream_t s)
 
 bool tb_applies(const Config& c, int tw_log2, int th)
 {
-    if (c.q != 9 || c.bc != 0) return false;
+    if (c.q != 9) return false;
     const int tw = 1 << tw_log2;
     const bool small = (tw == 64 && (th == 4 || th == 8)) || (tw == 128 && th == 4);
     const bool large = (tw == 64 && th == 16) || (tw == 128 && th == 8) || (tw == 256 && th == 4);
+    if (c.bc == 3 || c.bc == 4)  // pressure faces (no Forchheimer classes there)
+        return !c.forch && small && (c.store == GLBM_STORE_F64 || c.store == GLBM_STORE_F32);
+    if (c.bc != 0) return false;
     switch (c.store) {
     case GLBM_STORE_F32:
     case GLBM_STORE_F32LOC:
@@ -1503,31 +1576,45 @@ hipError_t launch_sweep_tb(const Config& c, const Args& a, hipStream_t s)
     if (a.ntiles <= 0) return hipSuccess;
     const int tw = 1 << a.tw_log2, th = (a.nslot * kBlock) >> a.tw_log2;
     if (!tb_applies(c, a.tw_log2, th)) return hipErrorInvalidValue;
-#define GLBM_TB_ST(ST, W, H)                                                                      \
-    if (c.store == ST) {                                                                          \
-        if (c.forch)                                                                              \
-            hipLaunchKernelGGL((k_sweep9tb<ST, true, W, H>), dim3(a.ntiles), dim3(kBlock), 0, s, a);  \
-        else                                                                                      \
-            hipLaunchKernelGGL((k_sweep9tb<ST, false, W, H>), dim3(a.ntiles), dim3(kBlock), 0, s, a); \
-        return hipGetLastError();                                                                 \
+#define GLBM_TB_ST(ST, W, H)                                                                         \
+    if (c.store == ST) {                                                                             \
+        if (c.forch)                                                                                 \
+            hipLaunchKernelGGL((k_sweep9tb<ST, 0, true, W, H>), dim3(a.ntiles), dim3(kBlock), 0, s, a);  \
+        else                                                                                         \
+            hipLaunchKernelGGL((k_sweep9tb<ST, 0, false, W, H>), dim3(a.ntiles), dim3(kBlock), 0, s, a); \
+        return hipGetLastError();                                                                    \
     }
-#define GLBM_TB(W, H)                                                                             \
-    if (tw == W && th == H) {                                                                     \
-        GLBM_TB_ST(GLBM_STORE_F32, W, H)                                                          \
-        GLBM_TB_ST(GLBM_STORE_F32LOC, W, H)                                                       \
-        GLBM_TB_ST(GLBM_STORE_F16LOC, W, H)                                                       \
-        return hipErrorInvalidValue;                                                              \
+#define GLBM_TB_P(ST, W, H)                                                                          \
+    if (c.store == ST) {                                                                             \
+        if (c.bc == 3)                                                                               \
+            hipLaunchKernelGGL((k_sweep9tb<ST, 3, false, W, H>), dim3(a.ntiles), dim3(kBlock), 0, s, a); \
+        else                                                                                         \
+            hipLaunchKernelGGL((k_sweep9tb<ST, 4, false, W, H>), dim3(a.ntiles), dim3(kBlock), 0, s, a); \
+        return hipGetLastError();                                                                    \
     }
-#define GLBM_TB64(W, H)                                                                           \
-    if (tw == W && th == H) {                                                                     \
-        GLBM_TB_ST(GLBM_STORE_F32, W, H)                                                          \
-        GLBM_TB_ST(GLBM_STORE_F32LOC, W, H)                                                       \
-        GLBM_TB_ST(GLBM_STORE_F16LOC, W, H)                                                       \
-        GLBM_TB_ST(GLBM_STORE_F64, W, H)                                                          \
-        return hipErrorInvalidValue;                                                              \
+#define GLBM_TB(W, H)                                                                                \
+    if (tw == W && th == H) {                                                                        \
+        GLBM_TB_ST(GLBM_STORE_F32, W, H)                                                             \
+        GLBM_TB_ST(GLBM_STORE_F32LOC, W, H)                                                          \
+        GLBM_TB_ST(GLBM_STORE_F16LOC, W, H)                                                          \
+        return hipErrorInvalidValue;                                                                 \
+    }
+#define GLBM_TB64(W, H)                                                                              \
+    if (tw == W && th == H) {                                                                        \
+        if (c.bc != 0) {                                                                             \
+            GLBM_TB_P(GLBM_STORE_F32, W, H)                                                          \
+            GLBM_TB_P(GLBM_STORE_F64, W, H)                                                          \
+            return hipErrorInvalidValue;                                                             \
+        }                                                                                            \
+        GLBM_TB_ST(GLBM_STORE_F32, W, H)                                                             \
+        GLBM_TB_ST(GLBM_STORE_F32LOC, W, H)                                                          \
+        GLBM_TB_ST(GLBM_STORE_F16LOC, W, H)                                                          \
+        GLBM_TB_ST(GLBM_STORE_F64, W, H)                                                             \
+        return hipErrorInvalidValue;                                                                 \
     }
     GLBM_TB64(64, 4) GLBM_TB64(64, 8) GLBM_TB64(128, 4) GLBM_TB(64, 16) GLBM_TB(128, 8) GLBM_TB(256, 4)
 #undef GLBM_TB64
+#undef GLBM_TB_P
 #undef GLBM_TB_ST
 #undef GLBM_TB
     return hipErrorInvalidValue;

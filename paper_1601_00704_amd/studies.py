@@ -48,7 +48,8 @@ def gas_params(case, molar_mass=0.016043):
 
 def solve_study(cases, maps=None, store="f64", tol=1e-8, max_steps=3000000, tile=None):
     """Solve every sample of a study in one batched context; returns per-sample records
-    and the run's wall time, steps and lattice updates."""
+    and the run's wall time, steps and lattice updates.  tile: (width, rows[, cache
+    policy]), default two time steps per launch on 64 x 4 tiles for F64 and F32."""
     maps = maps if maps is not None else [c.classes() for c in cases]
     descs = [g.make_desc(m.shape, store=g.STORE_NAMES[store], tau=1.0, g=(0, 0, 0), check_every=N_C,
                          pressure_axis=0, rho_in=1 + DRHO / 2, rho_out=1 - DRHO / 2) for m in maps]
@@ -57,9 +58,15 @@ def solve_study(cases, maps=None, store="f64", tol=1e-8, max_steps=3000000, tile
         for i, c in enumerate(cases):
             eps, kc, kk, ks, b = g.glbm_class_table_pressure(gas_params(c), *c.radii())
             s.set_pressure_perm(eps[:255], kc[:255], kk[:255], ks[:255], b[:255], c.p_in, c.p_out, inst=i)
+        if tile is None and store in ("f64", "f32"):
+            # two time steps per launch on 64 x 4 tiles (cache policy 77), bitwise equal
+            # to one step per launch
+            tile = (64, 4, 77)
         if tile:
             s.set_option(g.GLBM_OPT_TILE_WIDTH, tile[0])
             s.set_option(g.GLBM_OPT_TILE_ROWS, tile[1])
+            if len(tile) > 2:
+                s.set_option(g.GLBM_OPT_CACHE, tile[2])
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         rc = s.step(max_steps, tol=tol)

@@ -131,6 +131,46 @@ def test_layer_cases_match_oracle_and_order(gpu, store, tol):
     assert ks[3] > ks[2]
 
 
+@pytest.mark.parametrize("timing", [False, True])
+@pytest.mark.parametrize("store", ["f64", "f32"])
+@pytest.mark.parametrize("axis,shape,tile,walls", [(0, (36, 70), (64, 4), 0.06), (1, (66, 48), (64, 8), 0.0),
+                                                   (0, (40, 130), (128, 4), 0.05), (1, (20, 50), (64, 4), 0.04),
+                                                   (0, (9, 40), (64, 8), 0.0)])
+def test_pressure_two_step_bitwise(gpu, store, axis, shape, tile, walls, timing):
+    """Two time steps per launch under pressure faces (K(P) per class, with and without
+    wall nodes, the faces on x or on y, tiles wider than the grid) gives the same bits as
+    one step per launch, with graph replay or eager launches, over check intervals that
+    are and are not multiples of 4 and runs that start off a check boundary."""
+    g = gpu
+    cls, eps, k, _ = random_case(shape, seed=77, wall_frac=walls)
+    A, B, C, b = _kp_table(77)
+    pr = oracle.Pressure(axis=axis, rho_in=1.0005, rho_out=0.9995, k_const=A, k_kn=B, k_surf=C, lang_b=b,
+                         p_in=0.2e6, p_out=0.1e6)
+    out = []
+    for cache, every in ((13, 100), (77, 100), (79, 100), (13, 102), (77, 102)):
+        print("case store=%s axis=%d shape=%s tile=%s walls=%.2f timing=%d cache=%d every=%d"
+              % (store, axis, shape, tile, walls, timing, cache, every), flush=True)
+        s = gpu_solver(g, 9, cls, eps, k, G=(0, 0, 0), store=store, tile=tile, cache=cache, check_every=every,
+                       pressure=pr)
+        assert g.glbm_sweeps_per_launch(s.ctx) == (2 if cache & 64 else 1)
+        if timing:
+            s.set_option(g.GLBM_OPT_TIMING, 1)
+        s.step(2 * every)
+        s.step(6)
+        s.step(every)
+        p = s.populations()
+        r, st = s.residual()
+        kk = s.permeability()[0]
+        if timing:
+            ms, nl = g.glbm_sweep_time(s.ctx)
+            assert nl == 3 * every + 6
+        s.close()
+        out.append((p, r[0], st[0], kk[axis]))
+    for a, b2 in ((0, 1), (0, 2), (3, 4)):
+        assert np.array_equal(out[a][0], out[b2][0])
+        assert out[a][1:] == out[b2][1:]
+
+
 def test_pressure_argument_errors(gpu):
     """Pressure faces with walls on another axis, equal densities or a one-node axis are
     rejected; glbm_set_pressure_perm needs pressure faces; F_eps > 0 is rejected."""
