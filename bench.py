@@ -532,7 +532,8 @@ def run_studies(args):
     out = {}
     total_lu, total_wall = 0.0, 0.0
     for name, cases in (("layout", si.layout_study(realizations=2)), ("toc", si.toc_study())):
-        res, run = studies.solve_study(cases, store=args.store, tol=1e-8, max_steps=args.max_steps)
+        res, run = studies.solve_study(cases, store=args.store, tol=1e-8, max_steps=args.max_steps,
+                                       tile=tuple(args.tile) if args.tile else None)
         total_lu += run["lattice_updates"]
         total_wall += run["wall_s"]
         out[name] = {"run": run, "samples": [{k: v for k, v in r.items() if k not in ("name",)} for r in res]}

@@ -299,7 +299,7 @@ int glbm_sweeps_per_launch(glbm_ctx ctx, int32_t* sweeps);
  * `steps` sweeps and keep the fastest.  Widths 64 .. 1024 (up to twice the
  * widest instance), rows 1 .. 16, cache policies 1, 3, 4, 5, 9, 12, 13, 15
  * (and 29, 31 where the LDS-staged FP16 sweep applies, 37, 45, 47 where the
- * paired-node FP16 sweep does, 77, 79 where two steps per launch do and
+ * paired-node FP16 sweep does, 69, 71, 77, 79 where two steps per launch do and
  * `steps` is a multiple of 4).
  * The state advances by those sweeps (an even number per candidate); the
  * residual snapshot is reset.  If chosen is not NULL it receives {width,

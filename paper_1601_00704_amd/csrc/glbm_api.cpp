@@ -1205,7 +1205,7 @@ int glbm_autotune(glbm_ctx c, int32_t steps, int32_t* chosen)
             // policies with and without nontemporal stores (bit 0), and the FP16
             // sweeps with LDS-staged rows (bit 4) and with node pairs (bit 5)
             // where they apply
-            for (int cache : {1, 3, 4, 5, 9, 12, 13, 15, 29, 31, 37, 45, 47, 77, 79}) {
+            for (int cache : {1, 3, 4, 5, 9, 12, 13, 15, 29, 31, 37, 45, 47, 69, 71, 77, 79}) {
                 if ((cache & 16) && !(c->staged_ok && twl <= 8 && (th == 1 || th == 2 || th == 4))) continue;
                 if ((cache & 32) && !(c->paired_ok && twl >= 7 && (((1 << twl) * th / kBlock) % 2) == 0)) continue;
                 // two steps per launch: whole chunks only, in launch pairs

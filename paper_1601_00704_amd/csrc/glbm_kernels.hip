@@ -1035,7 +1035,8 @@ template <int TW, int TH> struct TbShape {
 // LDS, with the boundary rules of gather(): directions entering through a
 // pressure face are left to fill_face, and a pull that a face wall or a wall
 // node blocks takes the node's own opposite value.  c1 holds the classes of
-// the grown tile.
+// the grown tile (step 2 takes its nodes' classes from there too, instead of
+// a second read of the class map).
 template <int STORE, int BC, int TW, int TH>
 __device__ __forceinline__ void pull_tb(typename St<STORE>::T (&d)[9], typename St<STORE>::T (&r)[9],
                                         const typename St<STORE>::S (*f1)[TbShape<TW, TH>::kRegion],
@@ -1098,7 +1099,6 @@ __device__ __forceinline__ void sweep_tb_tile(const Args& a, const Tile& t, cons
     using S = typename SS::S;
     using T = typename SS::T;
     using Sh = TbShape<TW, TH>;
-    constexpr bool kC1 = face_walls(BC) || wall_nodes(BC) || pressure_faces(BC);
     const int nx = I.nx, ny = I.ny;
     const int sel = (a.parity + I.par) & 1;
     const S* __restrict__ src = static_cast<const S*>(a.buf[sel]) + I.pop_off;
@@ -1121,7 +1121,7 @@ __device__ __forceinline__ void sweep_tb_tile(const Args& a, const Tile& t, cons
         if (y >= ny) y %= ny;
         const int n = y * nx + x;
         const int c = cls[n];
-        if constexpr (kC1) c1[e] = uint8_t(c);
+        c1[e] = uint8_t(c);
         if (wall_nodes(BC) && c == kWallClass) continue;  // never swept, never pulled from
         T d[9], r[9];
         gather<9, STORE, BC>(d, r, src, cls, I, x, y, 0, n, nt_load);
@@ -1137,20 +1137,10 @@ __device__ __forceinline__ void sweep_tb_tile(const Args& a, const Tile& t, cons
         const int x = t.x0 + lx, y = t.y0 + ly;
         if (x >= nx || y >= ny) continue;
         const int n = y * nx + x;
-        const int c = kC1 ? int(c1[(ly + 1) * Sh::kRW + lx + 1]) : int(cls[n]);
+        const int c = c1[(ly + 1) * Sh::kRW + lx + 1];
         if (wall_nodes(BC) && c == kWallClass) continue;
         T d[9], r[9];
-        if constexpr (kC1) {
-            pull_tb<STORE, BC, TW, TH>(d, r, f1, rho1, c1, I, x, y, lx, ly);
-        } else {
-#pragma unroll
-            for (int i = 0; i < 9; ++i) {
-                const int e = (ly + 1 - Lat<9>::ey(i)) * Sh::kRW + (lx + 1 - Lat<9>::ex(i));
-                d[i] = SS::dec(f1[i][e], I.inv_scale);
-                if constexpr (SS::kRho) r[i] = rho1[e];
-                else r[i] = T(0);
-            }
-        }
+        pull_tb<STORE, BC, TW, TH>(d, r, f1, rho1, c1, I, x, y, lx, ly);
         collide_store<9, STORE, BC, FORCH, NTS>(d, r, n, tb + c * tcols, I, g, omega, cforce, dst);
     }
 }
@@ -1162,11 +1152,10 @@ __global__ __launch_bounds__(kBlock) void k_sweep9tb(Args a)
     using T = typename SS::T;
     using Sh = TbShape<TW, TH>;
     constexpr int NT = tab_cols<BC, FORCH>();
-    constexpr bool kC1 = face_walls(BC) || wall_nodes(BC) || pressure_faces(BC);
     __shared__ T tab[kClasses * NT];
     __shared__ typename SS::S f1[9][Sh::kRegion];
     __shared__ float rho1[SS::kRho ? Sh::kRegion : 1];
-    __shared__ uint8_t c1[kC1 ? Sh::kRegion : 1];
+    __shared__ uint8_t c1[Sh::kRegion];
     const int tid = (a.cache & 4) ? (int)blockIdx.x : xcd_tile(blockIdx.x, gridDim.x);
     const Tile t = a.tiles[tid];
     if (!a.active[t.inst]) return;

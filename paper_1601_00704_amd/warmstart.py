@@ -57,12 +57,12 @@ class Batch:
                       for i, m in zip(insts, maps)]
         self.s = g.Solver(self.descs, maps)
         if store == "f32":
-            # two time steps per launch on 64 x 8 tiles (cache policy 79): the fastest
+            # two time steps per launch on 64 x 8 tiles (cache policy 71): the fastest
             # measured setting of the FP32 sweep on these maps, bitwise equal to one step
             # per launch
             self.s.set_option(g.GLBM_OPT_TILE_WIDTH, 64)
             self.s.set_option(g.GLBM_OPT_TILE_ROWS, 8)
-            self.s.set_option(g.GLBM_OPT_CACHE, 79)
+            self.s.set_option(g.GLBM_OPT_CACHE, 71)
         for k, inst in enumerate(insts):
             r_iom, r_om = inst.radii()
             eps, kl = g.glbm_class_table(g.gas_params(inst), r_iom, r_om)

@@ -309,7 +309,7 @@ def test_two_step_sweep_bitwise(gpu, store, shape, tile, forch, timing):
     G = (2e-5, -1e-5, 0)
     applies = tile in TWO_STEP_TILES[store]
     out = []
-    for cache, every in ((13, 100), (77, 100), (79, 100), (13, 102), (77, 102)):
+    for cache, every in ((13, 100), (77, 100), (79, 100), (13, 102), (77, 102), (69, 100), (71, 102), (65, 100)):
         print("case store=%s shape=%s tile=%s forch=%d timing=%d cache=%d every=%d"
               % (store, shape, tile, forch, timing, cache, every), flush=True)
         s = gpu_solver(g, 9, cls, eps, k, f_eps=fe if forch else None, G=G, store=store, tile=tile, cache=cache,
@@ -327,7 +327,7 @@ def test_two_step_sweep_bitwise(gpu, store, shape, tile, forch, timing):
             assert nl == 3 * every + 6
         s.close()
         out.append((p, r[0], st[0], every))
-    for a, b in ((0, 1), (0, 2), (3, 4)):
+    for a, b in ((0, 1), (0, 2), (3, 4), (0, 5), (3, 6), (0, 7)):
         assert np.array_equal(out[a][0], out[b][0])
         assert out[a][1] == out[b][1] and out[a][2] == out[b][2]
 

@@ -147,7 +147,7 @@ def test_pressure_two_step_bitwise(gpu, store, axis, shape, tile, walls, timing)
     pr = oracle.Pressure(axis=axis, rho_in=1.0005, rho_out=0.9995, k_const=A, k_kn=B, k_surf=C, lang_b=b,
                          p_in=0.2e6, p_out=0.1e6)
     out = []
-    for cache, every in ((13, 100), (77, 100), (79, 100), (13, 102), (77, 102)):
+    for cache, every in ((13, 100), (77, 100), (79, 100), (13, 102), (77, 102), (69, 100), (71, 102), (65, 100)):
         print("case store=%s axis=%d shape=%s tile=%s walls=%.2f timing=%d cache=%d every=%d"
               % (store, axis, shape, tile, walls, timing, cache, every), flush=True)
         s = gpu_solver(g, 9, cls, eps, k, G=(0, 0, 0), store=store, tile=tile, cache=cache, check_every=every,
@@ -166,7 +166,7 @@ def test_pressure_two_step_bitwise(gpu, store, axis, shape, tile, walls, timing)
             assert nl == 3 * every + 6
         s.close()
         out.append((p, r[0], st[0], kk[axis]))
-    for a, b2 in ((0, 1), (0, 2), (3, 4)):
+    for a, b2 in ((0, 1), (0, 2), (3, 4), (0, 5), (3, 6), (0, 7)):
         assert np.array_equal(out[a][0], out[b2][0])
         assert out[a][1:] == out[b2][1:]
 
