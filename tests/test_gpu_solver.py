@@ -185,10 +185,12 @@ def _pops(s, inst=0):
     return s.populations(inst).copy()
 
 
-def test_batch_equals_single_bitwise(gpu):
+@pytest.mark.parametrize("cache", [13, 71])
+def test_batch_equals_single_bitwise(gpu, cache):
     """Each instance of an uneven batch evolves bitwise as it does alone, at the same tile
     shape (the default tile width follows the widest instance of a context, and the FP64
-    partial sums of the residual and the flux are grouped per tile)."""
+    partial sums of the residual and the flux are grouped per tile), with one or two time
+    steps per launch."""
     g = gpu
     shapes = [(40, 64), (33, 100), (64, 128)]
     cases = [random_case(sh, seed=50 + i) for i, sh in enumerate(shapes)]
@@ -197,6 +199,7 @@ def test_batch_equals_single_bitwise(gpu):
     sb = g.Solver(descs, [c[0] for c in cases])
     sb.set_option(g.GLBM_OPT_TILE_WIDTH, 64)
     sb.set_option(g.GLBM_OPT_TILE_ROWS, 4)
+    sb.set_option(g.GLBM_OPT_CACHE, cache)
     for i, c in enumerate(cases):
         sb.set_local_perm(c[1][:255], c[2][:255], inst=i)
     sb.step(350)
@@ -205,7 +208,7 @@ def test_batch_equals_single_bitwise(gpu):
     pb = [_pops(sb, i) for i in range(3)]
     sb.close()
     for i, c in enumerate(cases):
-        ss = gpu_solver(g, 9, c[0], c[1], c[2], G=G[i], store="f32", tile=(64, 4))
+        ss = gpu_solver(g, 9, c[0], c[1], c[2], G=G[i], store="f32", tile=(64, 4), cache=cache)
         ss.step(350)
         r1, st1 = ss.residual()
         assert np.array_equal(_pops(ss), pb[i])
@@ -332,14 +335,21 @@ def test_two_step_sweep_bitwise(gpu, store, shape, tile, forch, timing):
         assert out[a][1] == out[b][1] and out[a][2] == out[b][2]
 
 
-def test_batch_per_instance_convergence(gpu):
-    """Instances stop individually at their own first check with r <= tol."""
+@pytest.mark.parametrize("tile", [None, (64, 4, 77)])
+def test_batch_per_instance_convergence(gpu, tile):
+    """Instances stop individually at their own first check with r <= tol, also with two
+    time steps per launch (tiles of a stopped instance are skipped inside the launches)."""
     g = gpu
     cls_a, eps, k, _ = random_case((32, 64), seed=3, k_range=(5e-2, 5e-1))
     cls_b = si.uniform_classes((16, 64), 1)
     descs = [g.make_desc(c.shape, store=g.GLBM_STORE_F64, g=(1e-6, 0, 0), check_every=100) for c in (cls_a, cls_b)]
     s = g.Solver(descs, [cls_a, cls_b])
     s.set_local_perm(eps[:255], k[:255])
+    if tile:
+        s.set_option(g.GLBM_OPT_TILE_WIDTH, tile[0])
+        s.set_option(g.GLBM_OPT_TILE_ROWS, tile[1])
+        s.set_option(g.GLBM_OPT_CACHE, tile[2])
+        assert g.glbm_sweeps_per_launch(s.ctx) == 2
     rc = s.step(100000, tol=1e-10)
     r, st = s.residual()
     s.close()
