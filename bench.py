@@ -625,7 +625,9 @@ def main():
 
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed steps (default: 80 for the benchmark line, at least 8000 sweeps and about "
+                         "1 s of timed work; 10 for the other workloads)")
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--side", type=int, default=4096)
     ap.add_argument("--store", default=None, choices=("f32", "f16dev", "f16loc", "f32loc", "f64"),
@@ -659,6 +661,8 @@ def main():
     args = ap.parse_args()
     if args.store is None:
         args.store = "f64" if args.workload == "studies" else "f32"
+    if args.steps is None:
+        args.steps = 80 if args.workload == "shale4096" else 10
     if args.pmc_summary:
         pmc_summary(*args.pmc_summary, args)
         return
