@@ -258,6 +258,7 @@ def time_to_converge(store="f32", n=8, side=512, tol=1e-8, max_steps=2000000):
                      "steps": [int(v) for v in stw], "steps_median": float(np.median(stw))},
             "speedup_wall": round(wc / (ww + ti), 4), "steps_ratio_median": round(float(np.median(stc / stw)), 4),
             "k_rel_diff_max": float(kd.max()),
+            "percolates_x": [g.glbm_pore_percolates(m, 1) for m in maps],
             "network": {"weights": "paper_1601_00704_amd/weights/warmstart_cnn.npy", "trained_by": manifest["command"],
                         "train_side": manifest["side"], "final_loss": manifest["final_loss"]}}
 
@@ -361,7 +362,8 @@ def run_batch(args):
                        "n_c=%d-sweep chunk + FP64 per-instance checks" % (len(maps), sides, args.store.upper(), N_C),
            "instances": len(maps), "nodes": N, "sweeps_per_step": N_C, "graph": True,
            "tile": tile,
-           "median_residual": float(np.median(r)), "steps_total": int(st.max())}
+           "median_residual": float(np.median(r)), "steps_total": int(st.max()),
+           "percolating_instances": int(sum(g.glbm_pore_percolates(m, 1) for m in maps))}
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
             "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic_from_profile(workload_key(args)[0]),
             "kernel": "%s over the flat tile list" % sweep_kernel(9, args.store, per),
@@ -469,7 +471,7 @@ def run_pressure(args):
     cfg = {"workload": "D2Q9 GLBM %dx%d QSGS map (TOC 0.10), pressure faces on x 10.5 -> 9.5 MPa, K_app(P) at every "
                        "node, %s populations" % (args.side, args.side, args.store.upper()),
            "nodes": N, "sweeps_per_step": N_C, "steps_total": int(st[0]), "residual": float(r[0]),
-           "k_p_lattice": float(kx), "tile": tile}
+           "k_p_lattice": float(kx), "percolates_x": g.glbm_pore_percolates(cls, 1), "tile": tile}
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
             "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None,
             "kernel": "%s, pressure faces + K(P)" % sweep_kernel(9, args.store, per), "bytes_per_lu": bpl,
@@ -656,6 +658,9 @@ def main():
     ap.add_argument("--converge-problems", type=int, default=8)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run only a plain 1 GiB elementwise copy (counter calibration)")
+    ap.add_argument("--record", default=None, metavar="PATH",
+                    help="append a JSON record of the run (workload, seed, steps, r, k, throughput, HBM fraction, "
+                         "wall time, oracle rate, host threads) to PATH")
     ap.add_argument("--pmc-summary", nargs=4, metavar=("FETCH", "WRITE", "COPY_FETCH", "COPY_WRITE"),
                     help="summarise rocprofv3 --pmc output directories into profiles/")
     args = ap.parse_args()
@@ -669,24 +674,39 @@ def main():
     if args.calibrate_copy:
         calibrate_copy()
         return
-    if args.workload == "batch":
-        print(json.dumps(run_batch(args)), flush=True)
-        return
-    if args.workload == "d3q19":
-        print(json.dumps(run_d3q19(args)), flush=True)
-        return
-    if args.workload == "cnn":
-        print(json.dumps(run_cnn(args)), flush=True)
-        return
-    for name, fn in (("pressure", run_pressure), ("gmm", run_gmm), ("studies", run_studies)):
-        if args.workload == name:
-            print(json.dumps(fn(args)), flush=True)
-            return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the GLBM hot path here is built and timed on a single "
               "MI355X; sharding over several GPUs is not implemented.", file=sys.stderr)
         sys.exit(2)
+    runs = {"batch": run_batch, "d3q19": run_d3q19, "cnn": run_cnn, "pressure": run_pressure, "gmm": run_gmm,
+            "studies": run_studies, "shale4096": run_shale4096}
+    line = runs[args.workload](args)
+    print(json.dumps(line), flush=True)
+    if args.record:
+        append_record(args.record, args, line)
 
+
+def append_record(path, args, line):
+    """Append one JSON line per run to `path`: the workload, its seed where it has one,
+    the solver's state and k, the throughput and HBM fraction, the wall time, the oracle's
+    CPU rate and the host's thread count."""
+    cfg = line.get("config", {})
+    roof = line.get("roofline") or {}
+    cpu = line.get("cpu_baseline") or {}
+    rec = {"time": time.strftime("%Y-%m-%dT%H:%M:%S"), "workload": args.workload, "config": cfg.get("workload"),
+           "store": args.store, "seed": cfg.get("seed"), "steps_total": cfg.get("steps_total"),
+           "residual": cfg.get("residual", cfg.get("median_residual")), "k_lattice": cfg.get("k_lattice"),
+           "k_m2": cfg.get("k_m2"), "k_mD": cfg.get("k_mD"), "percolates_x": cfg.get("percolates_x"),
+           "metric": line.get("metric"), "value": line.get("value"), "unit": line.get("unit"),
+           "hbm_frac": roof.get("frac"), "wall_s": round(line.get("ms_per_step", 0.0) * line.get("steps", 0) / 1e3, 3),
+           "oracle_mlups": cpu.get("value"), "host_threads": os.cpu_count()}
+    with open(path, "a") as fh:
+        fh.write(json.dumps(rec) + "\n")
+
+
+def run_shale4096(args):
+    """The benchmark line: the 4096^2 D2Q9 map, autotuned, timed over args.steps checks of
+    n_c sweeps each, then the time-to-converge leg and the oracle's CPU rate."""
     import numpy as np
     import torch
     import shale_inputs as si
@@ -754,7 +774,9 @@ def main():
                                "populations, n_c=%d sweeps + FP64 residual/flux per step"
                                % (args.side, args.side, args.store.upper(), N_C),
                    "nodes": N, "sweeps_per_step": N_C, "steps_total": int(st[0]),
-                   "residual": float(r[0]), "k_lattice": float(kk[0]), "tile": tile},
+                   "residual": float(r[0]), "k_lattice": float(kk[0]), "seed": inst.seed,
+                   "k_m2": float(kk[0]) * inst.dx ** 2, "k_mD": float(kk[0]) * inst.dx ** 2 / 9.869233e-13 * 1e3,
+                   "percolates_x": g.glbm_pore_percolates(cls, 1), "tile": tile},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": round(achieved / PEAK_HBM_GBS, 4),
                      "traffic": traffic,
@@ -783,7 +805,7 @@ def main():
                                    "%d steps of the same crop on 1 thread (%.1f s)" % (max(args.cpu_steps // 16, 20),
                                                                                       dt1),
                                "cpu_model": cpu_model(), "host_threads": os.cpu_count()}
-    print(json.dumps(out), flush=True)
+    return out
 
 
 if __name__ == "__main__":

@@ -71,7 +71,9 @@ enum {
     GLBM_EDEVICE = -3,       /* a HIP runtime call failed */
     GLBM_ESTATE = -4,        /* call out of order (e.g. stepping before glbm_set_local_perm) */
     GLBM_ENONFINITE = -5,    /* a NaN or Inf population was seen by a check */
-    GLBM_ENOTCONVERGED = -6  /* glbm_step_n reached its step budget with tol > 0 unmet */
+    GLBM_ENOTCONVERGED = -6, /* glbm_step_n reached its step budget with tol > 0 unmet */
+    GLBM_EUNSTABLE = -7      /* a check saw a node velocity |u| > 0.1 (lattice units): outside the
+                                low-Mach range where the equilibrium of Eq. (30) holds */
 };
 
 #define GLBM_WALL_CLASS 255           /* class code of a solid wall node (no fluid) */
@@ -188,8 +190,10 @@ int glbm_set_pressure_perm(glbm_ctx ctx, int32_t inst, int32_t n_classes, const 
  * fluid nodes (FP64 sums) and the Darcy flux.  tol <= 0: exactly n steps.
  * tol > 0: an instance stops at the first check with r <= tol; the call
  * returns when all instances have stopped (GLBM_OK) or after n steps
- * (GLBM_ENOTCONVERGED).  GLBM_ENONFINITE if a check saw NaN/Inf.
- * GLBM_ESTATE before glbm_set_local_perm.
+ * (GLBM_ENOTCONVERGED).  GLBM_ENONFINITE if a check saw NaN/Inf;
+ * GLBM_EUNSTABLE if a check saw |u| > 0.1 at a fluid node (the state is kept
+ * as of that check, stepping stops there).  GLBM_ESTATE before
+ * glbm_set_local_perm.
  */
 int glbm_step_n(glbm_ctx ctx, int64_t n, double tol);
 
@@ -420,6 +424,24 @@ int glbm_gmm_fit(int32_t n_sets, const int64_t* offsets, const double* x_dev, in
  * a non-finite input).
  */
 int glbm_radius_bins(double mu_ln, double sigma_ln, int32_t n, double* r_out);
+
+/*
+ * Whether the open pores (class 0) of a class map connect the two faces
+ * normal to the drive axis: a chain of open-pore nodes, each linked to the
+ * next by a velocity of the lattice (D2Q9: the 8 neighbours; D3Q19: the 18
+ * face and edge neighbours), from coordinate 0 to coordinate n - 1 of that
+ * axis, with the other axes periodic.  Near the site-percolation threshold of
+ * that neighbourhood the k of random maps is bimodal across seeds (an
+ * open-pore path or none); this flag tells the two branches apart.
+ *   lattice, nx, ny, nz   as in glbm_instance_desc (nz = 1 for D2Q9)
+ *   cls                   host class map, x fastest (not retained)
+ *   axis                  1 = x, 2 = y, 3 = z (as pressure_axis)
+ *   percolates            receives 1 or 0
+ * Host only; no device work.  Errors: GLBM_EINVAL (null pointers, empty grid,
+ * an unknown lattice, nz != 1 for D2Q9, axis out of range).
+ */
+int glbm_pore_percolates(int32_t lattice, int32_t nx, int32_t ny, int32_t nz, const uint8_t* cls, int32_t axis,
+                         int32_t* percolates);
 
 #ifdef __cplusplus
 }

@@ -14,7 +14,7 @@ LIB = os.path.join(LIBDIR, "libglbm.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
-SOURCES = ["glbm_kernels.hip", "glbm_api.cpp", "glbm_physics.cpp", "glbm_cnn.hip", "glbm_gmm.hip"]
+SOURCES = ["glbm_kernels.hip", "glbm_api.cpp", "glbm_physics.cpp", "glbm_geometry.cpp", "glbm_cnn.hip", "glbm_gmm.hip"]
 
 # Packed-FP32 instructions are kept out of every code object; plain float code
 # otherwise compiles to them at -O3.  Multiply-adds are fused only within one

@@ -820,6 +820,7 @@ int glbm_step_n(glbm_ctx c, int64_t n, double tol)
         if (rc) return rc;
     }
     bool nonfinite = false;
+    int unstable = -1;  // first instance whose check saw |u| > kUMax
     int64_t left = n;
     auto any_active = [&]() {
         for (int i = 0; i < c->n_inst; ++i)
@@ -880,9 +881,10 @@ int glbm_step_n(glbm_ctx c, int64_t n, double tol)
                 if (!c->active_h[i]) continue;
                 c->snap_step[i] = c->steps[i];
                 if (!std::isfinite(c->res_p[i * kPartW + P_R]) && c->res_p[i * kPartW + P_BAD] > 0) nonfinite = true;
+                if (c->res_p[i * kPartW + P_FAST] > 0 && unstable < 0) unstable = i;
                 c->active_h[i] = c->active_p[i];
             }
-            if (nonfinite) break;
+            if (nonfinite || unstable >= 0) break;
         }
     }
     if (c->timing) {
@@ -896,6 +898,9 @@ int glbm_step_n(glbm_ctx c, int64_t n, double tol)
     rc = joined.done();
     if (rc) return rc;
     if (nonfinite) return fail(GLBM_ENONFINITE, "non-finite populations detected");
+    if (unstable >= 0)
+        return fail(GLBM_EUNSTABLE, "instance %d: %.0f nodes with |u| > %g at step %lld (outside the low-Mach range)",
+                    unstable, c->res_p[unstable * kPartW + P_FAST], kUMax, (long long)c->steps[unstable]);
     if (tol > 0.0 && any_active()) return fail(GLBM_ENOTCONVERGED, "step budget reached before r <= %g", tol);
     return GLBM_OK;
 }

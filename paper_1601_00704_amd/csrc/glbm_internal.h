@@ -15,7 +15,7 @@ constexpr int kMaxTileW = 1024;
 constexpr int kClasses = 256;
 constexpr int kWallClass = 255;
 constexpr int kTabW = 8;            // constants per class in the device table
-constexpr int kPartW = 8;           // doubles per tile partial / instance result
+constexpr int kPartW = 16;          // doubles per tile partial / instance result (slots below)
 
 // Per-class constants (index into a row of kTabW values).
 enum TabSlot {
@@ -44,7 +44,13 @@ enum PartSlot {
     P_BAD = 5,   // count of non-finite nodes
     P_R = 6,     // residual (instance record only)
     P_NCHK = 7,  // checks done (instance record only)
+    P_FAST = 8,  // count of nodes with |u| > kUMax (the instability guard)
 };
+
+// Instability guard: a check that sees a node velocity above this (lattice
+// units; the sound speed is 1/sqrt(3)) ends glbm_step_n with GLBM_EUNSTABLE,
+// since the equilibrium of Eq. (30) holds only at low Mach numbers.
+constexpr double kUMax = 0.1;
 
 // Population layout.  FP64 and FP32 stores keep the q values of kBlk
 // consecutive nodes together, as q runs of kBlk elements (node blocks): the

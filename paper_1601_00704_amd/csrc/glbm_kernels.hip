@@ -1213,7 +1213,7 @@ __device__ __forceinline__ void observe_tile(const Args& a, const Tile& t, const
     const T g[3] = {inst_g<T>(I, 0), inst_g<T>(I, 1), inst_g<T>(I, 2)};
     const int twm = (1 << a.tw_log2) - 1;
     const int z = t.z0;
-    double acc[6] = {0, 0, 0, 0, 0, 0};
+    double acc[7] = {0, 0, 0, 0, 0, 0, 0};  // P_SD .. P_BAD, then the count for P_FAST
 
     for (int sl = 0; sl < a.nslot; ++sl) {
         const int slot = sl * kBlock + threadIdx.x;
@@ -1245,15 +1245,19 @@ __device__ __forceinline__ void observe_tile(const Args& a, const Tile& t, const
             acc[P_UX + k] += double(s.u[k]);
         }
         if (!(finite(s.drho) && finite(s.u[0]) && finite(s.u[1]) && finite(s.u[2]))) acc[P_BAD] += 1.0;
+        const double u2 = double(s.u[0]) * double(s.u[0]) + double(s.u[1]) * double(s.u[1]) +
+                          double(s.u[2]) * double(s.u[2]);
+        if (u2 > kUMax * kUMax) acc[6] += 1.0;
         if (mode & 1)
 #pragma unroll
             for (int k = 0; k < 3; ++k) snap[k * N + n] = s.u[k];
     }
-    block_sum<6>(acc, red);
+    block_sum<7>(acc, red);
     if (threadIdx.x == 0) {
         double* p = a.part + (size_t)tid * kPartW;
 #pragma unroll
         for (int k = 0; k < 6; ++k) p[k] = acc[k];
+        p[P_FAST] = acc[6];
     }
 }
 
@@ -1264,7 +1268,7 @@ __global__ __launch_bounds__(kBlock) void k_observe(Args a, int mode, int all)
     using T = typename St<STORE>::T;
     constexpr int NT = tab_cols<BC, FORCH>();
     __shared__ T tab[kClasses * NT];
-    __shared__ double red[4 * 6];
+    __shared__ double red[4 * 7];
 
     const int tid = (a.cache & 4) ? (int)blockIdx.x : xcd_tile(blockIdx.x, gridDim.x);
     const Tile t = a.tiles[tid];
@@ -1296,7 +1300,7 @@ __global__ __launch_bounds__(kFinBlock) void k_finalize(Args a, double tol, int 
     const InstDev& I = a.inst[inst];
     const int k = threadIdx.x % kPartW, t0 = threadIdx.x / kPartW;
     double acc = 0.0;
-    if (k < 6 && t0 < I.ntiles) {
+    if ((k < 6 || k == P_FAST) && t0 < I.ntiles) {
         // element (t0 + kFinTiles * j) * kPartW + k of the instance's partials
         const double* p = a.part + (size_t)I.tile0 * kPartW + threadIdx.x;
         const int nj = (I.ntiles - 1 - t0) / kFinTiles + 1;
@@ -1323,6 +1327,7 @@ __global__ __launch_bounds__(kFinBlock) void k_finalize(Args a, double tol, int 
         double* res = a.res + (size_t)inst * kPartW;
 #pragma unroll
         for (int c = 0; c < 6; ++c) res[c] = out[c];
+        res[P_FAST] = red[P_FAST];
         if (with_r) {
             const double r = sqrt(out[P_SD]) / (double(a.dsteps[inst]) * sqrt(out[P_SU]));
             res[P_R] = (out[P_SU] > 0.0) ? r : INFINITY;

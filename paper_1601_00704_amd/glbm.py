@@ -20,8 +20,8 @@ LIB_PATH = os.path.join(_HERE, "lib", "libglbm.so")
 
 GLBM_D2Q9, GLBM_D3Q19 = 9, 19
 GLBM_STORE_F64, GLBM_STORE_F32, GLBM_STORE_F16DEV, GLBM_STORE_F16LOC, GLBM_STORE_F32LOC = 0, 1, 2, 3, 4
-GLBM_OK, GLBM_EINVAL, GLBM_ENOMEM, GLBM_EDEVICE, GLBM_ESTATE, GLBM_ENONFINITE, GLBM_ENOTCONVERGED = \
-    0, -1, -2, -3, -4, -5, -6
+GLBM_OK, GLBM_EINVAL, GLBM_ENOMEM, GLBM_EDEVICE, GLBM_ESTATE, GLBM_ENONFINITE, GLBM_ENOTCONVERGED, GLBM_EUNSTABLE = \
+    0, -1, -2, -3, -4, -5, -6, -7
 GLBM_WALL_CLASS = 255
 GLBM_SCALE_AUTO = -2147483648
 GLBM_OPT_GRAPH, GLBM_OPT_TIMING, GLBM_OPT_TILE_ROWS, GLBM_OPT_TILE_WIDTH, GLBM_OPT_CACHE = 1, 2, 3, 4, 5
@@ -42,7 +42,7 @@ EXPORTS = ("glbm_required_bytes", "glbm_init_geometry", "glbm_set_local_perm", "
            "glbm_residual", "glbm_permeability", "glbm_set_fields", "glbm_set_fields_device",
            "glbm_get_fields", "glbm_get_populations", "glbm_state_bytes", "glbm_save_state",
            "glbm_load_state", "glbm_set_option", "glbm_sweep_time", "glbm_sweeps_per_launch", "glbm_autotune",
-           "glbm_velocity_set", "glbm_destroy", "glbm_last_error", "glbm_class_table",
+           "glbm_velocity_set", "glbm_destroy", "glbm_last_error", "glbm_class_table", "glbm_pore_percolates",
            "glbm_conv3x3_forward", "glbm_conv3x3_flip_weights", "glbm_conv3x3_wgrad_workspace",
            "glbm_conv3x3_backward_weight", "glbm_cnn_create", "glbm_cnn_destroy", "glbm_cnn_num_params",
            "glbm_cnn_get_params", "glbm_cnn_set_params", "glbm_cnn_get_grads", "glbm_cnn_forward",
@@ -103,6 +103,7 @@ def _load():
         "glbm_sweeps_per_launch": (i32, [vp, vp]),
         "glbm_autotune": (i32, [vp, i32, vp]),
         "glbm_velocity_set": (i32, [i32, vp, vp]),
+        "glbm_pore_percolates": (i32, [i32, i32, i32, i32, vp, i32, vp]),
         "glbm_destroy": (i32, [vp]),
         "glbm_last_error": (ctypes.c_char_p, []),
         "glbm_class_table": (i32, [vp, i32, vp, i32, vp, vp, vp]),
@@ -276,6 +277,18 @@ def glbm_sweeps_per_launch(ctx) -> int:
     n = ctypes.c_int32()
     _check(_lib.glbm_sweeps_per_launch(ctx, ctypes.byref(n)))
     return n.value
+
+
+def glbm_pore_percolates(cls, axis: int = 1, lattice: int = None) -> bool:
+    """Whether the open pores (class 0) of a class map ((ny, nx) or (nz, ny, nx)) connect
+    the two faces of the drive axis (1 = x, 2 = y, 3 = z)."""
+    c = np.ascontiguousarray(cls, dtype=np.uint8)
+    if lattice is None:
+        lattice = GLBM_D2Q9 if c.ndim == 2 else GLBM_D3Q19
+    nz, ny, nx = (1,) + c.shape if c.ndim == 2 else c.shape
+    out = ctypes.c_int32()
+    _check(_lib.glbm_pore_percolates(lattice, nx, ny, nz, _ptr(c), axis, ctypes.byref(out)))
+    return bool(out.value)
 
 
 def glbm_autotune(ctx, steps: int = 20):

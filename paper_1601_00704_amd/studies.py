@@ -79,7 +79,8 @@ def solve_study(cases, maps=None, store="f64", tol=1e-8, max_steps=3000000, tile
     out = []
     for i, c in enumerate(cases):
         kp = float(k[i]) * c.dx ** 2
-        out.append({"name": c.name, **c.labels, "steps": int(st[i]), "residual": float(r[i]),
+        out.append({"name": c.name, **c.labels, "percolates_x": g.glbm_pore_percolates(maps[i], 1),
+                    "steps": int(st[i]), "residual": float(r[i]),
                     "k_lattice": float(k[i]), "k_m2": kp, "k_mD": kp / DARCY_M2 * 1e3})
     lups = float(sum(int(m.size) * int(st[i]) for i, m in enumerate(maps)))
     return out, {"rc": int(rc), "wall_s": wall, "lattice_updates": lups, "max_steps": int(st.max())}

@@ -737,3 +737,27 @@ def test_degenerate_open_pore_domain(gpu, store):
     for a in range(2):
         assert np.allclose(u[a], G[a] * (t + 0.5), rtol=tol, atol=0), (a, u[a][:3], G[a] * (t + 0.5))
     assert np.abs(rho - 1.0).max() < (1e-14 if store == "f64" else 1e-6)
+
+
+@pytest.mark.parametrize("store,cache", [("f64", 13), ("f32", 13), ("f32", 77), ("f32loc", 13)])
+def test_instability_guard(gpu, store, cache):
+    """Without a matrix the drive accelerates every node as u(t) = G (t + 1/2) (the
+    degenerate case above).  With G = 4e-4 that stays below |u| = 0.1 at the checks after
+    100 and 200 steps and passes it at the check after 300 (u = 0.1202), where
+    glbm_step_n stops with GLBM_EUNSTABLE and keeps the state of that check."""
+    g = gpu
+    cls = si.uniform_classes((16, 64), 0)
+    eps, k = np.ones(256), np.full(256, np.inf)
+    G = (4e-4, 0.0, 0.0)
+    s = gpu_solver(g, 9, cls, eps, k, G=G, store=store, check_every=100, tile=(64, 4), cache=cache)
+    try:
+        assert s.step(200) == g.GLBM_OK
+        with pytest.raises(g.GlbmError) as err:
+            s.step(1000)
+        assert err.value.code == g.GLBM_EUNSTABLE
+        _, st = s.residual()
+        assert st[0] == 300
+        rho, u = s.fields()
+        assert np.allclose(u[0], G[0] * 300.5, rtol=1e-4, atol=0)
+    finally:
+        s.close()
