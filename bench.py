@@ -658,6 +658,8 @@ def main():
     ap.add_argument("--converge-problems", type=int, default=8)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run only a plain 1 GiB elementwise copy (counter calibration)")
+    ap.add_argument("--forchheimer", action="store_true",
+                    help="benchmark line with the inertial drag of Eq. 27 on every matrix class (Ergun F_eps)")
     ap.add_argument("--record", default=None, metavar="PATH",
                     help="append a JSON record of the run (workload, seed, steps, r, k, throughput, HBM fraction, "
                          "wall time, oracle rate, host threads) to PATH")
@@ -723,7 +725,13 @@ def run_shale4096(args):
     d = g.make_desc(cls.shape, store=store, tau=inst.tau, g=inst.gvec(), check_every=N_C,
                     flags=opt_in(store))
     s = g.Solver([d], [cls])
-    s.set_local_perm(eps[:255], kl[:255])
+    fe = None
+    if args.forchheimer:
+        # the geometric function of the inertial drag (Eq. 27) in the Ergun form of
+        # the generalized LBE's source, F_eps = 1.75 / sqrt(150 eps^3); it acts only
+        # where K is finite (the open pores carry no drag)
+        fe = np.where(np.isfinite(kl), 1.75 / np.sqrt(150.0 * eps ** 3), 0.0)[:255]
+    s.set_local_perm(eps[:255], kl[:255], fe)
     N = cls.size
     print("setup: %dx%d map in %.1fs, store %s" % (args.side, args.side, t_geom, args.store),
           file=sys.stderr, flush=True)
@@ -776,7 +784,8 @@ def run_shale4096(args):
                    "nodes": N, "sweeps_per_step": N_C, "steps_total": int(st[0]),
                    "residual": float(r[0]), "k_lattice": float(kk[0]), "seed": inst.seed,
                    "k_m2": float(kk[0]) * inst.dx ** 2, "k_mD": float(kk[0]) * inst.dx ** 2 / 9.869233e-13 * 1e3,
-                   "percolates_x": g.glbm_pore_percolates(cls, 1), "tile": tile},
+                   "percolates_x": g.glbm_pore_percolates(cls, 1), "tile": tile,
+                   "forchheimer": "F_eps = 1.75 / sqrt(150 eps^3) per class" if args.forchheimer else None},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": round(achieved / PEAK_HBM_GBS, 4),
                      "traffic": traffic,

@@ -761,3 +761,36 @@ def test_instability_guard(gpu, store, cache):
         assert np.allclose(u[0], G[0] * 300.5, rtol=1e-4, atol=0)
     finally:
         s.close()
+
+
+@pytest.mark.parametrize("q,store,tol,rel", [(9, "f64", 1e-11, 1e-9), (9, "f32", 1e-8, 2e-5), (9, "f32loc", 1e-8, 2e-5),
+                                             (9, "f16loc", 0.0, 2e-3), (19, "f64", 1e-11, 1e-9), (19, "f32", 1e-8, 2e-5)])
+def test_inertial_regime_uniform_medium(gpu, q, store, tol, rel):
+    """Inertial regime (Eq. 27 with F_eps > 0): in a uniform periodic medium the steady
+    velocity solves (eps nu / K) u + (eps F_eps / sqrt K) u^2 = eps G, the root the oracle
+    tests pin.  With these inputs the quadratic term carries 8 % of the drag, so the
+    converged velocity is 8 % below the Darcy-Brinkman value eps G K / (eps nu) and only
+    the Forchheimer path reaches the root."""
+    g = gpu
+    eps, K, fe, G, tau = 0.5, 1.0, 1.2, 2e-3, 1.0
+    shape = (16, 32) if q == 9 else (6, 8, 10)
+    cls = np.ones(shape, np.uint8)
+    # FP16 storage: a scale of 2^20 keeps the stored parts (up to 4e-3 here) in range
+    s = gpu_solver(g, q, cls, eps, K, f_eps=fe, G=(G, 0, 0), store=store, tau=tau,
+                   scale_log2=20 if store == "f16loc" else None)
+    try:
+        if tol > 0:
+            assert s.step(400000, tol=tol) == g.GLBM_OK
+        else:
+            s.step(20000)  # FP16 storage ends at its residual floor; the velocity has settled by then
+        rho, u = s.fields()
+    finally:
+        s.close()
+    nu = (tau - 0.5) / 3.0
+    a, b = eps * fe / math.sqrt(K), eps * nu / K
+    root = (-b + math.sqrt(b * b + 4 * a * eps * G)) / (2 * a)
+    darcy = eps * G / b
+    assert darcy / root - 1 > 0.07
+    ux = u[0].ravel()
+    assert np.abs(ux - root).max() / root < rel, (ux.mean(), root)
+    assert np.abs(u[1:]).max() < rel * root
