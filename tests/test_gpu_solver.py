@@ -299,7 +299,8 @@ TWO_STEP_TILES = {"f32": {(64, 4), (64, 8), (64, 16), (128, 4), (128, 8), (256, 
 @pytest.mark.parametrize("timing", [False, True])
 @pytest.mark.parametrize("shape,tile,forch", [((48, 200), (64, 4), False), ((40, 130), (128, 8), True),
                                               ((21, 256), (256, 4), False), ((20, 50), (64, 16), False),
-                                              ((3, 130), (128, 4), True), ((64, 64), (64, 8), False)])
+                                              ((3, 130), (128, 4), True), ((64, 64), (64, 8), False),
+                                              ((1, 70), (64, 4), False), ((9, 1), (64, 8), True)])
 def test_two_step_sweep_bitwise(gpu, store, shape, tile, forch, timing):
     """Two time steps per launch with the intermediate state in LDS (cache policy bit
     6; D2Q9, periodic) gives the same bits as one step per launch (graph replay, or
