@@ -116,3 +116,20 @@ def test_largest_lattice_limit():
     # D3Q19 (q + 3 = 22): 448^3 fits, 480^3 does not
     assert g.glbm_required_bytes([_desc(g, shape=(448, 448, 448), lattice=g.GLBM_D3Q19)]) > 0
     assert g.glbm_required_bytes([_desc(g, shape=(480, 480, 480), lattice=g.GLBM_D3Q19)]) == 0
+
+
+def test_host_queries_reject_null_arguments():
+    """The host-only queries answer without a device: a null context or output is an
+    argument error, not a crash."""
+    import paper_1601_00704_amd.glbm as g
+    lib = ctypes.CDLL(g.LIB_PATH)
+    lib.glbm_sweeps_per_launch.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
+    assert lib.glbm_sweeps_per_launch(None, None) == g.GLBM_EINVAL
+    out = ctypes.c_int32(7)
+    assert lib.glbm_sweeps_per_launch(None, ctypes.byref(out)) == g.GLBM_EINVAL and out.value == 7
+    lib.glbm_pore_percolates.argtypes = [ctypes.c_int32] * 4 + [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]
+    assert lib.glbm_pore_percolates(9, 4, 4, 1, None, 1, ctypes.byref(out)) == g.GLBM_EINVAL
+    cls = np.zeros(16, np.uint8)
+    assert lib.glbm_pore_percolates(9, 4, 4, 1, cls.ctypes.data, 1, None) == g.GLBM_EINVAL
+    assert lib.glbm_pore_percolates(9, 4, 4, 1, cls.ctypes.data, 1, ctypes.byref(out)) == g.GLBM_OK
+    assert out.value == 1
