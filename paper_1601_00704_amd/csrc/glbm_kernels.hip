@@ -449,12 +449,18 @@ template <int Q, typename T> __device__ __forceinline__ T weight_defect()
 //   LOCAL = false: deviations d_i = f_i - w_i in and out.
 //   LOCAL = true (kRho stores): local parts e_i = f_i - w_i rho(x) in and out,
 //     e*_i = (1 - omega) e_i + omega w_i rho teq_i + F_i.
-// For a pair of opposite directions the equilibrium and the forcing term
-// split into a part even in e_i (shared) and an odd part (sign flipped), so
-// each pair is evaluated once.  The rest direction takes what closes the
-// zeroth moments (sum_i feq_i = rho, sum_i F_i = 0), so that rounded weights
-// cannot create or destroy mass; in the local form it also takes drho times
-// the defect 1 - sum w of the rounded weights, so that the values leaving the
+// For a pair of opposite directions, omega times the equilibrium plus the
+// forcing term splits into a part even in e_i (shared) and an odd part (sign
+// flipped), so each pair is evaluated once:
+//   even  P = w rho [e.u (omega k1 e.u + cforce k2 e.F) + C0]   (+ omega w drho
+//         for deviations), k1 = 4.5 / eps, k2 = 9 / eps,
+//         C0 = -(1.5 omega u.u + 3 cforce u.F) / eps;
+//   odd   D = 3 w rho (omega e.u + cforce e.F).
+// The rest direction takes what closes the zeroth moments (sum_i feq_i = rho,
+// sum_i F_i = 0): minus twice the sum of the pairs' even parts, the very
+// values added to the moving directions, so that rounded weights cannot
+// create or destroy mass; in the local form it also takes drho times the
+// defect 1 - sum w of the rounded weights, so that the values leaving the
 // node, w_i drho + e*_i, carry exactly its mass.
 template <int Q, typename T, bool LOCAL, typename NodeT>
 __device__ __forceinline__ void relax(T (&d)[Q], const NodeT& s, const T* tab, T omega, T cforce)
@@ -464,12 +470,10 @@ __device__ __forceinline__ void relax(T (&d)[Q], const NodeT& s, const T* tab, T
     constexpr int DIM = L::D;
     const T uu = dot<DIM>(s.u, s.u);
     const T uF = dot<DIM>(s.u, s.F);
-    const T A = T(-1.5) * ieps * uu;
-    const T B = T(-3) * ieps * uF;
-    const T k1 = T(4.5) * ieps, k2 = T(9) * ieps;
-    const T rc = s.rho * cforce;
+    const T ok1 = omega * T(4.5) * ieps, ck2 = cforce * T(9) * ieps;
+    const T C0 = -(T(1.5) * omega * uu + T(3) * cforce * uF) * ieps;
     const T omw = T(1) - omega;
-    T eq0 = s.drho, f0 = T(0);
+    T sum = T(0);
     bool first = true;
 #pragma unroll
     for (int i = 1; i < Q; ++i) {
@@ -478,23 +482,19 @@ __device__ __forceinline__ void relax(T (&d)[Q], const NodeT& s, const T* tab, T
         const T eu = edot<Q>(i, s.u);
         const T eF = edot<Q>(i, s.F);
         const T w = T(L::w(i));
-        const T wr = w * s.rho, wf = w * rc;
-        const T ev = LOCAL ? wr * (k1 * eu * eu + A) : w * s.drho + wr * (k1 * eu * eu + A);
-        const T od = T(3) * wr * eu;
-        const T evf = wf * (k2 * eu * eF + B);
-        const T odf = T(3) * wf * eF;
-        const T P = omega * ev + evf;
-        const T D = omega * od + odf;
+        const T wr = w * s.rho;
+        const T even = eu * (ok1 * eu + ck2 * eF) + C0;
+        const T P = LOCAL ? wr * even : omega * (w * s.drho) + wr * even;
+        const T D = T(3) * wr * (omega * eu + cforce * eF);
         d[i] = omw * d[i] + P + D;
         d[o] = omw * d[o] + P - D;
-        eq0 = (LOCAL && first) ? T(-2) * ev : eq0 - T(2) * ev;
-        f0 = first ? T(-2) * evf : f0 - T(2) * evf;
+        sum = first ? P : sum + P;
         first = false;
     }
     if (LOCAL)
-        d[0] = omw * d[0] + omega * eq0 + f0 + weight_defect<Q, T>() * s.drho;
+        d[0] = omw * d[0] - T(2) * sum + weight_defect<Q, T>() * s.drho;
     else
-        d[0] = omw * d[0] + omega * eq0 + f0;
+        d[0] = omw * d[0] + omega * s.drho - T(2) * sum;
 }
 
 // Columns of the class table a kernel reads (pressure faces and Forchheimer use all).
