@@ -145,11 +145,14 @@ template <typename V> __device__ __forceinline__ V* elem(V* base, uint32_t i)
     return reinterpret_cast<V*>(reinterpret_cast<B*>(base) + i * uint32_t(sizeof(V)));
 }
 
-// Element index of population i of node n (layout: glbm_internal.h).
+// Element index of population i of node n (layout: glbm_internal.h).  For
+// node blocks, ((n >> 12) q + i) 4096 + (n & 4095) written as n plus whole
+// blocks: one shift and one shift-add per node (q - 1 = 8 is a power of two
+// for D2Q9), the i term a constant.
 template <int Q, int STORE> __device__ __forceinline__ int pidx(int i, int n, int stride)
 {
     if constexpr (node_blocks(STORE))
-        return (((n >> kBlkLog2) * Q + i) << kBlkLog2) + (n & (kBlk - 1));
+        return n + (n >> kBlkLog2) * ((Q - 1) << kBlkLog2) + (i << kBlkLog2);
     else
         return i * stride + n;
 }
