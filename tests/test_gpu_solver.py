@@ -795,3 +795,43 @@ def test_inertial_regime_uniform_medium(gpu, q, store, tol, rel):
     ux = u[0].ravel()
     assert np.abs(ux - root).max() / root < rel, (ux.mean(), root)
     assert np.abs(u[1:]).max() < rel * root
+
+
+def test_uneven_batch_spot_check(gpu):
+    """Instances of the uneven batch workload's generator (sides 256-512 here, each with
+    its own class table, TOC, pressure and Langmuir inputs), stepped together in one
+    FP32 context with two time steps per launch: four of them match the oracle run
+    alone, element by element, after 200 steps (the FP32 tolerance of the parity tests,
+    3e-5 of the largest population deviation)."""
+    from helpers import oracle_problem
+    g = gpu
+    small = [i for i in (si.batch_instance(k) for k in range(64)) if max(i.shape) <= 512][:8]
+    assert len(small) == 8 and len({i.shape for i in small}) > 1
+    maps = [i.classes() for i in small]
+    tables = [kapp.class_table(i) for i in small]
+    descs = [g.make_desc(m.shape, store=g.GLBM_STORE_F32, tau=i.tau, g=i.gvec(), check_every=100)
+             for i, m in zip(small, maps)]
+    s = g.Solver(descs, maps)
+    try:
+        for j, (e, k, fe) in enumerate(tables):
+            s.set_local_perm(e[:255], k[:255], None if fe is None else np.broadcast_to(fe, (256,))[:255], inst=j)
+        s.set_option(g.GLBM_OPT_TILE_WIDTH, 64)
+        s.set_option(g.GLBM_OPT_TILE_ROWS, 8)
+        s.set_option(g.GLBM_OPT_CACHE, 71)
+        assert g.glbm_sweeps_per_launch(s.ctx) == 2
+        s.step(200)
+        pops = [s.populations(j) for j in range(len(small))]
+    finally:
+        s.close()
+    perm = oracle_order(9, g)
+    _, w = g.glbm_velocity_set(9)
+    for j in (1, 3, 5, 6):  # sides 256, 256, 512, 384
+        e, k, fe = tables[j]
+        prob = oracle_problem(9, maps[j], e, k, fe, tau=small[j].tau, G=small[j].gvec())
+        f = prob.rest()
+        prob.run(f, 200)
+        fo = f.reshape(9, -1)[perm]
+        dev = np.abs(fo - w[:, None]).max()
+        err = np.abs(pops[j] - fo).max()
+        print("instance %d shape %s: max dev %.3e, err %.3e (rel %.2e)" % (j, maps[j].shape, dev, err, err / dev))
+        assert dev > 0 and err <= 3e-5 * dev
