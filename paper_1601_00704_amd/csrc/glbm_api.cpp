@@ -468,7 +468,7 @@ int upload_table(glbm_ctx c, int inst, const std::vector<double>& row)
 
 int read_results(glbm_ctx c)
 {
-    HIPCHK(hipMemcpyAsync(c->res_p, c->res_d, (size_t)c->n_inst * kPartW * sizeof(double), hipMemcpyDeviceToHost,
+    HIPCHK(hipMemcpyAsync(c->res_p, c->res_d, (size_t)c->n_inst * kResW * sizeof(double), hipMemcpyDeviceToHost,
                           c->work));
     HIPCHK(hipMemcpyAsync(c->active_p, c->active_d, (size_t)c->n_inst * sizeof(int32_t), hipMemcpyDeviceToHost,
                           c->work));
@@ -627,11 +627,11 @@ int glbm_init_geometry(glbm_ctx* out, int32_t n_inst, const glbm_instance_desc* 
     TRYHIP(hipMalloc(&c->inst_d, n_inst * sizeof(InstDev)));
     TRYHIP(hipMalloc(&c->tab_d, (size_t)n_inst * kClasses * kTabW * c->tsz));
     TRYHIP(hipMalloc(&c->snap_d, (size_t)snap_total * c->tsz));
-    TRYHIP(hipMalloc(&c->res_d, (size_t)n_inst * kPartW * sizeof(double)));
-    TRYHIP(hipMalloc(&c->flux_d, (size_t)n_inst * kPartW * sizeof(double)));
+    TRYHIP(hipMalloc(&c->res_d, (size_t)n_inst * kResW * sizeof(double)));
+    TRYHIP(hipMalloc(&c->flux_d, (size_t)n_inst * kResW * sizeof(double)));
     TRYHIP(hipMalloc(&c->active_d, n_inst * sizeof(int32_t)));
     TRYHIP(hipMalloc(&c->dsteps_d, n_inst * sizeof(int32_t)));
-    TRYHIP(hipHostMalloc(reinterpret_cast<void**>(&c->res_p), (size_t)n_inst * kPartW * sizeof(double),
+    TRYHIP(hipHostMalloc(reinterpret_cast<void**>(&c->res_p), (size_t)n_inst * kResW * sizeof(double),
                          hipHostMallocDefault));
     TRYHIP(hipHostMalloc(reinterpret_cast<void**>(&c->active_p), n_inst * sizeof(int32_t), hipHostMallocDefault));
 
@@ -642,9 +642,9 @@ int glbm_init_geometry(glbm_ctx* out, int32_t n_inst, const glbm_instance_desc* 
     // rest state: all deviations zero (f_i = w_i, rho = 1, u = 0)
     TRYHIP(launch_zero(c->pop_base, need, c->work));
     TRYHIP(launch_zero(c->snap_d, (size_t)snap_total * c->tsz, c->work));
-    TRYHIP(launch_zero(c->res_d, (size_t)n_inst * kPartW * sizeof(double), c->work));
+    TRYHIP(launch_zero(c->res_d, (size_t)n_inst * kResW * sizeof(double), c->work));
     TRYHIP(launch_zero(c->tab_d, (size_t)n_inst * kClasses * kTabW * c->tsz, c->work));
-    for (int i = 0; i < n_inst; ++i) c->res_p[i * kPartW + P_R] = INFINITY;
+    for (int i = 0; i < n_inst; ++i) c->res_p[i * kResW + P_R] = INFINITY;
     default_tile(c);
     TRY(build_tiles(c));
     TRY(upload_state(c));
@@ -809,7 +809,7 @@ int glbm_step_n(glbm_ctx c, int64_t n, double tol)
 
     // (re)activate: everything when tol <= 0, else every instance not already below tol
     for (int i = 0; i < c->n_inst; ++i) {
-        const double r = c->res_p[i * kPartW + P_R];
+        const double r = c->res_p[i * kResW + P_R];
         c->active_h[i] = (tol > 0.0 && c->snap_valid && r <= tol && c->snap_step[i] == c->steps[i]) ? 0 : 1;
     }
     set_parities(c);
@@ -880,8 +880,8 @@ int glbm_step_n(glbm_ctx c, int64_t n, double tol)
             for (int i = 0; i < c->n_inst; ++i) {
                 if (!c->active_h[i]) continue;
                 c->snap_step[i] = c->steps[i];
-                if (!std::isfinite(c->res_p[i * kPartW + P_R]) && c->res_p[i * kPartW + P_BAD] > 0) nonfinite = true;
-                if (c->res_p[i * kPartW + P_FAST] > 0 && unstable < 0) unstable = i;
+                if (!std::isfinite(c->res_p[i * kResW + P_R]) && c->res_p[i * kResW + P_BAD] > 0) nonfinite = true;
+                if (c->res_p[i * kResW + P_FAST] > 0 && unstable < 0) unstable = i;
                 c->active_h[i] = c->active_p[i];
             }
             if (nonfinite || unstable >= 0) break;
@@ -900,7 +900,7 @@ int glbm_step_n(glbm_ctx c, int64_t n, double tol)
     if (nonfinite) return fail(GLBM_ENONFINITE, "non-finite populations detected");
     if (unstable >= 0)
         return fail(GLBM_EUNSTABLE, "instance %d: %.0f nodes with |u| > %g at step %lld (outside the low-Mach range)",
-                    unstable, c->res_p[unstable * kPartW + P_FAST], kUMax, (long long)c->steps[unstable]);
+                    unstable, c->res_p[unstable * kResW + P_FAST], kUMax, (long long)c->steps[unstable]);
     if (tol > 0.0 && any_active()) return fail(GLBM_ENOTCONVERGED, "step budget reached before r <= %g", tol);
     return GLBM_OK;
 }
@@ -911,7 +911,7 @@ int glbm_residual(glbm_ctx c, double* r, int64_t* steps)
     if (!c) return fail(GLBM_EINVAL, "null context");
     HIPCHK(hipStreamSynchronize(c->work));
     for (int i = 0; i < c->n_inst; ++i) {
-        if (r) r[i] = c->res_p[i * kPartW + P_R];
+        if (r) r[i] = c->res_p[i * kResW + P_R];
         if (steps) steps[i] = c->steps[i];
     }
     return GLBM_OK;
@@ -931,7 +931,7 @@ int glbm_permeability(glbm_ctx c, double* k)
     a.res = c->flux_d;
     HIPCHK(launch_observe(c->cfg, a, 4, c->work));
     HIPCHK(launch_finalize(a, c->n_inst, 0.0, 0, 0, c->work));
-    std::vector<double> h((size_t)c->n_inst * kPartW);
+    std::vector<double> h((size_t)c->n_inst * kResW);
     HIPCHK(hipMemcpyAsync(h.data(), c->flux_d, h.size() * sizeof(double), hipMemcpyDeviceToHost, c->work));
     HIPCHK(hipStreamSynchronize(c->work));
     for (int i = 0; i < c->n_inst; ++i) {
@@ -939,7 +939,7 @@ int glbm_permeability(glbm_ctx c, double* k)
         const glbm_instance_desc& D = c->desc[i];
         for (int d = 0; d < 3; ++d) {
             const double g = c->inst_h[i].g[d];
-            const double mean = h[i * kPartW + P_UX + d] / (double)c->n_fluid[i];
+            const double mean = h[i * kResW + P_UX + d] / (double)c->n_fluid[i];
             k[3 * i + d] = g != 0.0 ? nu * mean / g : NAN;
             if (D.pressure_axis == d + 1) {
                 // Darcy's law with the lattice pressure c_s^2 rho across the n - 1 node spacings between the faces
@@ -956,8 +956,8 @@ static int set_fields_impl(glbm_ctx c, int32_t inst, const void* rho_d, const vo
     HIPCHK(launch_set_fields(c->cfg, c->args(c->gstep), inst, c->inst_h[inst].ntiles, rho_d, u_d, is_double,
                              c->work));
     c->snap_valid = false;
-    for (int i = 0; i < c->n_inst; ++i) c->res_p[i * kPartW + P_R] = INFINITY;
-    HIPCHK(hipMemcpyAsync(c->res_d, c->res_p, (size_t)c->n_inst * kPartW * sizeof(double), hipMemcpyHostToDevice,
+    for (int i = 0; i < c->n_inst; ++i) c->res_p[i * kResW + P_R] = INFINITY;
+    HIPCHK(hipMemcpyAsync(c->res_d, c->res_p, (size_t)c->n_inst * kResW * sizeof(double), hipMemcpyHostToDevice,
                           c->work));
     HIPCHK(hipStreamSynchronize(c->work));
     return GLBM_OK;
@@ -1060,7 +1060,7 @@ size_t glbm_state_bytes(glbm_ctx c)
 {
     if (!c) return 0;
     return sizeof(CkptHeader) + c->pop_bytes + (size_t)c->snap_elems * c->tsz +
-           (size_t)c->n_inst * (kPartW * sizeof(double) + 2 * sizeof(int64_t));
+           (size_t)c->n_inst * (kResW * sizeof(double) + 2 * sizeof(int64_t));
 }
 
 int glbm_save_state(glbm_ctx c, void* host, size_t bytes)
@@ -1081,8 +1081,8 @@ int glbm_save_state(glbm_ctx c, void* host, size_t bytes)
     HIPCHK(hipMemcpyAsync(p, c->snap_d, h.snap_bytes, hipMemcpyDeviceToHost, c->work));
     p += h.snap_bytes;
     HIPCHK(hipStreamSynchronize(c->work));
-    memcpy(p, c->res_p, (size_t)c->n_inst * kPartW * sizeof(double));
-    p += (size_t)c->n_inst * kPartW * sizeof(double);
+    memcpy(p, c->res_p, (size_t)c->n_inst * kResW * sizeof(double));
+    p += (size_t)c->n_inst * kResW * sizeof(double);
     memcpy(p, c->steps.data(), c->n_inst * sizeof(int64_t));
     p += c->n_inst * sizeof(int64_t);
     memcpy(p, c->snap_step.data(), c->n_inst * sizeof(int64_t));
@@ -1109,14 +1109,14 @@ int glbm_load_state(glbm_ctx c, const void* host, size_t bytes)
     HIPCHK(hipMemcpyAsync(c->snap_d, p, h.snap_bytes, hipMemcpyHostToDevice, c->work));
     p += h.snap_bytes;
     HIPCHK(hipStreamSynchronize(c->work));
-    memcpy(c->res_p, p, (size_t)c->n_inst * kPartW * sizeof(double));
-    p += (size_t)c->n_inst * kPartW * sizeof(double);
+    memcpy(c->res_p, p, (size_t)c->n_inst * kResW * sizeof(double));
+    p += (size_t)c->n_inst * kResW * sizeof(double);
     memcpy(c->steps.data(), p, c->n_inst * sizeof(int64_t));
     p += c->n_inst * sizeof(int64_t);
     memcpy(c->snap_step.data(), p, c->n_inst * sizeof(int64_t));
     c->gstep = h.gstep;
     c->snap_valid = h.snap_valid != 0;
-    HIPCHK(hipMemcpyAsync(c->res_d, c->res_p, (size_t)c->n_inst * kPartW * sizeof(double), hipMemcpyHostToDevice,
+    HIPCHK(hipMemcpyAsync(c->res_d, c->res_p, (size_t)c->n_inst * kResW * sizeof(double), hipMemcpyHostToDevice,
                           c->work));
     set_parities(c);
     rc = upload_state(c);

@@ -15,7 +15,8 @@ constexpr int kMaxTileW = 1024;
 constexpr int kClasses = 256;
 constexpr int kWallClass = 255;
 constexpr int kTabW = 8;            // constants per class in the device table
-constexpr int kPartW = 16;          // doubles per tile partial / instance result (slots below)
+constexpr int kPartW = 8;           // doubles per tile partial (slots below)
+constexpr int kResW = 16;           // doubles per instance result (slots below)
 
 // Per-class constants (index into a row of kTabW values).
 enum TabSlot {
@@ -44,7 +45,8 @@ enum PartSlot {
     P_BAD = 5,   // count of non-finite nodes
     P_R = 6,     // residual (instance record only)
     P_NCHK = 7,  // checks done (instance record only)
-    P_FAST = 8,  // count of nodes with |u| > kUMax (the instability guard)
+    P_FAST = 8,  // count of nodes with |u| > kUMax, the instability guard (instance record)
+    P_FAST_T = 6,  // the same count in a tile partial (whose slot 6 holds no residual)
 };
 
 // Instability guard: a check that sees a node velocity above this (lattice

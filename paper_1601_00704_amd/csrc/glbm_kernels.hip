@@ -1260,7 +1260,7 @@ __device__ __forceinline__ void observe_tile(const Args& a, const Tile& t, const
         double* p = a.part + (size_t)tid * kPartW;
 #pragma unroll
         for (int k = 0; k < 6; ++k) p[k] = acc[k];
-        p[P_FAST] = acc[6];
+        p[P_FAST_T] = acc[6];
     }
 }
 
@@ -1303,7 +1303,7 @@ __global__ __launch_bounds__(kFinBlock) void k_finalize(Args a, double tol, int 
     const InstDev& I = a.inst[inst];
     const int k = threadIdx.x % kPartW, t0 = threadIdx.x / kPartW;
     double acc = 0.0;
-    if ((k < 6 || k == P_FAST) && t0 < I.ntiles) {
+    if ((k < 6 || k == P_FAST_T) && t0 < I.ntiles) {
         // element (t0 + kFinTiles * j) * kPartW + k of the instance's partials
         const double* p = a.part + (size_t)I.tile0 * kPartW + threadIdx.x;
         const int nj = (I.ntiles - 1 - t0) / kFinTiles + 1;
@@ -1327,10 +1327,10 @@ __global__ __launch_bounds__(kFinBlock) void k_finalize(Args a, double tol, int 
         double out[6];
 #pragma unroll
         for (int c = 0; c < 6; ++c) out[c] = red[c];
-        double* res = a.res + (size_t)inst * kPartW;
+        double* res = a.res + (size_t)inst * kResW;
 #pragma unroll
         for (int c = 0; c < 6; ++c) res[c] = out[c];
-        res[P_FAST] = red[P_FAST];
+        res[P_FAST] = red[P_FAST_T];
         if (with_r) {
             const double r = sqrt(out[P_SD]) / (double(a.dsteps[inst]) * sqrt(out[P_SU]));
             res[P_R] = (out[P_SU] > 0.0) ? r : INFINITY;
