@@ -68,6 +68,63 @@ __global__ void k_gmm_prepare(GmmSet* sets, int n_sets, int k)
     if (s < n_sets) prepare(sets[s], k);
 }
 
+// ln 2 split for the range reductions below: kLn2Hi holds its leading 32
+// bits (so k kLn2Hi is exact for |k| < 2^21), kLn2Lo the rest.
+constexpr double kLn2Hi = 0x1.62e42ffp-1;
+constexpr double kLn2Lo = -4.2009150726810846e-11;
+
+// e^a for a <= 0, written from the mathematics: a = k ln 2 + r with
+// |r| <= ln 2 / 2, e^r by its Taylor series to degree 13 (truncation below
+// 5e-18 relative on that interval, Horner form), then the exact scaling by
+// 2^k.  Below -745 the result is 0 (it would be a denormal or zero anyway).
+__device__ __forceinline__ double exp_nonpos(double a)
+{
+    if (a < -745.0) return 0.0;
+    const double k = rint(a * 1.4426950408889634);
+    const double r = fma(-k, kLn2Lo, fma(-k, kLn2Hi, a));
+    double p = 1.0 / 6227020800.0;
+    p = fma(p, r, 1.0 / 479001600.0);
+    p = fma(p, r, 1.0 / 39916800.0);
+    p = fma(p, r, 1.0 / 3628800.0);
+    p = fma(p, r, 1.0 / 362880.0);
+    p = fma(p, r, 1.0 / 40320.0);
+    p = fma(p, r, 1.0 / 5040.0);
+    p = fma(p, r, 1.0 / 720.0);
+    p = fma(p, r, 1.0 / 120.0);
+    p = fma(p, r, 1.0 / 24.0);
+    p = fma(p, r, 1.0 / 6.0);
+    p = fma(p, r, 0.5);
+    p = fma(p, r, 1.0);
+    p = fma(p, r, 1.0);
+    return ldexp(p, (int)k);
+}
+
+// log y for y in [1, 2], written from the mathematics: with m = y (or y / 2,
+// adding ln 2, when y > sqrt 2), s = (m - 1) / (m + 1) lies in [-0.172, 0.172]
+// and log m = 2 atanh s = 2 (s + s^3/3 + s^5/5 + ...), summed to s^23
+// (truncation below 1e-19 relative).  m - 1 is exact.
+__device__ __forceinline__ double log_1_2(double y)
+{
+    const bool big = y > 1.4142135623730951;
+    const double m = big ? 0.5 * y : y;
+    const double s = (m - 1.0) / (m + 1.0);
+    const double z = s * s;
+    double p = 1.0 / 23.0;
+    p = fma(p, z, 1.0 / 21.0);
+    p = fma(p, z, 1.0 / 19.0);
+    p = fma(p, z, 1.0 / 17.0);
+    p = fma(p, z, 1.0 / 15.0);
+    p = fma(p, z, 1.0 / 13.0);
+    p = fma(p, z, 1.0 / 11.0);
+    p = fma(p, z, 1.0 / 9.0);
+    p = fma(p, z, 1.0 / 7.0);
+    p = fma(p, z, 1.0 / 5.0);
+    p = fma(p, z, 1.0 / 3.0);
+    const double t = 2.0 * s;
+    const double lm = fma(t, z * p, t);
+    return big ? (lm + kLn2Lo) + kLn2Hi : lm;
+}
+
 template <int K>
 __global__ __launch_bounds__(kGmmBlock) void k_gmm_pass(const double* __restrict__ x, const GmmSet* __restrict__ sets,
                                                           const GmmChunk* __restrict__ chunks, double* __restrict__ part)
@@ -100,11 +157,11 @@ __global__ __launch_bounds__(kGmmBlock) void k_gmm_pass(const double* __restrict
         if constexpr (K == 2) {
             // the larger term is exp(0) = 1: one exponential, and the sum lies in
             // (1, 2], where log has no cancellation to guard against
-            const double o = exp(-fabs(t[1] - t[0]));
+            const double o = exp_nonpos(-fabs(t[1] - t[0]));
             const bool first = t[0] >= t[1];
             e[0] = first ? 1.0 : o;
             e[1] = first ? o : 1.0;
-            lse = log(1.0 + o);
+            lse = log_1_2(1.0 + o);
         } else {
             double sum = 0.0;
 #pragma unroll
