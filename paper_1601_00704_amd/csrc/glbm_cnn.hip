@@ -143,122 +143,13 @@ __global__ __launch_bounds__(kConvBlock) void k_conv_fwd(ConvArgs a)
     }
 }
 
-// ------------------------------------------------ forward, tap-major path --
-// For cin = 32 CI (every layer but the first, and the data gradient of every
-// layer with at least 32 output channels).  K runs tap by tap: a pixel's
-// neighbour address is formed once per tap, and the tap's weights [64
-// channels][cin] sit in one of two LDS buffers (one barrier per tap).  Each
-// wavefront covers MB blocks of 16 pixels, so a 32-wide slice of one tap
-// costs MB global loads, nt LDS reads and MB * nt MFMAs.  The A operands of a
-// whole tap are loaded before the barrier, overlapping their latency with the
-// staging of the weights.
-template <int CI, int MB, bool OUT_F32, bool RELU, bool ACC>
-__global__ __launch_bounds__(kConvBlock) void k_conv_fwd_tap(ConvArgs a)
-{
-    constexpr int kCin = 32 * CI;
-    constexpr int kRow = kCin + 8;  // padded LDS row (bf16)
-    // LDS rows for the weights of one tap: the 64-channel tile, or 32 rows when
-    // the layer has at most 32 output channels (MB = 4)
-    constexpr int kRows = MB == 4 ? 32 : kChTile;
-    __shared__ __attribute__((aligned(16))) uint16_t wt[2][kRows * kRow];
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int m = lane & 15, kq = lane >> 4;
-    const long long pw = (long long)blockIdx.x * (64 * MB) + wave * (16 * MB);
-    const int n0 = blockIdx.y * kChTile;
-    const int nt = min(kChTile, a.cout_pad - n0) >> 4;  // 16-channel blocks (1..4)
-    const int HW = a.H * a.W;
-
-    int py[MB], px[MB];
-    bool ok[MB];
-    const uint16_t* xb[MB];
-#pragma unroll
-    for (int mb = 0; mb < MB; ++mb) {
-        const long long p = pw + 16 * mb + m;
-        ok[mb] = p < a.npix;
-        const long long pc = ok[mb] ? p : 0;
-        const int b = int(pc / HW);
-        const int rem = int(pc - (long long)b * HW);
-        py[mb] = rem / a.W;
-        px[mb] = rem - py[mb] * a.W;
-        xb[mb] = a.x + (size_t)b * HW * a.x_pitch + a.x_off + 8 * kq;
-    }
-    f32x4 acc[MB][4];
-#pragma unroll
-    for (int mb = 0; mb < MB; ++mb)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) acc[mb][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-
-    for (int tap = 0; tap < 9; ++tap) {
-        uint16_t* w = wt[tap & 1];
-        // weights of this tap: the 16 nt rows in use from n0, columns tap * cin .. + cin
-        for (int e = threadIdx.x; e < 16 * nt * (kCin / 8); e += kConvBlock) {
-            const int r = e / (kCin / 8), c8 = (e % (kCin / 8)) * 8;
-            uint4 v = make_uint4(0, 0, 0, 0);
-            if (n0 + r < a.cout_pad)
-                v = *reinterpret_cast<const uint4*>(a.w + (size_t)(n0 + r) * a.k_pad + tap * kCin + c8);
-            *reinterpret_cast<uint4*>(&w[r * kRow + c8]) = v;
-        }
-        const int dy = tap / 3 - 1, dx = tap - 3 * (tap / 3) - 1;
-        uint4 av[MB][CI];
-#pragma unroll
-        for (int mb = 0; mb < MB; ++mb) {
-            int yy = py[mb] + dy, xx = px[mb] + dx;
-            yy += yy < 0 ? a.H : (yy >= a.H ? -a.H : 0);
-            xx += xx < 0 ? a.W : (xx >= a.W ? -a.W : 0);
-            const uint16_t* src = xb[mb] + (size_t)(yy * a.W + xx) * a.x_pitch;
-#pragma unroll
-            for (int c = 0; c < CI; ++c)
-                av[mb][c] = ok[mb] ? *reinterpret_cast<const uint4*>(src + 32 * c) : make_uint4(0, 0, 0, 0);
-        }
-        __syncthreads();
-#pragma unroll
-        for (int c = 0; c < CI; ++c) {
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                if (j < nt) {
-                    const uint4 bv = *reinterpret_cast<const uint4*>(&w[(16 * j + m) * kRow + 32 * c + 8 * kq]);
-                    const bf16x8 bf = __builtin_bit_cast(bf16x8, bv);
-#pragma unroll
-                    for (int mb = 0; mb < MB; ++mb)
-                        acc[mb][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, av[mb][c]),
-                                                                             bf, acc[mb][j], 0, 0, 0);
-                }
-            }
-        }
-    }
-    // epilogue: lane holds D[4 kq + i][m] of each 16 x 16 block
-#pragma unroll
-    for (int mb = 0; mb < MB; ++mb)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            if (j >= nt) continue;
-            const int n = n0 + 16 * j + m;
-            if (n >= a.cout) continue;
-            const float bias = a.bias ? a.bias[n] : 0.f;
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const long long q = pw + 16 * mb + 4 * kq + i;
-                if (q >= a.npix) continue;
-                float v = acc[mb][j][i] + bias;
-                if (RELU) v = fmaxf(v, 0.f);
-                if (OUT_F32) {
-                    static_cast<float*>(a.y)[(size_t)q * a.y_pitch + a.y_off + n] = v;
-                } else {
-                    uint16_t* yp = static_cast<uint16_t*>(a.y) + (size_t)q * a.y_pitch + a.y_off + n;
-                    if (ACC) v += bf2f(*yp);
-                    *yp = f2bf(v);
-                }
-            }
-        }
-}
-
 // ------------------------------------------------ forward, row-reuse path --
 // For cin = 32 CI.  A wavefront owns 16 pixels in each of R consecutive rows;
 // the workgroup's four wavefronts sit side by side (64 x R pixels).  K runs
 // over 32-channel slices of the input and, within a slice, over the column
 // shifts dx = -1, 0, 1: the slice's 16-byte fragments of the R + 2 input rows
 // at that shift are loaded once and serve every (dy, output row) pair that
-// reads them, so R + 2 loads feed 3 R NT MFMAs (the tap-major kernel spends
+// reads them, so R + 2 loads feed 3 R NT MFMAs (a tap-by-tap loop spends
 // one load per NT MFMAs).  The slice's weights for all nine taps (16 NT
 // channels x 32) sit in LDS.  The weights are the MFMA's row operand, so a
 // lane ends with four consecutive output channels of its own pixel and

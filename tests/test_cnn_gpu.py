@@ -94,7 +94,7 @@ def test_conv_forward_full_tile_grid(gpu):
 
 
 # Wider rows (128 and 256 pixels, as in the network) for every layer shape with cin a
-# multiple of 32 (tap-major kernel), ragged output channel counts included.
+# multiple of 32 (row-reuse kernel), ragged output channel counts included.
 @pytest.mark.parametrize("cin,cout,W", [(32, 32, 256), (96, 32, 256), (32, 3, 256), (96, 32, 128),
                                          (64, 128, 128), (192, 64, 128), (128, 128, 256), (64, 96, 128)])
 def test_conv_forward_wide_rows(gpu, cin, cout, W):
