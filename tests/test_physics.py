@@ -149,6 +149,30 @@ def test_langmuir_capacity_range_over_the_batch_draws():
     assert 500 < min(q) < 1000 and 8000 < max(q) < 20000
 
 
+
+@pytest.mark.parametrize("v_l,eps,toc", [(0.004, 0.3, 0.15), (0.002, 0.2, 0.05), (0.008, 0.45, 0.30),
+                                         (0.0035, 0.1, 0.9)])
+def test_langmuir_capacity_mole_balance(v_l, eps, toc):
+    """Eq. (38) against the definitions the paper gives beside it, worked out as a mole
+    balance over a bulk sample rather than through the formula: q_sat,b is the methane
+    volume (at the reference state) adsorbed per kilogram of bulk sample, TOC the
+    kerogen's volume fraction of the bulk, eps the kerogen's porosity, and q_sat,k the
+    moles of methane per cubic metre of kerogen skeleton.  Moles come from the ideal-gas
+    law at 273.15 K and 101.325 kPa (not from a density constant); the bulk density is
+    the 1650 kg/m^3 quoted with Eq. (38).  The tolerance covers the four-digit
+    methane density at the reference state.  A dropped (1 - eps), TOC on the wrong side
+    or a mass in place of a volume fails by far more."""
+    m_bulk = 3.7                          # kg of sample
+    v_bulk = m_bulk / 1650.0              # m^3 of sample
+    v_kerogen = toc * v_bulk              # m^3 of kerogen (pores included)
+    v_skeleton = (1.0 - eps) * v_kerogen  # m^3 of kerogen skeleton
+    v_gas = v_l * m_bulk                  # m^3 of methane at the reference state
+    moles = 101325.0 * v_gas / (8.314462618 * 273.15)
+    want = moles / v_skeleton
+    got = kapp.qsat_from_langmuir_volume(v_l, eps, toc)
+    assert abs(got - want) <= 1e-4 * want, (got, want)
+
+
 def test_native_pressure_coefficients_match_oracle():
     """glbm_class_table_pressure (native) against the oracle's K(P) coefficients of
     Eq. (18)-(19), class by class, and K(P) at the instance pressure equals the constant
