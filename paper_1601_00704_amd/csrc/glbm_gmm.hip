@@ -73,53 +73,71 @@ __global__ void k_gmm_prepare(GmmSet* sets, int n_sets, int k)
 constexpr double kLn2Hi = 0x1.62e42ffp-1;
 constexpr double kLn2Lo = -4.2009150726810846e-11;
 
+// Series coefficients, passed to the pass as a kernel argument so that they sit
+// in scalar registers (a literal coefficient is rebuilt in a vector register at
+// every use): 1/13!, 1/12!, ..., 1/2!, 1, 1 (Taylor series of e^r, highest
+// degree first) and 1/23, 1/21, ..., 1/3 (odd terms of atanh).
+struct GmmSeries {
+    double exp_c[14];
+    double atanh_c[11];
+};
+
+GmmSeries gmm_series()
+{
+    GmmSeries c;
+    double f = 1.0;
+    for (int n = 1; n <= 13; ++n) f *= n;  // 13!, exact in double
+    for (int n = 13; n >= 0; --n) {
+        c.exp_c[13 - n] = 1.0 / f;
+        if (n > 0) f /= n;
+    }
+    for (int j = 0; j < 11; ++j) c.atanh_c[j] = 1.0 / (23 - 2 * j);
+    return c;
+}
+
+// 1/y for y in [1, 4]: the hardware reciprocal estimate refined by two Newton
+// steps, e = 1 - y r, r <- r + r e (each step squares the relative error).  In
+// that range no operand scaling or special case arises, so the scaling and
+// fix-up steps of a full division are not needed; the result is within about
+// one unit in the last place, where a division would be correctly rounded.
+__device__ __forceinline__ double rcp_1_4(double y)
+{
+    double r = __builtin_amdgcn_rcp(y);
+    double e = fma(-y, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-y, r, 1.0);
+    return fma(r, e, r);
+}
+
 // e^a for a <= 0, written from the mathematics: a = k ln 2 + r with
 // |r| <= ln 2 / 2, e^r by its Taylor series to degree 13 (truncation below
 // 5e-18 relative on that interval, Horner form), then the exact scaling by
 // 2^k.  Below -745 the result is 0 (it would be a denormal or zero anyway).
-__device__ __forceinline__ double exp_nonpos(double a)
+__device__ __forceinline__ double exp_nonpos(double a, const GmmSeries& C)
 {
     if (a < -745.0) return 0.0;
     const double k = rint(a * 1.4426950408889634);
     const double r = fma(-k, kLn2Lo, fma(-k, kLn2Hi, a));
-    double p = 1.0 / 6227020800.0;
-    p = fma(p, r, 1.0 / 479001600.0);
-    p = fma(p, r, 1.0 / 39916800.0);
-    p = fma(p, r, 1.0 / 3628800.0);
-    p = fma(p, r, 1.0 / 362880.0);
-    p = fma(p, r, 1.0 / 40320.0);
-    p = fma(p, r, 1.0 / 5040.0);
-    p = fma(p, r, 1.0 / 720.0);
-    p = fma(p, r, 1.0 / 120.0);
-    p = fma(p, r, 1.0 / 24.0);
-    p = fma(p, r, 1.0 / 6.0);
-    p = fma(p, r, 0.5);
-    p = fma(p, r, 1.0);
-    p = fma(p, r, 1.0);
+    double p = C.exp_c[0];
+#pragma unroll
+    for (int c = 1; c < 14; ++c) p = fma(p, r, C.exp_c[c]);
     return ldexp(p, (int)k);
 }
 
 // log y for y in [1, 2], written from the mathematics: with m = y (or y / 2,
 // adding ln 2, when y > sqrt 2), s = (m - 1) / (m + 1) lies in [-0.172, 0.172]
 // and log m = 2 atanh s = 2 (s + s^3/3 + s^5/5 + ...), summed to s^23
-// (truncation below 1e-19 relative).  m - 1 is exact.
-__device__ __forceinline__ double log_1_2(double y)
+// (truncation below 1e-19 relative).  m - 1 is exact; 1 / (m + 1) comes from
+// rcp_1_4.
+__device__ __forceinline__ double log_1_2(double y, const GmmSeries& C)
 {
     const bool big = y > 1.4142135623730951;
     const double m = big ? 0.5 * y : y;
-    const double s = (m - 1.0) / (m + 1.0);
+    const double s = (m - 1.0) * rcp_1_4(m + 1.0);
     const double z = s * s;
-    double p = 1.0 / 23.0;
-    p = fma(p, z, 1.0 / 21.0);
-    p = fma(p, z, 1.0 / 19.0);
-    p = fma(p, z, 1.0 / 17.0);
-    p = fma(p, z, 1.0 / 15.0);
-    p = fma(p, z, 1.0 / 13.0);
-    p = fma(p, z, 1.0 / 11.0);
-    p = fma(p, z, 1.0 / 9.0);
-    p = fma(p, z, 1.0 / 7.0);
-    p = fma(p, z, 1.0 / 5.0);
-    p = fma(p, z, 1.0 / 3.0);
+    double p = C.atanh_c[0];
+#pragma unroll
+    for (int c = 1; c < 11; ++c) p = fma(p, z, C.atanh_c[c]);
     const double t = 2.0 * s;
     const double lm = fma(t, z * p, t);
     return big ? (lm + kLn2Lo) + kLn2Hi : lm;
@@ -127,7 +145,8 @@ __device__ __forceinline__ double log_1_2(double y)
 
 template <int K>
 __global__ __launch_bounds__(kGmmBlock) void k_gmm_pass(const double* __restrict__ x, const GmmSet* __restrict__ sets,
-                                                          const GmmChunk* __restrict__ chunks, double* __restrict__ part)
+                                                          const GmmChunk* __restrict__ chunks, double* __restrict__ part,
+                                                          GmmSeries ser)
 {
     __shared__ double red[kGmmBlock / 64][kRec];
     const GmmChunk c = chunks[blockIdx.x];
@@ -143,8 +162,12 @@ __global__ __launch_bounds__(kGmmBlock) void k_gmm_pass(const double* __restrict
     double acc[3 * K + 1];
 #pragma unroll
     for (int r = 0; r < 3 * K + 1; ++r) acc[r] = 0.0;
-    for (int64_t i = c.start + threadIdx.x; i < c.end; i += kGmmBlock) {
-        const double xi = x[i];
+    // the next sample is loaded before the current one is evaluated
+    int64_t i = c.start + threadIdx.x;
+    double xn = i < c.end ? x[i] : 0.0;
+    for (; i < c.end; i += kGmmBlock) {
+        const double xi = xn;
+        if (i + kGmmBlock < c.end) xn = x[i + kGmmBlock];
         double t[K], d[K];
         double mx = -INFINITY;
 #pragma unroll
@@ -153,15 +176,17 @@ __global__ __launch_bounds__(kGmmBlock) void k_gmm_pass(const double* __restrict
             t[j] = la[j] + nb[j] * d[j] * d[j];   // log(Phi_j g_j(x)), Eq. (21)
             mx = fmax(mx, t[j]);
         }
-        double e[K], lse;
+        double e[K], lse, inv;
         if constexpr (K == 2) {
             // the larger term is exp(0) = 1: one exponential, and the sum lies in
-            // (1, 2], where log has no cancellation to guard against
-            const double o = exp_nonpos(-fabs(t[1] - t[0]));
+            // [1, 2], where log has no cancellation to guard against
+            const double o = exp_nonpos(-fabs(t[1] - t[0]), ser);
             const bool first = t[0] >= t[1];
             e[0] = first ? 1.0 : o;
             e[1] = first ? o : 1.0;
-            lse = log_1_2(1.0 + o);
+            const double sum = 1.0 + o;
+            lse = log_1_2(sum, ser);
+            inv = rcp_1_4(sum);
         } else {
             double sum = 0.0;
 #pragma unroll
@@ -170,11 +195,8 @@ __global__ __launch_bounds__(kGmmBlock) void k_gmm_pass(const double* __restrict
                 sum += e[j];
             }
             lse = log(sum);
+            inv = 1.0 / sum;
         }
-        double sum = e[0];
-#pragma unroll
-        for (int j = 1; j < K; ++j) sum += e[j];
-        const double inv = 1.0 / sum;
 #pragma unroll
         for (int j = 0; j < K; ++j) {
             const double w = e[j] * inv;          // Eq. (20)
@@ -269,7 +291,7 @@ int gfail(int code, const char* fmt, ...)
 template <int K> hipError_t launch_pass(int nchunks, const double* x, const GmmSet* sets, const GmmChunk* ch,
                                         double* part, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_gmm_pass<K>, dim3(nchunks), dim3(kGmmBlock), 0, s, x, sets, ch, part);
+    hipLaunchKernelGGL(k_gmm_pass<K>, dim3(nchunks), dim3(kGmmBlock), 0, s, x, sets, ch, part, gmm_series());
     return hipGetLastError();
 }
 
