@@ -237,8 +237,19 @@ __global__ __launch_bounds__(kGmmBlock) void k_gmm_update(GmmSet* sets, const do
     const int comp = threadIdx.x % kRecPad, c0 = threadIdx.x / kRecPad;
     constexpr int kStep = kGmmBlock / kRecPad;
     double acc = 0.0;
-    if (comp < nrec)
-        for (int ch = c0; ch < S.nchunk; ch += kStep) acc += part[(size_t)(S.chunk0 + ch) * kRecPad + comp];
+    if (comp < nrec) {
+        // eight loads in flight, added in chunk order (the same sum as one at a time)
+        const double* __restrict__ p = part + (size_t)S.chunk0 * kRecPad + comp;
+        int ch = c0;
+        for (; ch + 7 * kStep < S.nchunk; ch += 8 * kStep) {
+            double v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) v[u] = p[(size_t)(ch + u * kStep) * kRecPad];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) acc += v[u];
+        }
+        for (; ch < S.nchunk; ch += kStep) acc += p[(size_t)ch * kRecPad];
+    }
     red[threadIdx.x] = acc;
     __syncthreads();
     for (int w = kGmmBlock / 2; w >= kRecPad; w >>= 1) {
