@@ -117,6 +117,38 @@ def test_gmm_vanishing_component_keeps_its_parameters(gpu):
         assert mu[0][1] == 1e6 and var[0][1] == 1.0
 
 
+
+def test_gmm_two_components_edge_arguments(gpu):
+    """k = 2 sets that drive the pass's own exponential and logarithm to their ends, at
+    ragged sizes: components 200 standard deviations apart (the smaller term underflows
+    to 0 and each responsibility is 0 or 1), components 40 apart (the exponent's argument
+    crosses the -745 cutoff inside the data), and identical starting components (every
+    sum of the two terms is exactly 2, so the logarithm takes its upper half, and EM
+    keeps the two equal).  Parameters and log-likelihood against the oracle within the
+    batch test's tolerances."""
+    g = gpu
+    sets = [si.mixture_samples(21, 20001, ((0.0, 1.0, 0.5), (200.0, 1.0, 0.5))),
+            si.mixture_samples(22, 4099, ((0.0, 1.0, 0.5), (40.0, 1.0, 0.5))),
+            si.mixture_samples(23, 12345)]
+    starts = [([0.5, 0.5], [0.0, 200.0], [1.0, 1.0]),
+              ([0.5, 0.5], [0.0, 40.0], [1.0, 1.0]),
+              ([0.5, 0.5], [12.0, 12.0], [30.0, 30.0])]
+    a = [np.abs(0.5 * ((x - m[0]) ** 2 - (x - m[1]) ** 2)) for x, (_, m, _) in zip(sets, starts)]
+    assert a[0].min() > 745.0 and a[1].min() < 745.0 < a[1].max() and a[2].max() == 0.0
+    iters = 20
+    print("case k=2 edge sets %s" % [len(x) for x in sets], flush=True)
+    phi, mu, var, ll, it = _fit_gpu(g, sets, starts, iters)
+    for r in range(len(sets)):
+        p0, m0, v0, hist = gmm.fit(sets[r], *starts[r], iters)
+        assert it[r] == iters
+        assert np.allclose(phi[r], p0, rtol=1e-11, atol=1e-14)
+        assert np.allclose(mu[r], m0, rtol=1e-11, atol=1e-14)
+        assert np.allclose(var[r], v0, rtol=1e-10, atol=1e-14)
+        assert abs(ll[r] - hist[-1]) <= 1e-11 * abs(hist[-1]) + 1e-12
+        print("  set %d (%d samples): phi %s mu %s var %s" % (r, len(sets[r]), phi[r], mu[r], var[r]))
+    assert phi[2][0] == phi[2][1] and mu[2][0] == mu[2][1] and var[2][0] == var[2][1]
+
+
 def test_gmm_argument_errors(gpu):
     """Empty sets, k outside 1 .. GLBM_GMM_MAX_COMPONENTS and non-positive starting
     variances or weights are rejected before any work."""
