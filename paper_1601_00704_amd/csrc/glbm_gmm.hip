@@ -14,8 +14,10 @@
 //     Phi = S0 / m,  mu' = mu + S1 / S0,  var' = S2 / S0 - (S1 / S0)^2.
 // Results are deterministic and independent of the batch composition.
 // The kernel reads 8 bytes per sample and iteration and evaluates k
-// exponentials (k - 1 for k = 2, whose larger term is 1) and one logarithm in
-// FP64 per sample: it is bound by those, not by memory.
+// exponentials (k - 1 for k = 2, whose larger term is 1) in FP64 per sample;
+// the log-likelihood takes one logarithm per thread, of the product of its
+// samples' sums (each in [1, k]).  It is bound by vector instruction issue,
+// not by memory.
 #include "glbm.h"
 #include "glbm_internal.h"
 
@@ -75,11 +77,10 @@ constexpr double kLn2Lo = -4.2009150726810846e-11;
 
 // Series coefficients, passed to the pass as a kernel argument so that they sit
 // in scalar registers (a literal coefficient is rebuilt in a vector register at
-// every use): 1/13!, 1/12!, ..., 1/2!, 1, 1 (Taylor series of e^r, highest
-// degree first) and 1/23, 1/21, ..., 1/3 (odd terms of atanh).
+// every use): 1/13!, 1/12!, ..., 1/2!, 1, 1, the Taylor series of e^r, highest
+// degree first.
 struct GmmSeries {
     double exp_c[14];
-    double atanh_c[11];
 };
 
 GmmSeries gmm_series()
@@ -91,7 +92,6 @@ GmmSeries gmm_series()
         c.exp_c[13 - n] = 1.0 / f;
         if (n > 0) f /= n;
     }
-    for (int j = 0; j < 11; ++j) c.atanh_c[j] = 1.0 / (23 - 2 * j);
     return c;
 }
 
@@ -124,25 +124,6 @@ __device__ __forceinline__ double exp_nonpos(double a, const GmmSeries& C)
     return ldexp(p, (int)k);
 }
 
-// log y for y in [1, 2], written from the mathematics: with m = y (or y / 2,
-// adding ln 2, when y > sqrt 2), s = (m - 1) / (m + 1) lies in [-0.172, 0.172]
-// and log m = 2 atanh s = 2 (s + s^3/3 + s^5/5 + ...), summed to s^23
-// (truncation below 1e-19 relative).  m - 1 is exact; 1 / (m + 1) comes from
-// rcp_1_4.
-__device__ __forceinline__ double log_1_2(double y, const GmmSeries& C)
-{
-    const bool big = y > 1.4142135623730951;
-    const double m = big ? 0.5 * y : y;
-    const double s = (m - 1.0) * rcp_1_4(m + 1.0);
-    const double z = s * s;
-    double p = C.atanh_c[0];
-#pragma unroll
-    for (int c = 1; c < 11; ++c) p = fma(p, z, C.atanh_c[c]);
-    const double t = 2.0 * s;
-    const double lm = fma(t, z * p, t);
-    return big ? (lm + kLn2Lo) + kLn2Hi : lm;
-}
-
 template <int K>
 __global__ __launch_bounds__(kGmmBlock) void k_gmm_pass(const double* __restrict__ x, const GmmSet* __restrict__ sets,
                                                           const GmmChunk* __restrict__ chunks, double* __restrict__ part,
@@ -162,6 +143,10 @@ __global__ __launch_bounds__(kGmmBlock) void k_gmm_pass(const double* __restrict
     double acc[3 * K + 1];
 #pragma unroll
     for (int r = 0; r < 3 * K + 1; ++r) acc[r] = 0.0;
+    // log-likelihood: sum of the per-sample maxima, plus one logarithm of the
+    // product of the per-sample sums (at most kGmmPerThread factors in [1, K])
+    static_assert(kGmmPerThread <= 16 && kGmmMaxK <= 8, "the product of the sums must stay below 2^48");
+    double prod = 1.0;
     // the next sample is loaded before the current one is evaluated
     int64_t i = c.start + threadIdx.x;
     double xn = i < c.end ? x[i] : 0.0;
@@ -176,16 +161,15 @@ __global__ __launch_bounds__(kGmmBlock) void k_gmm_pass(const double* __restrict
             t[j] = la[j] + nb[j] * d[j] * d[j];   // log(Phi_j g_j(x)), Eq. (21)
             mx = fmax(mx, t[j]);
         }
-        double e[K], lse, inv;
+        double e[K], inv;
         if constexpr (K == 2) {
-            // the larger term is exp(0) = 1: one exponential, and the sum lies in
-            // [1, 2], where log has no cancellation to guard against
+            // the larger term is exp(0) = 1: one exponential, and the sum lies in [1, 2]
             const double o = exp_nonpos(-fabs(t[1] - t[0]), ser);
             const bool first = t[0] >= t[1];
             e[0] = first ? 1.0 : o;
             e[1] = first ? o : 1.0;
             const double sum = 1.0 + o;
-            lse = log_1_2(sum, ser);
+            prod *= sum;
             inv = rcp_1_4(sum);
         } else {
             double sum = 0.0;
@@ -194,7 +178,7 @@ __global__ __launch_bounds__(kGmmBlock) void k_gmm_pass(const double* __restrict
                 e[j] = exp(t[j] - mx);
                 sum += e[j];
             }
-            lse = log(sum);
+            prod *= sum;
             inv = 1.0 / sum;
         }
 #pragma unroll
@@ -204,8 +188,9 @@ __global__ __launch_bounds__(kGmmBlock) void k_gmm_pass(const double* __restrict
             acc[3 * j + 1] += w * d[j];
             acc[3 * j + 2] += w * d[j] * d[j];
         }
-        acc[3 * K] += mx + lse;
+        acc[3 * K] += mx;
     }
+    acc[3 * K] += log(prod);
     // wavefront trees, then the four wavefronts in a fixed order
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
 #pragma unroll
