@@ -149,6 +149,31 @@ def test_gmm_two_components_edge_arguments(gpu):
     assert phi[2][0] == phi[2][1] and mu[2][0] == mu[2][1] and var[2][0] == var[2][1]
 
 
+
+def test_gmm_bench_size_sampled_sets(gpu):
+    """The benchmark's workload in its launch configuration: 64 sets of 2^20 log pore
+    radii (seeds 9000 + k, two lognormal modes), two components from the same start, all
+    sets fitted in one call.  Sets are independent, so four sampled sets (first, last and
+    two between) are checked against the oracle fitted on that set alone, after three
+    iterations, within the batch test's tolerances."""
+    import torch
+    g = gpu
+    n_sets, m, iters = 64, 1 << 20, 3
+    xs = [np.log(si.pore_radius_samples(9000 + k, m)) for k in range(n_sets)]
+    start = ([0.5, 0.5], [math.log(3e-9), math.log(30e-9)], [0.5, 0.5])
+    print("case bench size: %d sets x %d samples, %d iterations" % (n_sets, m, iters), flush=True)
+    phi, mu, var, ll, it = _fit_gpu(g, xs, [start] * n_sets, iters)
+    torch.cuda.empty_cache()
+    assert np.all(it == iters)
+    for r in (0, 21, 42, 63):
+        p0, m0, v0, hist = gmm.fit(xs[r], *start, iters)
+        assert np.allclose(phi[r], p0, rtol=1e-11, atol=1e-14)
+        assert np.allclose(mu[r], m0, rtol=1e-11, atol=1e-14)
+        assert np.allclose(var[r], v0, rtol=1e-10, atol=1e-14)
+        assert abs(ll[r] - hist[-1]) <= 1e-11 * abs(hist[-1]) + 1e-12
+        print("  set %d: mu %s loglik %.12e vs %.12e" % (r, mu[r], ll[r], hist[-1]))
+
+
 def test_gmm_argument_errors(gpu):
     """Empty sets, k outside 1 .. GLBM_GMM_MAX_COMPONENTS and non-positive starting
     variances or weights are rejected before any work."""
