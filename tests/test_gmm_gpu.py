@@ -119,12 +119,12 @@ def test_gmm_vanishing_component_keeps_its_parameters(gpu):
 
 
 def test_gmm_two_components_edge_arguments(gpu):
-    """k = 2 sets that drive the pass's own exponential and logarithm to their ends, at
-    ragged sizes: components 200 standard deviations apart (the smaller term underflows
-    to 0 and each responsibility is 0 or 1), components 40 apart (the exponent's argument
-    crosses the -745 cutoff inside the data), and identical starting components (every
-    sum of the two terms is exactly 2, so the logarithm takes its upper half, and EM
-    keeps the two equal).  Parameters and log-likelihood against the oracle within the
+    """k = 2 sets that drive the pass's own exponential to its ends, at ragged sizes:
+    components 200 standard deviations apart (the smaller term underflows to 0 and each
+    responsibility is 0 or 1), components 40 apart (the exponent's argument crosses the
+    -745 cutoff inside the data), and identical starting components (the exponential of
+    0 must be exactly 1, every sum of the two terms is 2, and EM keeps the two
+    components equal).  Parameters and log-likelihood against the oracle within the
     batch test's tolerances."""
     g = gpu
     sets = [si.mixture_samples(21, 20001, ((0.0, 1.0, 0.5), (200.0, 1.0, 0.5))),
