@@ -174,6 +174,49 @@ def test_gmm_bench_size_sampled_sets(gpu):
         print("  set %d: mu %s loglik %.12e vs %.12e" % (r, mu[r], ll[r], hist[-1]))
 
 
+
+def test_gmm_concurrent_calls(gpu):
+    """Two threads fit different batches at the same time on two streams, after calls of
+    other sizes in the same process: every result equals the same fit run alone, bitwise."""
+    import threading
+    import torch
+    g = gpu
+    st = ([0.5, 0.5], [8.0, 25.0], [4.0, 25.0])
+    a = [si.mixture_samples(41 + i, 30000 + 777 * i) for i in range(3)]
+    b = [si.mixture_samples(51 + i, 90001 + 123 * i) for i in range(5)]
+    ref = {"a": _fit_gpu(g, a, [st] * len(a), 30), "b": _fit_gpu(g, b, [st] * len(b), 30)}
+    again = _fit_gpu(g, a, [st] * len(a), 30)   # a smaller batch after a larger one
+    for x, y in zip(again, ref["a"]):
+        assert np.array_equal(x, y)
+    data = {}
+    for name, sets in (("a", a), ("b", b)):
+        offs = np.concatenate([[0], np.cumsum([len(x) for x in sets])]).astype(np.int64)
+        data[name] = (offs, torch.from_numpy(np.concatenate(sets)).cuda(), len(sets))
+    streams = {"a": torch.cuda.Stream(), "b": torch.cuda.Stream()}
+    torch.cuda.synchronize()
+    out, err = {}, {}
+
+    def run(name):
+        try:
+            offs, xd, n = data[name]
+            starts = [np.tile(np.array(v, np.float64), (n, 1)) for v in st]
+            out[name] = g.glbm_gmm_fit(offs, xd.data_ptr(), *starts, 30, 0.0, stream=streams[name].cuda_stream)
+        except Exception as e:  # reported below
+            err[name] = e
+
+    print("case concurrent fits on two streams", flush=True)
+    threads = [threading.Thread(target=run, args=(n,)) for n in ("a", "b")]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join(timeout=90)
+    assert not any(t.is_alive() for t in threads)
+    assert not err, err
+    for name in ("a", "b"):
+        for x, y in zip(out[name], ref[name]):
+            assert np.array_equal(x, y), name
+
+
 def test_gmm_argument_errors(gpu):
     """Empty sets, k outside 1 .. GLBM_GMM_MAX_COMPONENTS and non-positive starting
     variances or weights are rejected before any work."""
