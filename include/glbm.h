@@ -410,6 +410,8 @@ int glbm_class_table_pressure(const glbm_gas_params* p, int32_t n_iom, const dou
  * component whose responsibilities all vanish gets Phi = 0 (Eq. 22) and keeps
  * its mean and variance (Eq. 23-24 are then 0/0).  Work is
  * queued on hip_stream (NULL: null stream) and the call synchronises it.
+ * Each call allocates its own device buffers and frees them before it returns,
+ * so calls from several threads on different streams are independent.
  * Errors: GLBM_EINVAL (bad sizes or starting point), GLBM_ENOMEM, GLBM_EDEVICE.
  */
 int glbm_gmm_fit(int32_t n_sets, const int64_t* offsets, const double* x_dev, int32_t k, double* phi, double* mu,
