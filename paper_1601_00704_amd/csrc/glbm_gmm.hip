@@ -154,39 +154,42 @@ __global__ __launch_bounds__(kGmmBlock) void k_gmm_pass(const double* __restrict
         const double xi = xn;
         if (i + kGmmBlock < c.end) xn = x[i + kGmmBlock];
         double t[K], d[K];
-        double mx = -INFINITY;
 #pragma unroll
         for (int j = 0; j < K; ++j) {
             d[j] = xi - mu[j];
             t[j] = la[j] + nb[j] * d[j] * d[j];   // log(Phi_j g_j(x)), Eq. (21)
-            mx = fmax(mx, t[j]);
         }
-        double e[K], inv;
+        double w[K], mx;                          // responsibilities of Eq. (20), larger term
         if constexpr (K == 2) {
             // the larger term is exp(0) = 1: one exponential, and the sum lies in [1, 2]
-            const double o = exp_nonpos(-fabs(t[1] - t[0]), ser);
             const bool first = t[0] >= t[1];
-            e[0] = first ? 1.0 : o;
-            e[1] = first ? o : 1.0;
+            mx = first ? t[0] : t[1];
+            const double o = exp_nonpos(-fabs(t[1] - t[0]), ser);
             const double sum = 1.0 + o;
             prod *= sum;
-            inv = rcp_1_4(sum);
+            const double inv = rcp_1_4(sum), wo = o * inv;
+            w[0] = first ? inv : wo;
+            w[1] = first ? wo : inv;
         } else {
-            double sum = 0.0;
+            mx = -INFINITY;
+#pragma unroll
+            for (int j = 0; j < K; ++j) mx = fmax(mx, t[j]);
+            double e[K], sum = 0.0;
 #pragma unroll
             for (int j = 0; j < K; ++j) {
                 e[j] = exp(t[j] - mx);
                 sum += e[j];
             }
             prod *= sum;
-            inv = 1.0 / sum;
+            const double inv = 1.0 / sum;
+#pragma unroll
+            for (int j = 0; j < K; ++j) w[j] = e[j] * inv;
         }
 #pragma unroll
         for (int j = 0; j < K; ++j) {
-            const double w = e[j] * inv;          // Eq. (20)
-            acc[3 * j] += w;
-            acc[3 * j + 1] += w * d[j];
-            acc[3 * j + 2] += w * d[j] * d[j];
+            acc[3 * j] += w[j];
+            acc[3 * j + 1] += w[j] * d[j];
+            acc[3 * j + 2] += w[j] * d[j] * d[j];
         }
         acc[3 * K] += mx;
     }
